@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the FFT-LB time step on one MI355X.
+
+Workload: spinodal quench on a 1024 x 1024 periodic grid (rho = rho_c (1 + 0.005 xi),
+T = 0.8 T_c, a = 2, b = 0.4, the paper's dx, dt, tau, K, q and the k4 window).  A step is
+one full FFT-LB update of all 33 populations (convection and force derivatives by
+windowed FFT, collision, force, moments).  Inputs are resident in HBM when timing starts.
+
+Prints one JSON line.  value = site-velocity updates per second = 33 nx ny steps / s.
+roofline: the dominant kernel's algorithmic bytes per launch over its mean launch time,
+timed with HIP events on the stream it runs on, against 8 TB/s.
+cpu_baseline: the FP64 oracle timed on this host on one step of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "site·velocity updates/s per FFT-LB step; % HBM roofline; time-to-equilibrium"
+
+# Algorithmic bytes per site of each kernel of the step (FP32 values; a packed half
+# spectrum of a real plane is nx*ny/2 complex = one float per site):
+#   0 convection columns: read 32 spectra, write 32                    ->  64 floats
+#   1 stage-1 columns:    read 4 spectra, write 11                     ->  15
+#   2 stage-2 rows:       read 11 spectra + 4 fields, write 5 spectra + C ->  21
+#   3 stage-2 columns:    read 5 spectra, write 3                      ->   8
+#   4 collide rows:       read f (33) + 32 conv spectra + 3 + C + 4 fields,
+#                         write f (33) + 32 spectra + 4 spectra + 4 fields -> 146
+STAGES = ("conv_columns", "stage1_columns", "stage2_rows", "stage2_columns", "collide_rows")
+STAGE_KERNELS = ("k_col_conv", "k_col_multi", "k_rows_stage2", "k_col_multi", "k_rows_collide")
+STAGE_FLOATS_PER_SITE = (64, 15, 21, 8, 146)
+DOMINANT = 4
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_spinodal1024.json")
+KERNEL_SOURCES = ("paper_1011_3582_amd/csrc/kernels.hpp", "paper_1011_3582_amd/csrc/fft_lds.hpp",
+                  "paper_1011_3582_amd/csrc/model.hpp", "paper_1011_3582_amd/csrc/fftlb.hip")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(nx, ny):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3 counter runs,
+    scaled by the copy-kernel calibration; None if absent or taken on other kernel code."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("nx") != nx or rec.get("ny") != ny:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(fields, params, nx, ny):
+    """FP64 oracle, as it stands, on one step of the same workload (single-threaded)."""
+    import numpy as np
+    from oracle import fftlb_oracle as O
+    op = O.Params(dx=params.dx, dy=params.dy, dt=params.dt, tau=params.tau, K=params.K, H=params.H,
+                  zeta=params.zeta, q=params.q, a=params.a, b=params.b, m=params.m)
+    f0 = O.feq(*fields.as_f64())
+    t0 = time.perf_counter()
+    O.step(f0, op)
+    dt = time.perf_counter() - t0
+    return {"value": 33.0 * nx * ny / dt, "unit": "site·velocity updates/s", "cores": 1,
+            "kind": "oracle", "sample": f"1 step of the {nx}x{ny} workload, FP64 NumPy/SciPy, "
+                                        f"{dt:.1f} s on the host CPU"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (traffic calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1011_3582_amd import fftlb as F
+    from paper_1011_3582_amd import workloads as W
+
+    nx = ny = 1024
+    fields = W.spinodal_1024()
+    params = F.Params()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = F.Solver(*(torch.from_numpy(a) for a in (fields.rho, fields.ux, fields.uy, fields.T)), params, device=dev)
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    s.step(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_s = ev0.elapsed_time(ev1) / 1e3
+    _, glob = s.moments()
+    assert glob["nonfinite"] == 0.0, "state became non-finite"
+
+    # per-kernel mean launch time, HIP events on the stream the kernels run on
+    state = s.get_state()
+    kern_ms = []
+    for k in range(len(STAGES)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.run_stage(k, 2)
+        a.record()
+        s.run_stage(k, args.kernel_reps)
+        b.record()
+        torch.cuda.synchronize()
+        kern_ms.append(a.elapsed_time(b) / args.kernel_reps)
+        s.set_state(state)
+    s.close()
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    sites = nx * ny
+    step_s = wall / args.steps
+    value = 33.0 * sites * args.steps / wall
+    t_dom = kern_ms[DOMINANT] / 1e3
+    bytes_dom = STAGE_FLOATS_PER_SITE[DOMINANT] * 4 * sites
+    achieved = bytes_dom / t_dom / 1e9
+    traffic = measured_traffic(nx, ny)
+    step_bytes = sum(STAGE_FLOATS_PER_SITE) * 4 * sites
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site·velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "spinodal quench 1024x1024 (rho_c(1+0.005 xi), T=0.8 Tc, a=2, b=0.4, "
+                               "dx=1/256, dt=1e-5, tau=1e-2, K=1e-5, q=-0.004, k4 window)",
+                   "nx": nx, "ny": ny, "precision": "FP32 step, FP64 global reductions"},
+        "roofline": {"bound": "hbm", "kernel": STAGE_KERNELS[DOMINANT], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "bytes_per_launch": bytes_dom, "launch_ms": kern_ms[DOMINANT]},
+        "step_roofline": {"bytes_per_step": step_bytes, "achieved_GBs": step_bytes / step_s / 1e9,
+                          "frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS,
+                          "kernel_ms": dict(zip(STAGES, kern_ms)),
+                          "event_ms_per_step": ev_s / args.steps * 1e3},
+        "globals": {k: glob[k] for k in ("mass", "energy", "residual", "umax")},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline (1 step)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(fields, params, nx, ny)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,671 @@
+// HIP kernels of one FFT-LB time step (gfx950).
+//
+// Spectral data layout ("row spectra").  A real plane g[ny][nx] is stored after its
+// row transform as nx/2 complex columns per row: column 0 holds (Re G(0), Re G(nx/2))
+// (the DC and Nyquist terms of a real row are real), columns 1..nx/2-1 hold G(kx).
+// Columns are grouped in tiles of TW consecutive kx; a tile is stored as [y][TW], so a
+// row kernel reads or writes TW * 8 bytes contiguous per tile and a column kernel
+// reads a contiguous [ny][TW] block.  Element (y, kx) of a plane is at
+//     (kx / TW) * ny * TW + y * TW + (kx % TW).
+//
+// Per time step (all derivatives by windowed FFT, Sec. 3.6):
+//   k_col_conv      column FFT of the 32 moving populations' row spectra, multiply by
+//                   i (v_x k_m(kx) + v_y k_m(ky)) / (nx ny), inverse column FFT (in place);
+//   k_col_multi     column pass of the macroscopic fields: 4 spectra -> 11 derivative
+//                   spectra (stage 1), and later 5 -> 3 divergence spectra (stage 2);
+//   k_rows_stage2   inverse row FFTs of the 11 derivatives, the pointwise closure of
+//                   Eqs. (18)-(23), forward row FFTs of the 5 fields whose divergences the
+//                   force needs, FP64 partial sums for the global diagnostics;
+//   k_rows_collide  inverse row FFTs of the convection terms and of the force
+//                   divergences, equilibrium, force, explicit update, moments of f^{n+1},
+//                   forward row FFTs of f^{n+1} and of its moments (inputs of the next step).
+// Two real rows are transformed as one complex row (z = a + i b) and separated by
+// Hermitian symmetry.
+#pragma once
+#include "fft_lds.hpp"
+#include "model.hpp"
+
+namespace fftlb {
+
+constexpr int kRowsPerThreadSites = 4;  // each row-kernel thread owns 4 sites of its row
+
+// Row-kernel geometry: NX/4 threads per row, enough rows per block for >= 64 threads.
+template <int NX>
+struct RowGeom {
+  static constexpr int TPR = NX / 4;
+  static constexpr int RB = (TPR >= 64) ? 1 : 64 / TPR;
+  static constexpr int NT = RB * TPR;
+  static constexpr int LDS = RB * NX;  // float2 elements of the row buffer
+};
+
+struct SpecGeom {
+  int ny;       // column length
+  int tw;       // tile width (power of two)
+  int log2tw;
+  __device__ __forceinline__ int idx(int y, int k) const {
+    return ((k >> log2tw) * ny + y) * tw + (k & (tw - 1));
+  }
+};
+
+// Pointers into the workspace (and the caller's buffers for the init/set modes).
+struct Planes {
+  float* f;          // [33][ny][nx]
+  float2* sf;        // [32] row spectra of f_1..f_32 (in place: convection spectra after k_col_conv)
+  float2* sm;        // [4]  row spectra of rho, ux, uy, T
+  float2* s1;        // [11] stage-1 derivative spectra
+  float2* s2i;       // [5]  stage-2 input spectra
+  float2* s2o;       // [3]  stage-2 output spectra: B^x, B^y, G
+  float* macro;      // [4][ny][nx] rho, ux, uy, T (real)
+  float* cpl;        // [ny][nx] coefficient C of Eq. (22)
+  const float2* twx; // row twiddles, nx entries
+  double* part_d;    // [blocks][6] stage-2 partials: mass, px, py, energy, max|u|, nonfinite
+  float* part_f;     // [blocks][2] collide partials: max |sum_q C_q|, nonfinite
+  const float* in0;  // init: rho0, ux0, uy0, T0 / set: f
+  const float* in1;
+  const float* in2;
+  const float* in3;
+  int nx, ny;
+  long plane;        // nx * ny
+  SpecGeom sg;
+};
+
+// ---------------------------------------------------------------------------
+// Block helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool nonfinite(float x) { return !(fabsf(x) <= 3.402823466e38f); }
+
+// Row groups: thread -> (row within block, lane within row).
+template <int NX>
+struct RowThread {
+  int rl, lt, y;
+  __device__ __forceinline__ RowThread(int tid, int blk) {
+    rl = tid / RowGeom<NX>::TPR;
+    lt = tid % RowGeom<NX>::TPR;
+    y = blk * RowGeom<NX>::RB + rl;
+  }
+  __device__ __forceinline__ int x(int j) const { return lt + j * RowGeom<NX>::TPR; }
+};
+
+// LDS <- Z(k) = A(k) + i B(k) for k = 0..NX-1, from the packed half spectra of planes A
+// and B (B may be null) at the block's rows; Hermitian completion of the upper half.
+template <int NX>
+__device__ __forceinline__ void rows_load_pair(float2* lds, const float2* __restrict__ SA,
+                                               const float2* __restrict__ SB, const SpecGeom& sg,
+                                               int row0, int tid) {
+  constexpr int H = NX / 2;
+  constexpr int NT = RowGeom<NX>::NT;
+  for (int e = tid; e < RowGeom<NX>::RB * H; e += NT) {
+    const int rl = e / H, k = e % H;
+    const int gi = sg.idx(row0 + rl, k);
+    const float2 a = SA[gi];
+    const float2 b = SB ? SB[gi] : make_float2(0.0f, 0.0f);
+    float2* z = lds + rl * NX;
+    if (k == 0) {
+      z[0] = make_float2(a.x, b.x);
+      z[H] = make_float2(a.y, b.y);
+    } else {
+      z[k] = make_float2(a.x - b.y, a.y + b.x);
+      z[NX - k] = make_float2(a.x + b.y, b.x - a.y);
+    }
+  }
+}
+
+// Packed half spectra of A = Re z and B = Im z from the forward transform Z in LDS.
+template <int NX>
+__device__ __forceinline__ void rows_store_pair(const float2* lds, float2* __restrict__ SA,
+                                                float2* __restrict__ SB, const SpecGeom& sg, int row0,
+                                                int tid) {
+  constexpr int H = NX / 2;
+  constexpr int NT = RowGeom<NX>::NT;
+  for (int e = tid; e < RowGeom<NX>::RB * H; e += NT) {
+    const int rl = e / H, k = e % H;
+    const float2* z = lds + rl * NX;
+    const float2 Z = z[k];
+    float2 A, B;
+    if (k == 0) {
+      const float2 W = z[H];
+      A = make_float2(Z.x, W.x);
+      B = make_float2(Z.y, W.y);
+    } else {
+      const float2 W = z[NX - k];
+      A = make_float2(0.5f * (Z.x + W.x), 0.5f * (Z.y - W.y));
+      B = make_float2(0.5f * (Z.y + W.y), 0.5f * (W.x - Z.x));
+    }
+    const int gi = sg.idx(row0 + rl, k);
+    SA[gi] = A;
+    if (SB) SB[gi] = B;
+  }
+}
+
+// Inverse row transform of a pair of spectra; afterwards lds[x] = a(x) + i b(x).
+template <int NX>
+__device__ __forceinline__ void rows_inverse_pair(float2* lds, const float2* SA, const float2* SB,
+                                                  const SpecGeom& sg, const float2* twx, int row0, int tid) {
+  rows_load_pair<NX>(lds, SA, SB, sg, row0, tid);
+  __syncthreads();
+  fft_lds<NX, +1, RowGeom<NX>::NT, RowGeom<NX>::RB, false>(lds, NX, 1, twx, tid);
+}
+
+// Forward row transform of lds[x] = a(x) + i b(x) (already written, unsynchronised) and
+// store of both packed half spectra.  Ends with a barrier so lds can be reused.
+template <int NX>
+__device__ __forceinline__ void rows_forward_pair(float2* lds, float2* SA, float2* SB, const SpecGeom& sg,
+                                                  const float2* twx, int row0, int tid) {
+  __syncthreads();
+  fft_lds<NX, -1, RowGeom<NX>::NT, RowGeom<NX>::RB, false>(lds, NX, 1, twx, tid);
+  rows_store_pair<NX>(lds, SA, SB, sg, row0, tid);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Column kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  // Consecutive logical blocks land on the same XCD (blocks are dealt round-robin to 8 XCDs),
+  // so column tiles that share cache lines share an L2.
+  if (nblocks % 8) return b;
+  return (b % 8) * (nblocks / 8) + b / 8;
+}
+
+// Convection: for each of the 32 moving populations, column FFT, multiply by
+// i (v_x k_m(kx) + v_y k_m(ky)) * scale, inverse column FFT, in place.
+template <int NY, int CW, int NT>
+__global__ __launch_bounds__(NT) void k_col_conv(float2* __restrict__ spec, const float2* __restrict__ twy,
+                                                 const float* __restrict__ kapx,
+                                                 const float* __restrict__ kapy, int nx, int tw, float scale) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int nsub = (nx / 2) / CW;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = b / nsub, sub = b % nsub;
+  const int c0 = sub * CW;
+  float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
+  for (int e = tid; e < NY * CW; e += NT) {
+    const int y = e / CW, c = e % CW;
+    lds[e] = g[y * tw + c];
+  }
+  __syncthreads();
+  fft_lds<NY, -1, NT, CW, true>(lds, 1, CW, twy, tid);
+  const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
+  for (int e = tid; e < NY * CW; e += NT) {
+    const int y = e / CW, c = e % CW;
+    const float m = (vx * kapx[c0 + c] + vy * kapy[y]) * scale;
+    const float2 v = lds[e];
+    lds[e] = make_float2(-m * v.y, m * v.x);
+  }
+  __syncthreads();
+  fft_lds<NY, +1, NT, CW, true>(lds, 1, CW, twy, tid);
+  for (int e = tid; e < NY * CW; e += NT) {
+    const int y = e / CW, c = e % CW;
+    g[y * tw + c] = lds[e];
+  }
+}
+
+// Multiplier kinds of the multi-output column pass.
+enum : int {
+  MK_NONE = 0,
+  MK_IKX = 1,   // i k_x
+  MK_IKY = 2,   // i k_y
+  MK_KXX = 3,   // -k_x^2
+  MK_KYY = 4,   // -k_y^2
+  MK_KXY = 5,   // -k_x k_y
+  MK_LAP = 6,   // -(k_x^2 + k_y^2)
+};
+
+struct ColGroup {
+  const float2* in[3];
+  float2* out[6];
+  int nin, nout;
+  int kind[6][3];
+};
+
+struct ColLaunch {
+  ColGroup g[3];
+};
+
+// Column pass of derivative groups: forward column FFT of nin input spectra, then for
+// each output a linear combination sum_p m_op(kx, ky) X_p, inverse column FFT, store.
+template <int NY, int CW, int NT>
+__global__ __launch_bounds__(NT) void k_col_multi(ColLaunch L, const float2* __restrict__ twy,
+                                                  const float* __restrict__ kapx,
+                                                  const float* __restrict__ kapy, int nx, int tw, float scale) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const ColGroup& G = L.g[blockIdx.y];
+  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
+  const long off = (long)(c0 / tw) * NY * tw + (c0 % tw);
+  const int W = G.nin * CW;  // LDS row width of the input block
+  for (int p = 0; p < G.nin; ++p) {
+    const float2* g = G.in[p] + off;
+    for (int e = tid; e < NY * CW; e += NT) {
+      const int y = e / CW, c = e % CW;
+      lds[y * W + p * CW + c] = g[y * tw + c];
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true>(lds + p * CW, 1, W, twy, tid);
+  float2* work = lds + NY * W;
+  for (int o = 0; o < G.nout; ++o) {
+    for (int e = tid; e < NY * CW; e += NT) {
+      const int y = e / CW, c = e % CW;
+      const float kx = kapx[c0 + c], ky = kapy[y];
+      float re = 0.0f, im = 0.0f;
+      for (int p = 0; p < G.nin; ++p) {
+        const int kd = G.kind[o][p];
+        if (kd == MK_NONE) continue;
+        const float2 v = lds[y * W + p * CW + c];
+        if (kd == MK_IKX || kd == MK_IKY) {
+          const float k = kd == MK_IKX ? kx : ky;
+          re -= k * v.y;
+          im += k * v.x;
+        } else {
+          const float m = kd == MK_KXX ? -kx * kx
+                        : kd == MK_KYY ? -ky * ky
+                        : kd == MK_KXY ? -kx * ky
+                                       : -(kx * kx + ky * ky);
+          re += m * v.x;
+          im += m * v.y;
+        }
+      }
+      work[e] = make_float2(re * scale, im * scale);
+    }
+    __syncthreads();
+    fft_lds<NY, +1, NT, CW, true>(work, 1, CW, twy, tid);
+    float2* g = G.out[o] + off;
+    for (int e = tid; e < NY * CW; e += NT) {
+      const int y = e / CW, c = e % CW;
+      g[y * tw + c] = work[e];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row kernels
+// ---------------------------------------------------------------------------
+
+// Stage 2: derivatives at the sites, closure of Eqs. (18)-(23), forward row transforms of
+// P1 = S + Lxx, P2 = Lxy, P3 = S + Lyy, gx, gy; C to its plane; diagnostics partials.
+template <int NX>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model M) {
+  extern __shared__ float2 lds[];
+  using G = RowGeom<NX>;
+  const int tid = threadIdx.x;
+  const RowThread<NX> rt(tid, blockIdx.x);
+  const int row0 = blockIdx.x * G::RB;
+  float2* z = lds + rt.rl * NX;
+  constexpr int J = kRowsPerThreadSites;
+  const long rowoff = (long)rt.y * P.nx;
+
+  float rho[J], ux[J], uy[J], T[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const long s = rowoff + rt.x(j);
+    rho[j] = P.macro[s];
+    ux[j] = P.macro[P.plane + s];
+    uy[j] = P.macro[2 * P.plane + s];
+    T[j] = P.macro[3 * P.plane + s];
+  }
+  // the 11 stage-1 derivatives: rx, ry, lap, dxux, dyux, dxuy, dyuy, thx, thy, Tx, Ty
+  float d[11][J];
+#pragma unroll
+  for (int pr = 0; pr < 6; ++pr) {
+    const int a = 2 * pr, bb = 2 * pr + 1;
+    rows_inverse_pair<NX>(lds, P.s1 + (long)a * P.plane / 2, bb < 11 ? P.s1 + (long)bb * P.plane / 2 : nullptr,
+                          P.sg, P.twx, row0, tid);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const float2 v = z[rt.x(j)];
+      d[a][j] = v.x;
+      if (bb < 11) d[bb][j] = v.y;
+    }
+    __syncthreads();
+  }
+
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  float umax = 0.0f;
+  int bad = 0;
+  float P1[J], P2[J], P3[J], gx[J], gy[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const float r = rho[j], t = T[j];
+    const float rx = d[0][j], ry = d[1][j], lap = d[2][j];
+    const float dxux = d[3][j], dyux = d[4][j], dxuy = d[5][j], dyuy = d[6][j];
+    const float thx = d[7][j], thy = d[8][j], Tx = d[9][j], Ty = d[10][j];
+    const float theta = dxux + dyuy;
+    const float Mg = M.K + M.H * t;
+    const float rT = r * t;
+    const float Pw = rT / (1.0f - M.b * r) - M.a * r * r;
+    const float S = Pw - rT - M.zeta * theta;
+    const float grad2 = rx * rx + ry * ry;
+    const float iso = r * M.K * (rx * Tx + ry * Ty) / t - Mg * (r * lap + 0.5f * grad2);
+    const float Lxx = Mg * rx * rx + iso;
+    const float Lyy = Mg * ry * ry + iso;
+    const float Lxy = Mg * rx * ry;
+    P1[j] = S + Lxx;
+    P2[j] = Lxy;
+    P3[j] = S + Lyy;
+    gx[j] = 2.0f * M.q * rT * Tx;
+    gy[j] = 2.0f * M.q * rT * Ty;
+    const float lam_du = Lxx * dxux + Lxy * dxuy + Lxy * dyux + Lyy * dyuy;
+    const float cubic = rx * (dxux * rx + dxuy * ry) + ry * (dyux * rx + dyuy * ry);
+    const float num = (Pw - rT) * theta + lam_du - M.zeta * theta * theta + M.a * r * r * theta +
+                      M.K * (-0.5f * grad2 * theta - r * (rx * thx + ry * thy) - cubic);
+    const float C = num / (2.0f * rT * t);
+    P.cpl[rowoff + rt.x(j)] = C;
+    const float u2 = ux[j] * ux[j] + uy[j] * uy[j];
+    const double e = (double)rT - (double)M.a * r * r + 0.5 * (double)M.K * grad2 + 0.5 * (double)r * u2;
+    acc[0] += r;
+    acc[1] += (double)r * ux[j];
+    acc[2] += (double)r * uy[j];
+    acc[3] += e;
+    umax = fmaxf(umax, sqrtf(u2));
+    bad |= nonfinite(r) | nonfinite(t) | nonfinite(u2) | nonfinite(C);
+  }
+  // forward row transforms of the five fields whose divergences the force needs
+  const long hp = P.plane / 2;
+#pragma unroll
+  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(P1[j], P2[j]);
+  rows_forward_pair<NX>(lds, P.s2i, P.s2i + hp, P.sg, P.twx, row0, tid);
+#pragma unroll
+  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(P3[j], gx[j]);
+  rows_forward_pair<NX>(lds, P.s2i + 2 * hp, P.s2i + 3 * hp, P.sg, P.twx, row0, tid);
+#pragma unroll
+  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(gy[j], 0.0f);
+  rows_forward_pair<NX>(lds, P.s2i + 4 * hp, nullptr, P.sg, P.twx, row0, tid);
+
+  // block reduction of the diagnostics (fixed order: deterministic)
+  __shared__ double red_d[16][4];
+  __shared__ float red_f[16][2];
+  const int wave = tid / 64, lane = tid % 64;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = wave_sum(acc[i]);
+  umax = wave_max(umax);
+  const float badf = wave_max(bad ? 1.0f : 0.0f);
+  if (lane == 0) {
+    for (int i = 0; i < 4; ++i) red_d[wave][i] = acc[i];
+    red_f[wave][0] = umax;
+    red_f[wave][1] = badf;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    constexpr int NW = (G::NT + 63) / 64;
+    double s[4] = {0, 0, 0, 0};
+    float um = 0.0f, bd = 0.0f;
+    for (int w = 0; w < NW; ++w) {
+      for (int i = 0; i < 4; ++i) s[i] += red_d[w][i];
+      um = fmaxf(um, red_f[w][0]);
+      bd = fmaxf(bd, red_f[w][1]);
+    }
+    double* o = P.part_d + 6 * (long)blockIdx.x;
+    for (int i = 0; i < 4; ++i) o[i] = s[i];
+    o[4] = um;
+    o[5] = bd;
+  }
+}
+
+enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
+
+// Collision, force and update (MODE_STEP), or f := f^eq(inputs) (MODE_INIT), or f := input
+// (MODE_SET); then moments of the new f and forward row transforms of f_1..f_32 and of
+// rho, ux, uy, T for the next step.
+template <int NX, int MODE>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Model M) {
+  extern __shared__ float2 lds[];
+  using G = RowGeom<NX>;
+  constexpr int J = kRowsPerThreadSites;
+  const int tid = threadIdx.x;
+  const RowThread<NX> rt(tid, blockIdx.x);
+  const int row0 = blockIdx.x * G::RB;
+  float2* z = lds + rt.rl * NX;
+  const long rowoff = (long)rt.y * P.nx;
+  const long hp = P.plane / 2;
+
+  Site st[J];
+  if constexpr (MODE == MODE_STEP) {
+    float Bx[J], By[J], Gd[J];
+    rows_inverse_pair<NX>(lds, P.s2o, P.s2o + hp, P.sg, P.twx, row0, tid);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const float2 v = z[rt.x(j)];
+      Bx[j] = v.x;
+      By[j] = v.y;
+    }
+    __syncthreads();
+    rows_inverse_pair<NX>(lds, P.s2o + 2 * hp, nullptr, P.sg, P.twx, row0, tid);
+#pragma unroll
+    for (int j = 0; j < J; ++j) Gd[j] = z[rt.x(j)].x;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const long s = rowoff + rt.x(j);
+      const float r = P.macro[s], ux = P.macro[P.plane + s], uy = P.macro[2 * P.plane + s];
+      const float t = P.macro[3 * P.plane + s];
+      site_equilibrium(st[j], r, ux, uy, t);
+      const float rT = r * t;
+      const float cc = P.cpl[s] + Gd[j] / (2.0f * rT * t);   // C + C_q
+      site_force(st[j], t, Bx[j] / rT, By[j] / rT, cc);
+    }
+  } else if constexpr (MODE == MODE_INIT) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const long s = rowoff + rt.x(j);
+      site_equilibrium(st[j], P.in0[s], P.in1[s], P.in2[s], P.in3[s]);
+    }
+  }
+
+  float m0[J], mx[J], my[J], me[J], rs[J];
+  int bad = 0;
+  // rest particle
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const long s = rowoff + rt.x(j);
+    float fn;
+    if constexpr (MODE == MODE_STEP) {
+      fn = relax_update(st[j], M, P.f[s], feq_rest(st[j]), 0.0f, 0.0f, 0.0f, 0.0f);
+    } else if constexpr (MODE == MODE_INIT) {
+      fn = feq_rest(st[j]);
+    } else {
+      fn = P.in0[s];
+    }
+    P.f[s] = fn;
+    m0[j] = fn;
+    mx[j] = my[j] = me[j] = rs[j] = 0.0f;
+    bad |= nonfinite(fn);
+  }
+  // moving populations, two at a time (one complex row transform per pair)
+#pragma unroll 1
+  for (int pr = 0; pr < 16; ++pr) {
+    const int qa = 1 + 2 * pr, qb = qa + 1;
+    const int k = pr >> 2;  // speed group of both
+    float2* Sa = P.sf + (long)(qa - 1) * hp;
+    float2* Sb = P.sf + (long)(qb - 1) * hp;
+    float ca[J], cb[J];
+    if constexpr (MODE == MODE_STEP) {
+      rows_inverse_pair<NX>(lds, Sa, Sb, P.sg, P.twx, row0, tid);
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const float2 v = z[rt.x(j)];
+        ca[j] = v.x;
+        cb[j] = v.y;
+      }
+      __syncthreads();
+    }
+    const float vxa = c_vel.vx[qa], vya = c_vel.vy[qa], v2 = c_vel.v2[qa];
+    const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const long s = rowoff + rt.x(j);
+      float fa, fb;
+      if constexpr (MODE == MODE_SET) {
+        fa = P.in0[(long)qa * P.plane + s];
+        fb = P.in0[(long)qb * P.plane + s];
+      } else {
+        const float Fk = group_weight(st[j], k);
+        const float ea = feq_moving(st[j], Fk, vxa, vya);
+        const float eb = feq_moving(st[j], Fk, vxb, vyb);
+        if constexpr (MODE == MODE_STEP) {
+          fa = relax_update(st[j], M, P.f[(long)qa * P.plane + s], ea, ca[j], vxa, vya, v2);
+          fb = relax_update(st[j], M, P.f[(long)qb * P.plane + s], eb, cb[j], vxb, vyb, v2);
+          rs[j] += ca[j] + cb[j];
+        } else {
+          fa = ea;
+          fb = eb;
+        }
+      }
+      P.f[(long)qa * P.plane + s] = fa;
+      P.f[(long)qb * P.plane + s] = fb;
+      m0[j] += fa + fb;
+      mx[j] += vxa * fa + vxb * fb;
+      my[j] += vya * fa + vyb * fb;
+      me[j] += v2 * (fa + fb);
+      bad |= nonfinite(fa) | nonfinite(fb);
+      z[rt.x(j)] = make_float2(fa, fb);
+    }
+    rows_forward_pair<NX>(lds, Sa, Sb, P.sg, P.twx, row0, tid);
+  }
+  // moments of the new state and their row spectra
+  float r[J], ux[J], uy[J], T[J];
+  float rmax = 0.0f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const long s = rowoff + rt.x(j);
+    r[j] = m0[j];
+    const float ir = 1.0f / r[j];
+    ux[j] = mx[j] * ir;
+    uy[j] = my[j] * ir;
+    T[j] = 0.5f * me[j] * ir - 0.5f * (ux[j] * ux[j] + uy[j] * uy[j]);
+    P.macro[s] = r[j];
+    P.macro[P.plane + s] = ux[j];
+    P.macro[2 * P.plane + s] = uy[j];
+    P.macro[3 * P.plane + s] = T[j];
+    rmax = fmaxf(rmax, fabsf(rs[j]));
+    z[rt.x(j)] = make_float2(r[j], ux[j]);
+  }
+  rows_forward_pair<NX>(lds, P.sm, P.sm + hp, P.sg, P.twx, row0, tid);
+#pragma unroll
+  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(uy[j], T[j]);
+  rows_forward_pair<NX>(lds, P.sm + 2 * hp, P.sm + 3 * hp, P.sg, P.twx, row0, tid);
+
+  if constexpr (MODE == MODE_STEP) {
+    __shared__ float red[16][2];
+    const int wave = tid / 64, lane = tid % 64;
+    rmax = wave_max(rmax);
+    const float badf = wave_max(bad ? 1.0f : 0.0f);
+    if (lane == 0) {
+      red[wave][0] = rmax;
+      red[wave][1] = badf;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      constexpr int NW = (G::NT + 63) / 64;
+      float a = 0.0f, bd = 0.0f;
+      for (int w = 0; w < NW; ++w) {
+        a = fmaxf(a, red[w][0]);
+        bd = fmaxf(bd, red[w][1]);
+      }
+      P.part_f[2 * blockIdx.x] = a;
+      P.part_f[2 * blockIdx.x + 1] = bd;
+    }
+  }
+}
+
+// Real plane(s) -> packed row spectra (b may be null).
+template <int NX>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_real(const float* __restrict__ a,
+                                                                       const float* __restrict__ b,
+                                                                       float2* sa, float2* sb, SpecGeom sg,
+                                                                       const float2* __restrict__ twx, int nx) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const RowThread<NX> rt(tid, blockIdx.x);
+  float2* z = lds + rt.rl * NX;
+  const long rowoff = (long)rt.y * nx;
+#pragma unroll
+  for (int j = 0; j < kRowsPerThreadSites; ++j) {
+    const long s = rowoff + rt.x(j);
+    z[rt.x(j)] = make_float2(a[s], b ? b[s] : 0.0f);
+  }
+  rows_forward_pair<NX>(lds, sa, sb, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
+}
+
+// Packed row spectra -> real plane(s) (b may be null).
+template <int NX>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_inverse_real(const float2* sa, const float2* sb,
+                                                                       float* __restrict__ a, float* __restrict__ b,
+                                                                       SpecGeom sg, const float2* __restrict__ twx,
+                                                                       int nx) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const RowThread<NX> rt(tid, blockIdx.x);
+  float2* z = lds + rt.rl * NX;
+  const long rowoff = (long)rt.y * nx;
+  rows_inverse_pair<NX>(lds, sa, sb, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
+#pragma unroll
+  for (int j = 0; j < kRowsPerThreadSites; ++j) {
+    const long s = rowoff + rt.x(j);
+    const float2 v = z[rt.x(j)];
+    a[s] = v.x;
+    if (b) b[s] = v.y;
+  }
+}
+
+// Sum the per-block partials in FP64, in a fixed order, into the 8 globals.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part_d, int nd,
+                                                  const float* __restrict__ part_f, int nf, int have_step,
+                                                  double cell, double dt, double steps,
+                                                  double* __restrict__ out) {
+  __shared__ double sd[256][4];
+  __shared__ float sf[256][4];
+  const int tid = threadIdx.x;
+  double s[4] = {0, 0, 0, 0};
+  float um = 0.0f, bd = 0.0f, rr = 0.0f;
+  for (int i = tid; i < nd; i += 256) {
+    for (int c = 0; c < 4; ++c) s[c] += part_d[6 * i + c];
+    um = fmaxf(um, (float)part_d[6 * i + 4]);
+    bd = fmaxf(bd, (float)part_d[6 * i + 5]);
+  }
+  if (have_step)
+    for (int i = tid; i < nf; i += 256) {
+      rr = fmaxf(rr, part_f[2 * i]);
+      bd = fmaxf(bd, part_f[2 * i + 1]);
+    }
+  for (int c = 0; c < 4; ++c) sd[tid][c] = s[c];
+  sf[tid][0] = um;
+  sf[tid][1] = bd;
+  sf[tid][2] = rr;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      for (int c = 0; c < 4; ++c) sd[tid][c] += sd[tid + w][c];
+      for (int c = 0; c < 3; ++c) sf[tid][c] = fmaxf(sf[tid][c], sf[tid + w][c]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = sd[0][0] * cell;
+    out[1] = sd[0][1] * cell;
+    out[2] = sd[0][2] * cell;
+    out[3] = sd[0][3] * cell;
+    out[4] = (double)sf[0][2] * dt;
+    out[5] = sf[0][0];
+    out[6] = sf[0][1] > 0.0f ? 1.0 : 0.0;
+    out[7] = steps;
+  }
+}
+
+}  // namespace fftlb

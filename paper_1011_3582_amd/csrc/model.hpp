@@ -1,0 +1,139 @@
+// Constants and per-site physics of the thermal van der Waals FFT-LB model.
+//
+//  * velocity set, Eq. (1): v_0 = 0, v_ki = v_k (cos((i-1) pi/4), sin((i-1) pi/4)),
+//    v_k = 1.0, 1.9, 2.9, 4.3; population index q = 1 + 8(k-1) + (i-1);
+//  * weights F_k(T), Eqs. (4)-(6), evaluated in FP64 per site because the quartic
+//    polynomial cancels strongly at liquid-vapour temperatures;
+//  * equilibrium, Eq. (3), and force term, Eq. (11), in FP32.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fftlb {
+
+constexpr int kQ = 33;
+constexpr double kSpeeds[4] = {1.0, 1.9, 2.9, 4.3};
+
+struct VelTable {
+  float vx[kQ], vy[kQ], v2[kQ];
+};
+
+constexpr VelTable make_vel_table() {
+  VelTable t{};
+  constexpr double r = 0.70710678118654752440;  // cos(pi/4)
+  const double c8[8] = {1.0, r, 0.0, -r, -1.0, -r, 0.0, r};
+  const double s8[8] = {0.0, r, 1.0, r, 0.0, -r, -1.0, -r};
+  t.vx[0] = t.vy[0] = t.v2[0] = 0.0f;
+  for (int k = 0; k < 4; ++k)
+    for (int i = 0; i < 8; ++i) {
+      const int q = 1 + 8 * k + i;
+      t.vx[q] = static_cast<float>(kSpeeds[k] * c8[i]);
+      t.vy[q] = static_cast<float>(kSpeeds[k] * s8[i]);
+      t.v2[q] = static_cast<float>(kSpeeds[k] * kSpeeds[k]);
+    }
+  return t;
+}
+
+// F_k(T) = T (c0 + T (c1 + T (c2 + T c3))) with, for the cyclic neighbours s1, s2, s3 of
+// s_k = v_k^2 (Eq. (6)): c3 = 48/D, c2 = -6 (s1 + s2 + s3)/D, c1 = (s1 s2 + s2 s3 + s3 s1)/D,
+// c0 = -s1 s2 s3 / (4 D), D = s_k (s_k - s1)(s_k - s2)(s_k - s3).
+struct WeightPoly {
+  double c[4][4];
+};
+
+constexpr WeightPoly make_weight_poly() {
+  WeightPoly w{};
+  double s[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 4; ++k) s[k] = kSpeeds[k] * kSpeeds[k];
+  for (int k = 0; k < 4; ++k) {
+    const double s1 = s[(k + 1) % 4], s2 = s[(k + 2) % 4], s3 = s[(k + 3) % 4];
+    const double D = s[k] * (s[k] - s1) * (s[k] - s2) * (s[k] - s3);
+    w.c[k][3] = 48.0 / D;
+    w.c[k][2] = -6.0 * (s1 + s2 + s3) / D;
+    w.c[k][1] = (s1 * s2 + s2 * s3 + s3 * s1) / D;
+    w.c[k][0] = -s1 * s2 * s3 / (4.0 * D);
+  }
+  return w;
+}
+
+__constant__ VelTable c_vel = make_vel_table();
+__constant__ WeightPoly c_wpoly = make_weight_poly();
+
+// Scalar parameters handed to the kernels by value.
+struct Model {
+  float dt;     // time step
+  float omega;  // dt / tau (0 when the collision is off)
+  float K, H, zeta, q, a, b;
+  float scale;  // 1 / (nx ny): normalisation of the inverse 2D transform
+};
+
+// Weights of the rest particle and the four speed groups at temperature T.
+__device__ __forceinline__ void weights(float T, float& F0, float& F1, float& F2, float& F3, float& F4) {
+  const double t = T;
+  double F[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* c = c_wpoly.c[k];
+    F[k] = t * (c[0] + t * (c[1] + t * (c[2] + t * c[3])));
+  }
+  F0 = static_cast<float>(1.0 - 8.0 * (F[0] + F[1] + F[2] + F[3]));
+  F1 = static_cast<float>(F[0]);
+  F2 = static_cast<float>(F[1]);
+  F3 = static_cast<float>(F[2]);
+  F4 = static_cast<float>(F[3]);
+}
+
+// Everything about one site that the 33-velocity loop needs.
+struct Site {
+  float rho, ux, uy, invT;
+  float base, g;             // 1 - u^2/2T + u^4/8T^2  and  1 - u^2/2T
+  float F0, F1, F2, F3, F4;  // weights
+  float s0, sx, sy, cc;      // force factor: A + B.(v-u) + (C+Cq)|v-u|^2 = s0 + sx vx + sy vy + cc |v|^2
+};
+
+__device__ __forceinline__ void site_equilibrium(Site& s, float rho, float ux, float uy, float T) {
+  s.rho = rho;
+  s.ux = ux;
+  s.uy = uy;
+  s.invT = 1.0f / T;
+  const float u2 = ux * ux + uy * uy;
+  s.g = 1.0f - 0.5f * u2 * s.invT;
+  s.base = s.g + 0.125f * u2 * u2 * s.invT * s.invT;
+  weights(T, s.F0, s.F1, s.F2, s.F3, s.F4);
+  s.s0 = s.sx = s.sy = s.cc = 0.0f;
+}
+
+// Force coefficients A, B, C + C_q (Eqs. (20)-(23)) folded into the polynomial in v.
+__device__ __forceinline__ void site_force(Site& s, float T, float Bx, float By, float cc) {
+  const float A = -2.0f * cc * T;
+  const float u2 = s.ux * s.ux + s.uy * s.uy;
+  s.s0 = A - (Bx * s.ux + By * s.uy) + cc * u2;
+  s.sx = Bx - 2.0f * cc * s.ux;
+  s.sy = By - 2.0f * cc * s.uy;
+  s.cc = cc;
+}
+
+__device__ __forceinline__ float group_weight(const Site& s, int k) {
+  return k == 0 ? s.F1 : (k == 1 ? s.F2 : (k == 2 ? s.F3 : s.F4));
+}
+
+// Eq. (3) for a moving population with velocity (vx, vy) and group weight Fk.
+__device__ __forceinline__ float feq_moving(const Site& s, float Fk, float vx, float vy) {
+  const float w = (vx * s.ux + vy * s.uy) * s.invT;
+  const float poly = s.base + s.g * (w + 0.5f * w * w) + w * w * w * (1.0f / 6.0f) +
+                     w * w * w * w * (1.0f / 24.0f);
+  return s.rho * Fk * poly;
+}
+
+__device__ __forceinline__ float feq_rest(const Site& s) { return s.rho * s.F0 * s.base; }
+
+// f^{n+1} = f - dt C - omega (f - feq) + dt I with I = -(s0 + sx vx + sy vy + cc |v|^2) feq.
+// The increment is formed first and added once: f is rounded to FP32 a single time and
+// no O(eps) multiple of f (e.g. from rounding 1 - omega) biases the mass.
+__device__ __forceinline__ float relax_update(const Site& s, const Model& M, float f, float feq, float conv,
+                                              float vx, float vy, float v2) {
+  const float fac = s.s0 + s.sx * vx + s.sy * vy + s.cc * v2;
+  const float inc = M.omega * (feq - f) - M.dt * (fac * feq + conv);
+  return f + inc;
+}
+
+}  // namespace fftlb

@@ -1,0 +1,235 @@
+"""Python binding of libfftlb.so (ctypes).  Argument marshalling only: every step of the
+solver runs in the HIP kernels of the library; PyTorch provides device memory and streams.
+
+Importing this module loads the library and raises if it is not built or not loadable;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import re
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfftlb.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "fftlb.h")
+
+FFTLB_OK, FFTLB_EINVAL, FFTLB_ENOSPC, FFTLB_EHIP, FFTLB_EUNSTABLE = 0, -1, -2, -3, -4
+Q = 33
+NGLOBALS = 8
+GLOBAL_NAMES = ("mass", "px", "py", "energy", "residual", "umax", "nonfinite", "steps")
+
+
+class FFTLBError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = _lib.fftlb_strerror(code).decode() if _lib is not None else str(code)
+        detail = _lib.fftlb_last_error().decode() if (_lib is not None and code == FFTLB_EHIP) else ""
+        super().__init__(f"{what}: {msg} ({code}){' - ' + detail if detail else ''}")
+
+
+class Config(ctypes.Structure):
+    """Mirror of struct fftlb_config in include/fftlb.h."""
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
+                ("tau", ctypes.c_double), ("K", ctypes.c_double), ("H", ctypes.c_double),
+                ("zeta", ctypes.c_double), ("q", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("filter_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+@dataclasses.dataclass
+class Params:
+    """Model parameters; defaults are the paper's (Sec. 3.5 list, k4 window) with the
+    van der Waals constants of the benchmark fluid (a = 2, b = 0.4)."""
+    dx: float = 1.0 / 256.0
+    dy: float = 1.0 / 256.0
+    dt: float = 1e-5
+    tau: float = 1e-2
+    K: float = 1e-5
+    H: float = 0.0
+    zeta: float = 0.0
+    q: float = -0.004
+    a: float = 2.0
+    b: float = 0.4
+    m: int = 4
+
+    def config(self, nx: int, ny: int) -> Config:
+        return Config(nx, ny, self.dx, self.dy, self.dt, self.tau, self.K, self.H, self.zeta, self.q,
+                      self.a, self.b, self.m, 0)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1011_3582_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    cfgp = ctypes.POINTER(Config)
+    sig = {
+        "fftlb_workspace_bytes": (ctypes.c_int, [cfgp, ctypes.POINTER(sz)]),
+        "fftlb_init": (ctypes.c_int, [cfgp, vp, sz, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]),
+        "fftlb_step": (ctypes.c_int, [vp, i64, vp]),
+        "fftlb_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "fftlb_get_state": (ctypes.c_int, [vp, vp, vp]),
+        "fftlb_set_state": (ctypes.c_int, [vp, vp, vp]),
+        "fftlb_derivative": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+        "fftlb_run_stage": (ctypes.c_int, [vp, i32, i32, vp]),
+        "fftlb_destroy": (ctypes.c_int, [vp]),
+        "fftlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "fftlb_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def library():
+    return _lib
+
+
+def header_functions(path: str = HEADER_PATH):
+    """Names of the functions declared in include/fftlb.h."""
+    txt = open(path).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(fftlb_\w+)\s*\(", txt, re.M)))
+
+
+def _check(rc: int, what: str):
+    if rc != FFTLB_OK:
+        raise FFTLBError(rc, what)
+
+
+def workspace_bytes(nx: int, ny: int, params: Params | None = None) -> int:
+    cfg = (params or Params()).config(nx, ny)
+    out = ctypes.c_size_t()
+    _check(_lib.fftlb_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)), "fftlb_workspace_bytes")
+    return out.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _field(x, ny, nx, device):
+    t = torch.as_tensor(x, dtype=torch.float32, device=device)
+    if t.shape != (ny, nx):
+        raise ValueError(f"field shape {tuple(t.shape)} != {(ny, nx)}")
+    return t.contiguous()
+
+
+class Solver:
+    """One FFT-LB simulation on one GPU.
+
+    rho0, ux0, uy0, T0: [ny, nx] arrays or tensors (copied to the device as float32).
+    The distribution starts at the local equilibrium f^eq(rho0, u0, T0).
+    """
+
+    def __init__(self, rho0, ux0, uy0, T0, params: Params | None = None, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the FFT-LB solver runs only through its HIP library")
+        self.params = params or Params()
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        rho0 = torch.as_tensor(rho0)
+        self.ny, self.nx = int(rho0.shape[0]), int(rho0.shape[1])
+        self.cfg = self.params.config(self.nx, self.ny)
+        with torch.cuda.device(self.device):
+            nbytes = workspace_bytes(self.nx, self.ny, self.params)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            fields = [_field(a, self.ny, self.nx, self.device) for a in (rho0, ux0, uy0, T0)]
+            h = ctypes.c_void_p()
+            rc = _lib.fftlb_init(ctypes.byref(self.cfg), _ptr(self.workspace), nbytes, *(_ptr(f) for f in fields),
+                                 _stream(self.device), ctypes.byref(h))
+            _check(rc, "fftlb_init")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("solver is closed")
+        return self._h
+
+    def step(self, nsteps: int = 1):
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_step(self.handle, int(nsteps), _stream(self.device)), "fftlb_step")
+
+    def moments(self, globals_: bool = True):
+        """Returns (rho, ux, uy, T) float32 device tensors and a dict of FP64 globals."""
+        with torch.cuda.device(self.device):
+            outs = [torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) for _ in range(4)]
+            g = torch.empty(NGLOBALS, dtype=torch.float64, device=self.device) if globals_ else None
+            _check(_lib.fftlb_moments(self.handle, *(_ptr(o) for o in outs), _ptr(g), _stream(self.device)),
+                   "fftlb_moments")
+            glob = None
+            if g is not None:
+                vals = g.cpu().tolist()
+                glob = dict(zip(GLOBAL_NAMES, vals))
+                if glob["nonfinite"] != 0.0:
+                    raise FFTLBError(FFTLB_EUNSTABLE, "fftlb_moments")
+        return outs, glob
+
+    def globals_tensor(self, out):
+        """Enqueue the FP64 globals into a device float64[8] tensor (no host sync)."""
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_moments(self.handle, None, None, None, None, _ptr(out), _stream(self.device)),
+                   "fftlb_moments")
+
+    def run_stage(self, stage: int, reps: int = 1):
+        """Enqueue `reps` launches of one kernel of the step (see fftlb_run_stage)."""
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_run_stage(self.handle, int(stage), int(reps), _stream(self.device)), "fftlb_run_stage")
+
+    def get_state(self):
+        with torch.cuda.device(self.device):
+            f = torch.empty((Q, self.ny, self.nx), dtype=torch.float32, device=self.device)
+            _check(_lib.fftlb_get_state(self.handle, _ptr(f), _stream(self.device)), "fftlb_get_state")
+        return f
+
+    def set_state(self, f):
+        with torch.cuda.device(self.device):
+            t = torch.as_tensor(f, dtype=torch.float32, device=self.device).contiguous()
+            if t.shape != (Q, self.ny, self.nx):
+                raise ValueError("state shape must be [33, ny, nx]")
+            _check(_lib.fftlb_set_state(self.handle, _ptr(t), _stream(self.device)), "fftlb_set_state")
+            torch.cuda.current_stream(self.device).synchronize()
+
+    def derivative(self, g, op: int):
+        with torch.cuda.device(self.device):
+            t = _field(g, self.ny, self.nx, self.device)
+            out = torch.empty_like(t)
+            _check(_lib.fftlb_derivative(self.handle, _ptr(t), _ptr(out), int(op), _stream(self.device)),
+                   "fftlb_derivative")
+        return out
+
+    def close(self):
+        if self._h is not None:
+            _lib.fftlb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def svups(nx: int, ny: int, steps: int, seconds: float) -> float:
+    """Site-velocity updates per second: 33 nx ny steps / seconds."""
+    return Q * nx * ny * steps / seconds if seconds > 0 else math.nan

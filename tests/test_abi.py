@@ -1,0 +1,68 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry point,
+and rejects bad arguments on the host before touching a device."""
+import ctypes
+import math
+
+import pytest
+
+from paper_1011_3582_amd import fftlb as F
+
+
+def test_library_exports_every_declared_function():
+    names = F.header_functions()
+    assert {"fftlb_init", "fftlb_step", "fftlb_moments", "fftlb_get_state", "fftlb_set_state",
+            "fftlb_destroy", "fftlb_workspace_bytes", "fftlb_strerror", "fftlb_derivative",
+            "fftlb_last_error"} <= set(names)
+    lib = F.library()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_config_struct_matches_header_layout():
+    # int32 nx, ny; 10 doubles; int32 filter_order, reserved
+    assert ctypes.sizeof(F.Config) == 8 + 10 * 8 + 8
+    assert F.Config.dx.offset == 8
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (1024, 1024), (512, 4), (8, 32), (2048, 16)])
+def test_workspace_bytes_valid(nx, ny):
+    b = F.workspace_bytes(nx, ny)
+    # 93 float planes of nx*ny plus small tables and partials
+    assert 93 * nx * ny * 4 <= b <= 93 * nx * ny * 4 + 64 * 1024 + 64 * ny
+
+
+@pytest.mark.parametrize("change", [
+    dict(nx=96), dict(nx=4), dict(ny=2), dict(nx=4096), dict(ny=3000), dict(nx=8, ny=16),
+    dict(dt=0.0), dict(dx=-1.0), dict(tau=0.0), dict(tau=math.nan), dict(K=-1.0), dict(b=-0.1),
+    dict(filter_order=5), dict(filter_order=-1), dict(reserved=1), dict(q=math.inf),
+])
+def test_invalid_configs_rejected(change):
+    cfg = F.Params().config(64, 64)
+    for k, v in change.items():
+        setattr(cfg, k, v)
+    out = ctypes.c_size_t()
+    assert F.library().fftlb_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == F.FFTLB_EINVAL
+    h = ctypes.c_void_p()
+    rc = F.library().fftlb_init(ctypes.byref(cfg), None, 0, None, None, None, None, None, ctypes.byref(h))
+    assert rc == F.FFTLB_EINVAL and h.value is None
+
+
+def test_init_rejects_small_or_misaligned_workspace_before_device_work():
+    cfg = F.Params().config(64, 64)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: size/alignment are checked first
+    lib = F.library()
+    need = F.workspace_bytes(64, 64)
+    assert lib.fftlb_init(ctypes.byref(cfg), fake, need - 1, fake, fake, fake, fake, None, ctypes.byref(h)) == F.FFTLB_ENOSPC
+    assert lib.fftlb_init(ctypes.byref(cfg), ctypes.c_void_p(0x1004), need, fake, fake, fake, fake, None,
+                          ctypes.byref(h)) == F.FFTLB_ENOSPC
+    assert lib.fftlb_init(ctypes.byref(cfg), fake, need, None, fake, fake, fake, None, ctypes.byref(h)) == F.FFTLB_EINVAL
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = F.library()
+    assert lib.fftlb_step(None, 1, None) == F.FFTLB_EINVAL
+    assert lib.fftlb_moments(None, None, None, None, None, None, None) == F.FFTLB_EINVAL
+    assert lib.fftlb_get_state(None, None, None) == F.FFTLB_EINVAL
+    assert lib.fftlb_destroy(None) == F.FFTLB_EINVAL
+    assert lib.fftlb_strerror(F.FFTLB_ENOSPC).decode().startswith("workspace")

@@ -1,15 +1,18 @@
 // In-LDS Stockham FFTs for gfx950, used by every kernel of the solver.
 //
-// A transform of length N (a power of two) is a sequence of radix-4 passes, preceded
-// by one radix-2 pass when log2 N is odd.  Each pass reads its butterfly inputs from
-// LDS into registers, waits at a barrier, multiplies by the twiddles, does the
-// butterfly in registers and writes the outputs back in place (Stockham autosort:
-// natural order in, natural order out).
+// A transform of length N (a power of two) is a sequence of radix-16 passes, preceded
+// by one radix-2, -4 or -8 pass when log2 N is not a multiple of 4.  Each pass reads
+// its butterfly inputs from LDS into registers, waits at a barrier, multiplies by the
+// twiddles, does the butterfly in registers and writes the outputs back in place
+// (Stockham autosort: natural order in, natural order out).  With radix 16 a 1024-point
+// transform takes three passes, and a thread holds 16 complex values per pass.
 //
-// Layout: element i of transform t lives at lds[t * st + i * si].  With TFAST the
-// consecutive threads of a block walk consecutive transforms (column kernels, where
-// transforms are interleaved with stride 1); otherwise consecutive elements of one
-// transform (row kernels, where each transform is contiguous).
+// Layout: element i of transform t lives at lds[swz(t * st + i * si)], where swz() XORs
+// the low five index bits with the next five: a bijection inside every aligned block of
+// 32 elements that spreads the strided stores of the first passes over the LDS banks
+// (two 64-bit accesses per bank row at worst) without enlarging the buffer.  With TFAST the consecutive threads of a block walk
+// consecutive transforms (column kernels, transforms interleaved with stride 1);
+// otherwise consecutive butterflies of one transform (row kernels, contiguous transforms).
 //
 // Twiddles come from a table tw[j] = exp(-2 pi i j / N) computed in FP64 on the host.
 // Direction: DIR = -1 forward (kernel exp(-i k x)), DIR = +1 inverse, both unnormalised.
@@ -30,29 +33,109 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
+// Bank swizzle of an LDS element index (see the file comment).
+__device__ __forceinline__ int swz(int e) { return e ^ ((e >> 5) & 31); }
+
+// Returns v unchanged but opaque to the optimiser.  Index arithmetic derived from the
+// result is recomputed where it is used instead of being hoisted out of loops and kept
+// live (the many per-pass LDS addresses would otherwise exhaust the VGPRs).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// exp(DIR * 2 pi i j / R) for the twiddles inside the radix-8 and radix-16 butterflies.
+template <int R, int DIR>
+__device__ __forceinline__ float2 unit_root(int j) {
+  // cos/sin of multiples of pi/8, exact to float rounding
+  constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+  constexpr float C16[16] = {1.0f, c1, h, s1, 0.0f, -s1, -h, -c1, -1.0f, -c1, -h, -s1, 0.0f, s1, h, c1};
+  constexpr float S16[16] = {0.0f, s1, h, c1, 1.0f, c1, h, s1, 0.0f, -s1, -h, -c1, -1.0f, -c1, -h, -s1};
+  const int m = (j * (16 / R)) & 15;
+  return make_float2(C16[m], DIR < 0 ? -S16[m] : S16[m]);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  const float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 a = cadd(x0, x2), b = csub(x0, x2);
+  const float2 c = cadd(x1, x3), d = csub(x1, x3);
+  // forward: y1 = b - i d, y3 = b + i d; inverse: the conjugate rotation
+  const float2 jd = DIR < 0 ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+  x0 = cadd(a, c);
+  x2 = csub(a, c);
+  x1 = cadd(b, jd);
+  x3 = csub(b, jd);
+}
+
+// R-point DFT of v[0..R-1] in registers, in place.  R = 4 B: DFT_4 over the stride-B
+// elements, twiddles w_R^(nB kA), then DFT_B over each group of B.  Output k = kA + 4 kB
+// is left in v[out_slot<R>(k)] = v[kA B + kB] (no register shuffling; callers index the
+// outputs through out_slot).
+template <int R>
+constexpr int out_slot(int k) {
+  return R <= 4 ? k : (k % 4) * (R / 4) + k / 4;
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
   if constexpr (R == 2) {
-    float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
+    dft2<DIR>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
   } else {
-    static_assert(R == 4, "radix");
-    float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-    float2 c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
-    // forward: y1 = b - i d, y3 = b + i d; inverse: the conjugate rotation
-    float2 jd = DIR < 0 ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
-    v[0] = cadd(a, c);
-    v[2] = csub(a, c);
-    v[1] = cadd(b, jd);
-    v[3] = csub(b, jd);
+    constexpr int A = 4, B = R / 4;
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) dft4<DIR>(v[nb], v[nb + B], v[nb + 2 * B], v[nb + 3 * B]);
+    // v[kA * B + nB] now holds DFT_A output kA of column nB
+#pragma unroll
+    for (int nb = 1; nb < B; ++nb)
+#pragma unroll
+      for (int ka = 1; ka < A; ++ka) v[ka * B + nb] = cmul(v[ka * B + nb], unit_root<R, DIR>(nb * ka));
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) {
+      if constexpr (B == 2) {
+        dft2<DIR>(v[ka * B], v[ka * B + 1]);
+      } else {
+        dft4<DIR>(v[ka * B], v[ka * B + 1], v[ka * B + 2], v[ka * B + 3]);
+      }
+    }
+  }
+}
+
+// Twiddles w^r (r = 1..R-1) applied to v[r], from the table entries of w, w^2, w^4, w^8
+// (exact up to their FP32 rounding); the other powers are products of at most four of
+// them, formed as they are used.
+template <int R, int DIR>
+__device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restrict__ tw, int stride) {
+  float2 p[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    if ((1 << b) < R) p[b] = tw[(1 << b) * stride];
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    float2 w = make_float2(1.0f, 0.0f);
+    bool first = true;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (r & (1 << b)) {
+        w = first ? p[b] : cmul(w, p[b]);
+        first = false;
+      }
+    v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
   }
 }
 
 // One Stockham pass of radix R over NB transforms of length N, span P (product of the
 // radices of the passes before it), executed by NTH threads.
 template <int N, int R, int P, int DIR, int NTH, int NB, bool TFAST>
-__device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int st, int si,
+__device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off, int st, int si,
                                               const float2* __restrict__ tw, int tid) {
   constexpr int NBF = N / R;               // butterflies per transform
   constexpr int TOT = NBF * NB;            // butterflies per pass
@@ -60,6 +143,7 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int st, 
   constexpr bool EXACT = (TOT % NTH) == 0;
   float2 v[BPT][R];
   int base[BPT], idx[BPT];
+  tid = opaque(tid);
 #pragma unroll
   for (int s = 0; s < BPT; ++s) {
     const int b = tid + s * NTH;
@@ -71,11 +155,11 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int st, 
       t = b / NBF;
       i = b % NBF;
     }
-    base[s] = t * st;
+    base[s] = off + t * st;
     idx[s] = i;
     if (EXACT || b < TOT) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[s][r] = lds[base[s] + (i + r * NBF) * si];
+      for (int r = 0; r < R; ++r) v[s][r] = lds[swz(base[s] + (i + r * NBF) * si)];
     }
   }
   __syncthreads();
@@ -85,40 +169,43 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int st, 
     if (EXACT || b < TOT) {
       const int i = idx[s];
       const int k = i & (P - 1);
-      if constexpr (P > 1) {
-        const int stride = k * (N / (P * R));
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const float2 w = tw[r * stride];
-          v[s][r] = DIR < 0 ? cmul(v[s][r], w) : cmulc(v[s][r], w);
-        }
-      }
+      if constexpr (P > 1) apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
       dft<R, DIR>(v[s]);
       const int j0 = (i - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[base[s] + (j0 + r * P) * si] = v[s][r];
+      for (int r = 0; r < R; ++r) lds[swz(base[s] + (j0 + r * P) * si)] = v[s][out_slot<R>(r)];
     }
   }
   __syncthreads();
 }
 
+// Radix of the pass with span P: the remainder pass (2, 4 or 8) first, radix 16 after.
+template <int N, int P>
+constexpr int pass_radix() {
+  constexpr int l = ilog2(N);
+  if (P == 1 && (l % 4) != 0) return 1 << (l % 4);
+  return 16;
+}
+
 template <int N, int P, int DIR, int NTH, int NB, bool TFAST>
-__device__ __forceinline__ void fft_passes(float2* lds, int st, int si, const float2* __restrict__ tw,
+__device__ __forceinline__ void fft_passes(float2* lds, int off, int st, int si, const float2* __restrict__ tw,
                                            int tid) {
   if constexpr (P < N) {
-    constexpr int R = (P == 1 && (ilog2(N) & 1)) ? 2 : 4;
-    stockham_pass<N, R, P, DIR, NTH, NB, TFAST>(lds, st, si, tw, tid);
-    fft_passes<N, P * R, DIR, NTH, NB, TFAST>(lds, st, si, tw, tid);
+    constexpr int R = pass_radix<N, P>();
+    stockham_pass<N, R, P, DIR, NTH, NB, TFAST>(lds, off, st, si, tw, tid);
+    fft_passes<N, P * R, DIR, NTH, NB, TFAST>(lds, off, st, si, tw, tid);
   }
 }
 
-// Full length-N transform of NB sequences in LDS.  Callers must have a barrier between
-// their last write of the data and this call; the call ends with a barrier.
+// Full length-N transform of NB sequences in LDS; element i of transform t is at
+// lds[swz(off + t * st + i * si)] (the swizzle is applied to the whole index, so `off`
+// must be passed here rather than folded into the pointer).  Callers must have a barrier
+// between their last write of the data and this call; the call ends with a barrier.
 template <int N, int DIR, int NTH, int NB, bool TFAST>
-__device__ __forceinline__ void fft_lds(float2* lds, int st, int si, const float2* __restrict__ tw,
+__device__ __forceinline__ void fft_lds(float2* lds, int off, int st, int si, const float2* __restrict__ tw,
                                         int tid) {
   static_assert((N & (N - 1)) == 0 && N >= 2, "power-of-two length");
-  fft_passes<N, 1, DIR, NTH, NB, TFAST>(lds, st, si, tw, tid);
+  fft_passes<N, 1, DIR, NTH, NB, TFAST>(lds, off, st, si, tw, tid);
 }
 
 }  // namespace fftlb

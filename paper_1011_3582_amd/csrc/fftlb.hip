@@ -37,7 +37,7 @@ constexpr int kMaxN = 2048;
 constexpr int kStepsPerGraph = 16;
 
 int row_rows_per_block(int nx) {
-  const int tpr = nx / 4;
+  const int tpr = nx / (nx >= 2048 ? 4 : 2);  // threads per row, as in RowGeom
   return tpr >= 64 ? 1 : 64 / tpr;
 }
 
@@ -169,7 +169,8 @@ int dispatch_nx(int nx, A&&... a) {
   return FFTLB_EINVAL;
 }
 
-constexpr int col_threads(int ny, int cw) { return std::min(256, std::max(64, ny * cw / 4)); }
+// radix-16 passes: one 16-point butterfly per thread per pass
+constexpr int col_threads(int ny, int cw) { return std::min(1024, std::max(64, ny * cw / 16)); }
 
 template <int NY, int CW>
 struct ColConv {
@@ -179,7 +180,7 @@ struct ColConv {
     } else {
       constexpr int NT = col_threads(NY, CW);
       const int nblocks = 32 * ((h->nx / 2) / CW);
-      hipLaunchKernelGGL((k_col_conv<NY, CW, NT>), dim3(nblocks), dim3(NT), NY * CW * sizeof(float2), s,
+      hipLaunchKernelGGL((k_col_conv<NY, CW, NT>), dim3(nblocks), dim3(NT), lds_alloc(NY * CW) * sizeof(float2), s,
                          h->P.sf, h->twy, h->kapx, h->kapy, h->nx, h->tw, h->M.scale);
       return FFTLB_OK;
     }
@@ -194,7 +195,7 @@ struct ColMulti {
     } else {
       constexpr int NT = col_threads(NY, CW);
       const int nsub = (h->nx / 2) / CW;
-      const size_t lds = (size_t)NY * CW * (maxin + 1) * sizeof(float2);
+      const size_t lds = (size_t)(lds_alloc(NY * CW * maxin) + lds_alloc(NY * CW)) * sizeof(float2);
       hipLaunchKernelGGL((k_col_multi<NY, CW, NT>), dim3(nsub, ngroups), dim3(NT), lds, s, L, h->twy, h->kapx,
                          h->kapy, h->nx, h->tw, h->M.scale);
       return FFTLB_OK;

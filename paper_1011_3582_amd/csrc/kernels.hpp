@@ -27,15 +27,21 @@
 
 namespace fftlb {
 
-constexpr int kRowsPerThreadSites = 4;  // each row-kernel thread owns 4 sites of its row
+// LDS allocation (in float2) rounded up to whole 32-element swizzle blocks.
+constexpr int lds_alloc(int n) { return (n + 31) / 32 * 32; }
 
-// Row-kernel geometry: NX/4 threads per row, enough rows per block for >= 64 threads.
+// Row-kernel geometry.  Each thread owns J sites of its row (J = 2, or 4 for 2048-point
+// rows), a block holds RB rows (at least 64 threads), and row transforms are done NPB
+// plane pairs at a time: a batch is NPB * RB complex transforms of length NX, so with
+// radix-16 passes each thread does one 16-point butterfly per pass (NPB = 16 / J).
 template <int NX>
 struct RowGeom {
-  static constexpr int TPR = NX / 4;
+  static constexpr int J = NX >= 2048 ? 4 : 2;
+  static constexpr int TPR = NX / J;
   static constexpr int RB = (TPR >= 64) ? 1 : 64 / TPR;
   static constexpr int NT = RB * TPR;
-  static constexpr int LDS = RB * NX;  // float2 elements of the row buffer
+  static constexpr int NPB = 16 / J;
+  static constexpr int LDS = lds_alloc(NPB * RB * NX);  // float2 elements (<= 64 KB)
 };
 
 struct SpecGeom {
@@ -97,76 +103,105 @@ struct RowThread {
     y = blk * RowGeom<NX>::RB + rl;
   }
   __device__ __forceinline__ int x(int j) const { return lt + j * RowGeom<NX>::TPR; }
+  // LDS element of site x(j) in batch slot `slot`
+  __device__ __forceinline__ int at(int slot, int j) const {
+    return swz((slot * RowGeom<NX>::RB + rl) * NX + x(j));
+  }
 };
 
-// LDS <- Z(k) = A(k) + i B(k) for k = 0..NX-1, from the packed half spectra of planes A
-// and B (B may be null) at the block's rows; Hermitian completion of the upper half.
-template <int NX>
-__device__ __forceinline__ void rows_load_pair(float2* lds, const float2* __restrict__ SA,
-                                               const float2* __restrict__ SB, const SpecGeom& sg,
-                                               int row0, int tid) {
+// A batch of up to four plane pairs: pair p transforms planes (a[p], b[p]) as z = a + i b.
+template <int NP>
+struct PairBatch {
+  const float2* a[NP];
+  const float2* b[NP];   // may be null
+};
+
+template <int NP>
+struct PairBatchOut {
+  float2* a[NP];
+  float2* b[NP];         // may be null
+};
+
+// LDS slot p <- Z(k) = A(k) + i B(k), k = 0..NX-1, for every row of the block, from the
+// packed half spectra of planes a[p], b[p]; Hermitian completion of the upper half.
+template <int NX, int NP>
+__device__ __forceinline__ void rows_load_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
+                                                int row0, int tid) {
   constexpr int H = NX / 2;
+  constexpr int RB = RowGeom<NX>::RB;
   constexpr int NT = RowGeom<NX>::NT;
-  for (int e = tid; e < RowGeom<NX>::RB * H; e += NT) {
-    const int rl = e / H, k = e % H;
-    const int gi = sg.idx(row0 + rl, k);
-    const float2 a = SA[gi];
-    const float2 b = SB ? SB[gi] : make_float2(0.0f, 0.0f);
-    float2* z = lds + rl * NX;
-    if (k == 0) {
-      z[0] = make_float2(a.x, b.x);
-      z[H] = make_float2(a.y, b.y);
-    } else {
-      z[k] = make_float2(a.x - b.y, a.y + b.x);
-      z[NX - k] = make_float2(a.x + b.y, b.x - a.y);
+  tid = opaque(tid);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const float2* __restrict__ A = in.a[p];
+    const float2* __restrict__ B = in.b[p];
+    for (int e = tid; e < RB * H; e += NT) {
+      const int rl = e / H, k = e % H;
+      const int gi = sg.idx(row0 + rl, k);
+      const float2 a = A[gi];
+      const float2 b = B ? B[gi] : make_float2(0.0f, 0.0f);
+      const int z = (p * RB + rl) * NX;
+      if (k == 0) {
+        lds[swz(z)] = make_float2(a.x, b.x);
+        lds[swz(z + H)] = make_float2(a.y, b.y);
+      } else {
+        lds[swz(z + k)] = make_float2(a.x - b.y, a.y + b.x);
+        lds[swz(z + NX - k)] = make_float2(a.x + b.y, b.x - a.y);
+      }
     }
   }
 }
 
-// Packed half spectra of A = Re z and B = Im z from the forward transform Z in LDS.
-template <int NX>
-__device__ __forceinline__ void rows_store_pair(const float2* lds, float2* __restrict__ SA,
-                                                float2* __restrict__ SB, const SpecGeom& sg, int row0,
-                                                int tid) {
+// Packed half spectra of A = Re z and B = Im z from the forward transforms Z in LDS slots.
+template <int NX, int NP>
+__device__ __forceinline__ void rows_store_batch(const float2* lds, const PairBatchOut<NP>& out,
+                                                 const SpecGeom& sg, int row0, int tid) {
   constexpr int H = NX / 2;
+  constexpr int RB = RowGeom<NX>::RB;
   constexpr int NT = RowGeom<NX>::NT;
-  for (int e = tid; e < RowGeom<NX>::RB * H; e += NT) {
-    const int rl = e / H, k = e % H;
-    const float2* z = lds + rl * NX;
-    const float2 Z = z[k];
-    float2 A, B;
-    if (k == 0) {
-      const float2 W = z[H];
-      A = make_float2(Z.x, W.x);
-      B = make_float2(Z.y, W.y);
-    } else {
-      const float2 W = z[NX - k];
-      A = make_float2(0.5f * (Z.x + W.x), 0.5f * (Z.y - W.y));
-      B = make_float2(0.5f * (Z.y + W.y), 0.5f * (W.x - Z.x));
+  tid = opaque(tid);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    float2* __restrict__ OA = out.a[p];
+    float2* __restrict__ OB = out.b[p];
+    for (int e = tid; e < RB * H; e += NT) {
+      const int rl = e / H, k = e % H;
+      const int z = (p * RB + rl) * NX;
+      const float2 Z = lds[swz(z + k)];
+      float2 A, B;
+      if (k == 0) {
+        const float2 W = lds[swz(z + H)];
+        A = make_float2(Z.x, W.x);
+        B = make_float2(Z.y, W.y);
+      } else {
+        const float2 W = lds[swz(z + NX - k)];
+        A = make_float2(0.5f * (Z.x + W.x), 0.5f * (Z.y - W.y));
+        B = make_float2(0.5f * (Z.y + W.y), 0.5f * (W.x - Z.x));
+      }
+      const int gi = sg.idx(row0 + rl, k);
+      OA[gi] = A;
+      if (OB) OB[gi] = B;
     }
-    const int gi = sg.idx(row0 + rl, k);
-    SA[gi] = A;
-    if (SB) SB[gi] = B;
   }
 }
 
-// Inverse row transform of a pair of spectra; afterwards lds[x] = a(x) + i b(x).
-template <int NX>
-__device__ __forceinline__ void rows_inverse_pair(float2* lds, const float2* SA, const float2* SB,
-                                                  const SpecGeom& sg, const float2* twx, int row0, int tid) {
-  rows_load_pair<NX>(lds, SA, SB, sg, row0, tid);
+// Inverse row transforms of a batch; afterwards slot p holds a_p(x) + i b_p(x).
+template <int NX, int NP>
+__device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
+                                                   const float2* twx, int row0, int tid) {
+  rows_load_batch<NX, NP>(lds, in, sg, row0, tid);
   __syncthreads();
-  fft_lds<NX, +1, RowGeom<NX>::NT, RowGeom<NX>::RB, false>(lds, NX, 1, twx, tid);
+  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false>(lds, 0, NX, 1, twx, tid);
 }
 
-// Forward row transform of lds[x] = a(x) + i b(x) (already written, unsynchronised) and
-// store of both packed half spectra.  Ends with a barrier so lds can be reused.
-template <int NX>
-__device__ __forceinline__ void rows_forward_pair(float2* lds, float2* SA, float2* SB, const SpecGeom& sg,
-                                                  const float2* twx, int row0, int tid) {
+// Forward row transforms of slots already written (unsynchronised) and store of the packed
+// half spectra.  Ends with a barrier so the LDS can be reused.
+template <int NX, int NP>
+__device__ __forceinline__ void rows_forward_batch(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
+                                                   const float2* twx, int row0, int tid) {
   __syncthreads();
-  fft_lds<NX, -1, RowGeom<NX>::NT, RowGeom<NX>::RB, false>(lds, NX, 1, twx, tid);
-  rows_store_pair<NX>(lds, SA, SB, sg, row0, tid);
+  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false>(lds, 0, NX, 1, twx, tid);
+  rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
   __syncthreads();
 }
 
@@ -184,7 +219,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
 // Convection: for each of the 32 moving populations, column FFT, multiply by
 // i (v_x k_m(kx) + v_y k_m(ky)) * scale, inverse column FFT, in place.
 template <int NY, int CW, int NT>
-__global__ __launch_bounds__(NT) void k_col_conv(float2* __restrict__ spec, const float2* __restrict__ twy,
+__global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, const float2* __restrict__ twy,
                                                  const float* __restrict__ kapx,
                                                  const float* __restrict__ kapy, int nx, int tw, float scale) {
   extern __shared__ float2 lds[];
@@ -196,22 +231,22 @@ __global__ __launch_bounds__(NT) void k_col_conv(float2* __restrict__ spec, cons
   float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
-    lds[e] = g[y * tw + c];
+    lds[swz(e)] = g[y * tw + c];
   }
   __syncthreads();
-  fft_lds<NY, -1, NT, CW, true>(lds, 1, CW, twy, tid);
+  fft_lds<NY, -1, NT, CW, true>(lds, 0, 1, CW, twy, tid);
   const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
     const float m = (vx * kapx[c0 + c] + vy * kapy[y]) * scale;
-    const float2 v = lds[e];
-    lds[e] = make_float2(-m * v.y, m * v.x);
+    const float2 v = lds[swz(e)];
+    lds[swz(e)] = make_float2(-m * v.y, m * v.x);
   }
   __syncthreads();
-  fft_lds<NY, +1, NT, CW, true>(lds, 1, CW, twy, tid);
+  fft_lds<NY, +1, NT, CW, true>(lds, 0, 1, CW, twy, tid);
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
-    g[y * tw + c] = lds[e];
+    g[y * tw + c] = lds[swz(e)];
   }
 }
 
@@ -240,7 +275,7 @@ struct ColLaunch {
 // Column pass of derivative groups: forward column FFT of nin input spectra, then for
 // each output a linear combination sum_p m_op(kx, ky) X_p, inverse column FFT, store.
 template <int NY, int CW, int NT>
-__global__ __launch_bounds__(NT) void k_col_multi(ColLaunch L, const float2* __restrict__ twy,
+__global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* __restrict__ twy,
                                                   const float* __restrict__ kapx,
                                                   const float* __restrict__ kapy, int nx, int tw, float scale) {
   extern __shared__ float2 lds[];
@@ -253,12 +288,12 @@ __global__ __launch_bounds__(NT) void k_col_multi(ColLaunch L, const float2* __r
     const float2* g = G.in[p] + off;
     for (int e = tid; e < NY * CW; e += NT) {
       const int y = e / CW, c = e % CW;
-      lds[y * W + p * CW + c] = g[y * tw + c];
+      lds[swz(y * W + p * CW + c)] = g[y * tw + c];
     }
   }
   __syncthreads();
-  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true>(lds + p * CW, 1, W, twy, tid);
-  float2* work = lds + NY * W;
+  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true>(lds, p * CW, 1, W, twy, tid);
+  float2* work = lds + lds_alloc(NY * W);
   for (int o = 0; o < G.nout; ++o) {
     for (int e = tid; e < NY * CW; e += NT) {
       const int y = e / CW, c = e % CW;
@@ -267,7 +302,7 @@ __global__ __launch_bounds__(NT) void k_col_multi(ColLaunch L, const float2* __r
       for (int p = 0; p < G.nin; ++p) {
         const int kd = G.kind[o][p];
         if (kd == MK_NONE) continue;
-        const float2 v = lds[y * W + p * CW + c];
+        const float2 v = lds[swz(y * W + p * CW + c)];
         if (kd == MK_IKX || kd == MK_IKY) {
           const float k = kd == MK_IKX ? kx : ky;
           re -= k * v.y;
@@ -281,14 +316,14 @@ __global__ __launch_bounds__(NT) void k_col_multi(ColLaunch L, const float2* __r
           im += m * v.y;
         }
       }
-      work[e] = make_float2(re * scale, im * scale);
+      work[swz(e)] = make_float2(re * scale, im * scale);
     }
     __syncthreads();
-    fft_lds<NY, +1, NT, CW, true>(work, 1, CW, twy, tid);
+    fft_lds<NY, +1, NT, CW, true>(work, 0, 1, CW, twy, tid);
     float2* g = G.out[o] + off;
     for (int e = tid; e < NY * CW; e += NT) {
       const int y = e / CW, c = e % CW;
-      g[y * tw + c] = work[e];
+      g[y * tw + c] = work[swz(e)];
     }
     __syncthreads();
   }
@@ -304,12 +339,12 @@ template <int NX>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model M) {
   extern __shared__ float2 lds[];
   using G = RowGeom<NX>;
+  constexpr int J = G::J;
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
   const int row0 = blockIdx.x * G::RB;
-  float2* z = lds + rt.rl * NX;
-  constexpr int J = kRowsPerThreadSites;
   const long rowoff = (long)rt.y * P.nx;
+  const long hp = P.plane / 2;
 
   float rho[J], ux[J], uy[J], T[J];
 #pragma unroll
@@ -322,16 +357,40 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model
   }
   // the 11 stage-1 derivatives: rx, ry, lap, dxux, dyux, dxuy, dyuy, thx, thy, Tx, Ty
   float d[11][J];
+  if constexpr (G::NPB >= 6) {
+    PairBatch<6> b{{P.s1, P.s1 + 2 * hp, P.s1 + 4 * hp, P.s1 + 6 * hp, P.s1 + 8 * hp, P.s1 + 10 * hp},
+                   {P.s1 + hp, P.s1 + 3 * hp, P.s1 + 5 * hp, P.s1 + 7 * hp, P.s1 + 9 * hp, nullptr}};
+    rows_inverse_batch<NX, 6>(lds, b, P.sg, P.twx, row0, tid);
 #pragma unroll
-  for (int pr = 0; pr < 6; ++pr) {
-    const int a = 2 * pr, bb = 2 * pr + 1;
-    rows_inverse_pair<NX>(lds, P.s1 + (long)a * P.plane / 2, bb < 11 ? P.s1 + (long)bb * P.plane / 2 : nullptr,
-                          P.sg, P.twx, row0, tid);
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const float2 v = lds[rt.at(p, j)];
+        d[2 * p][j] = v.x;
+        if (2 * p + 1 < 11) d[2 * p + 1][j] = v.y;
+      }
+    __syncthreads();
+  } else {
+    PairBatch<4> b1{{P.s1, P.s1 + 2 * hp, P.s1 + 4 * hp, P.s1 + 6 * hp},
+                    {P.s1 + hp, P.s1 + 3 * hp, P.s1 + 5 * hp, P.s1 + 7 * hp}};
+    rows_inverse_batch<NX, 4>(lds, b1, P.sg, P.twx, row0, tid);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const float2 v = lds[rt.at(p, j)];
+        d[2 * p][j] = v.x;
+        d[2 * p + 1][j] = v.y;
+      }
+    __syncthreads();
+    PairBatch<2> b2{{P.s1 + 8 * hp, P.s1 + 10 * hp}, {P.s1 + 9 * hp, nullptr}};
+    rows_inverse_batch<NX, 2>(lds, b2, P.sg, P.twx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const float2 v = z[rt.x(j)];
-      d[a][j] = v.x;
-      if (bb < 11) d[bb][j] = v.y;
+      const float2 v = lds[rt.at(0, j)];
+      d[8][j] = v.x;
+      d[9][j] = v.y;
+      d[10][j] = lds[rt.at(1, j)].x;
     }
     __syncthreads();
   }
@@ -339,7 +398,6 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   float umax = 0.0f;
   int bad = 0;
-  float P1[J], P2[J], P3[J], gx[J], gy[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const float r = rho[j], t = T[j];
@@ -356,11 +414,10 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model
     const float Lxx = Mg * rx * rx + iso;
     const float Lyy = Mg * ry * ry + iso;
     const float Lxy = Mg * rx * ry;
-    P1[j] = S + Lxx;
-    P2[j] = Lxy;
-    P3[j] = S + Lyy;
-    gx[j] = 2.0f * M.q * rT * Tx;
-    gy[j] = 2.0f * M.q * rT * Ty;
+    // slots: 0 = (S + Lxx, Lxy), 1 = (S + Lyy, gx), 2 = (gy, 0)
+    lds[rt.at(0, j)] = make_float2(S + Lxx, Lxy);
+    lds[rt.at(1, j)] = make_float2(S + Lyy, 2.0f * M.q * rT * Tx);
+    lds[rt.at(2, j)] = make_float2(2.0f * M.q * rT * Ty, 0.0f);
     const float lam_du = Lxx * dxux + Lxy * dxuy + Lxy * dyux + Lyy * dyuy;
     const float cubic = rx * (dxux * rx + dxuy * ry) + ry * (dyux * rx + dyuy * ry);
     const float num = (Pw - rT) * theta + lam_du - M.zeta * theta * theta + M.a * r * r * theta +
@@ -377,16 +434,8 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model
     bad |= nonfinite(r) | nonfinite(t) | nonfinite(u2) | nonfinite(C);
   }
   // forward row transforms of the five fields whose divergences the force needs
-  const long hp = P.plane / 2;
-#pragma unroll
-  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(P1[j], P2[j]);
-  rows_forward_pair<NX>(lds, P.s2i, P.s2i + hp, P.sg, P.twx, row0, tid);
-#pragma unroll
-  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(P3[j], gx[j]);
-  rows_forward_pair<NX>(lds, P.s2i + 2 * hp, P.s2i + 3 * hp, P.sg, P.twx, row0, tid);
-#pragma unroll
-  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(gy[j], 0.0f);
-  rows_forward_pair<NX>(lds, P.s2i + 4 * hp, nullptr, P.sg, P.twx, row0, tid);
+  PairBatchOut<3> o{{P.s2i, P.s2i + 2 * hp, P.s2i + 4 * hp}, {P.s2i + hp, P.s2i + 3 * hp, nullptr}};
+  rows_forward_batch<NX, 3>(lds, o, P.sg, P.twx, row0, tid);
 
   // block reduction of the diagnostics (fixed order: deterministic)
   __shared__ double red_d[16][4];
@@ -404,17 +453,17 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model
   __syncthreads();
   if (tid == 0) {
     constexpr int NW = (G::NT + 63) / 64;
-    double s[4] = {0, 0, 0, 0};
+    double sm[4] = {0, 0, 0, 0};
     float um = 0.0f, bd = 0.0f;
     for (int w = 0; w < NW; ++w) {
-      for (int i = 0; i < 4; ++i) s[i] += red_d[w][i];
+      for (int i = 0; i < 4; ++i) sm[i] += red_d[w][i];
       um = fmaxf(um, red_f[w][0]);
       bd = fmaxf(bd, red_f[w][1]);
     }
-    double* o = P.part_d + 6 * (long)blockIdx.x;
-    for (int i = 0; i < 4; ++i) o[i] = s[i];
-    o[4] = um;
-    o[5] = bd;
+    double* out = P.part_d + 6 * (long)blockIdx.x;
+    for (int i = 0; i < 4; ++i) out[i] = sm[i];
+    out[4] = um;
+    out[5] = bd;
   }
 }
 
@@ -422,49 +471,42 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 
 // Collision, force and update (MODE_STEP), or f := f^eq(inputs) (MODE_INIT), or f := input
 // (MODE_SET); then moments of the new f and forward row transforms of f_1..f_32 and of
-// rho, ux, uy, T for the next step.
+// rho, ux, uy, T for the next step.  The 32 moving populations go in four rounds of one
+// speed group (8 populations, 4 complex row transforms) each.
 template <int NX, int MODE>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Model M) {
   extern __shared__ float2 lds[];
   using G = RowGeom<NX>;
-  constexpr int J = kRowsPerThreadSites;
+  constexpr int J = G::J;
+  constexpr int GPR = G::NPB / 4;   // speed groups per round
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
   const int row0 = blockIdx.x * G::RB;
-  float2* z = lds + rt.rl * NX;
   const long rowoff = (long)rt.y * P.nx;
   const long hp = P.plane / 2;
 
   Site st[J];
   if constexpr (MODE == MODE_STEP) {
-    float Bx[J], By[J], Gd[J];
-    rows_inverse_pair<NX>(lds, P.s2o, P.s2o + hp, P.sg, P.twx, row0, tid);
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const float2 v = z[rt.x(j)];
-      Bx[j] = v.x;
-      By[j] = v.y;
-    }
-    __syncthreads();
-    rows_inverse_pair<NX>(lds, P.s2o + 2 * hp, nullptr, P.sg, P.twx, row0, tid);
-#pragma unroll
-    for (int j = 0; j < J; ++j) Gd[j] = z[rt.x(j)].x;
-    __syncthreads();
+    PairBatch<2> b{{P.s2o, P.s2o + 2 * hp}, {P.s2o + hp, nullptr}};
+    rows_inverse_batch<NX, 2>(lds, b, P.sg, P.twx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const long s = rowoff + rt.x(j);
+      const float2 bxy = lds[rt.at(0, j)];
+      const float gd = lds[rt.at(1, j)].x;
       const float r = P.macro[s], ux = P.macro[P.plane + s], uy = P.macro[2 * P.plane + s];
       const float t = P.macro[3 * P.plane + s];
-      site_equilibrium(st[j], r, ux, uy, t);
+      site_init(st[j], r, ux, uy, t);
       const float rT = r * t;
-      const float cc = P.cpl[s] + Gd[j] / (2.0f * rT * t);   // C + C_q
-      site_force(st[j], t, Bx[j] / rT, By[j] / rT, cc);
+      const float cc = P.cpl[s] + gd / (2.0f * rT * t);   // C + C_q
+      site_force(st[j], bxy.x / rT, bxy.y / rT, cc);
     }
+    __syncthreads();
   } else if constexpr (MODE == MODE_INIT) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const long s = rowoff + rt.x(j);
-      site_equilibrium(st[j], P.in0[s], P.in1[s], P.in2[s], P.in3[s]);
+      site_init(st[j], P.in0[s], P.in1[s], P.in2[s], P.in3[s]);
     }
   }
 
@@ -487,79 +529,98 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
     mx[j] = my[j] = me[j] = rs[j] = 0.0f;
     bad |= nonfinite(fn);
   }
-  // moving populations, two at a time (one complex row transform per pair)
+  // moving populations: each round covers GPR speed groups (8 GPR populations, 4 GPR
+  // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1)
 #pragma unroll 1
-  for (int pr = 0; pr < 16; ++pr) {
-    const int qa = 1 + 2 * pr, qb = qa + 1;
-    const int k = pr >> 2;  // speed group of both
-    float2* Sa = P.sf + (long)(qa - 1) * hp;
-    float2* Sb = P.sf + (long)(qb - 1) * hp;
-    float ca[J], cb[J];
-    if constexpr (MODE == MODE_STEP) {
-      rows_inverse_pair<NX>(lds, Sa, Sb, P.sg, P.twx, row0, tid);
+  for (int rd = 0; rd < 4 / GPR; ++rd) {
+    const RowThread<NX> rt(opaque(tid), blockIdx.x);
+    const int q0 = 1 + 8 * GPR * rd;
+    float2* S = P.sf + (long)(q0 - 1) * hp;  // spectra of q0 .. q0 + 8 GPR - 1 are consecutive planes
+    PairBatchOut<G::NPB> io;
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const float2 v = z[rt.x(j)];
-        ca[j] = v.x;
-        cb[j] = v.y;
-      }
-      __syncthreads();
+    for (int p = 0; p < G::NPB; ++p) {
+      io.a[p] = S + 2 * p * hp;
+      io.b[p] = S + (2 * p + 1) * hp;
     }
-    const float vxa = c_vel.vx[qa], vya = c_vel.vy[qa], v2 = c_vel.v2[qa];
-    const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
+    if constexpr (MODE == MODE_STEP) {
+      PairBatch<G::NPB> in;
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const long s = rowoff + rt.x(j);
-      float fa, fb;
-      if constexpr (MODE == MODE_SET) {
-        fa = P.in0[(long)qa * P.plane + s];
-        fb = P.in0[(long)qb * P.plane + s];
-      } else {
-        const float Fk = group_weight(st[j], k);
-        const float ea = feq_moving(st[j], Fk, vxa, vya);
-        const float eb = feq_moving(st[j], Fk, vxb, vyb);
-        if constexpr (MODE == MODE_STEP) {
-          fa = relax_update(st[j], M, P.f[(long)qa * P.plane + s], ea, ca[j], vxa, vya, v2);
-          fb = relax_update(st[j], M, P.f[(long)qb * P.plane + s], eb, cb[j], vxb, vyb, v2);
-          rs[j] += ca[j] + cb[j];
-        } else {
-          fa = ea;
-          fb = eb;
+      for (int p = 0; p < G::NPB; ++p) {
+        in.a[p] = io.a[p];
+        in.b[p] = io.b[p];
+      }
+      rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, P.twx, row0, tid);
+    }
+#pragma unroll
+    for (int g = 0; g < GPR; ++g) {
+      const int k = GPR * rd + g;
+      const float v2 = c_vel.v2[1 + 8 * k];
+      GroupEq ge[J];
+      if constexpr (MODE != MODE_SET) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) ge[j] = group_eq(st[j], (float)group_weight((double)st[j].T, k));
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int slot = 4 * g + p;
+        const int qa = q0 + 2 * slot, qb = qa + 1;
+        const float vxa = c_vel.vx[qa], vya = c_vel.vy[qa];
+        const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
+        float* fA = P.f + (long)qa * P.plane + rowoff;
+        float* fB = P.f + (long)qb * P.plane + rowoff;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const int x = rt.x(j);
+          const int li = rt.at(slot, j);
+          float fa, fb;
+          if constexpr (MODE == MODE_SET) {
+            fa = P.in0[(long)qa * P.plane + rowoff + x];
+            fb = P.in0[(long)qb * P.plane + rowoff + x];
+          } else {
+            const float ea = feq_moving(st[j], ge[j], vxa, vya);
+            const float eb = feq_moving(st[j], ge[j], vxb, vyb);
+            if constexpr (MODE == MODE_STEP) {
+              const float2 c = lds[li];
+              fa = relax_update(st[j], M, fA[x], ea, c.x, vxa, vya, v2);
+              fb = relax_update(st[j], M, fB[x], eb, c.y, vxb, vyb, v2);
+              rs[j] += c.x + c.y;
+            } else {
+              fa = ea;
+              fb = eb;
+            }
+          }
+          fA[x] = fa;
+          fB[x] = fb;
+          m0[j] += fa + fb;
+          mx[j] += vxa * fa + vxb * fb;
+          my[j] += vya * fa + vyb * fb;
+          me[j] += v2 * (fa + fb);
+          bad |= nonfinite(fa) | nonfinite(fb);
+          lds[li] = make_float2(fa, fb);
         }
       }
-      P.f[(long)qa * P.plane + s] = fa;
-      P.f[(long)qb * P.plane + s] = fb;
-      m0[j] += fa + fb;
-      mx[j] += vxa * fa + vxb * fb;
-      my[j] += vya * fa + vyb * fb;
-      me[j] += v2 * (fa + fb);
-      bad |= nonfinite(fa) | nonfinite(fb);
-      z[rt.x(j)] = make_float2(fa, fb);
     }
-    rows_forward_pair<NX>(lds, Sa, Sb, P.sg, P.twx, row0, tid);
+    rows_forward_batch<NX, G::NPB>(lds, io, P.sg, P.twx, row0, tid);
   }
   // moments of the new state and their row spectra
-  float r[J], ux[J], uy[J], T[J];
   float rmax = 0.0f;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const long s = rowoff + rt.x(j);
-    r[j] = m0[j];
-    const float ir = 1.0f / r[j];
-    ux[j] = mx[j] * ir;
-    uy[j] = my[j] * ir;
-    T[j] = 0.5f * me[j] * ir - 0.5f * (ux[j] * ux[j] + uy[j] * uy[j]);
-    P.macro[s] = r[j];
-    P.macro[P.plane + s] = ux[j];
-    P.macro[2 * P.plane + s] = uy[j];
-    P.macro[3 * P.plane + s] = T[j];
+    const float r = m0[j];
+    const float ir = 1.0f / r;
+    const float ux = mx[j] * ir, uy = my[j] * ir;
+    const float T = 0.5f * me[j] * ir - 0.5f * (ux * ux + uy * uy);
+    P.macro[s] = r;
+    P.macro[P.plane + s] = ux;
+    P.macro[2 * P.plane + s] = uy;
+    P.macro[3 * P.plane + s] = T;
     rmax = fmaxf(rmax, fabsf(rs[j]));
-    z[rt.x(j)] = make_float2(r[j], ux[j]);
+    lds[rt.at(0, j)] = make_float2(r, ux);
+    lds[rt.at(1, j)] = make_float2(uy, T);
   }
-  rows_forward_pair<NX>(lds, P.sm, P.sm + hp, P.sg, P.twx, row0, tid);
-#pragma unroll
-  for (int j = 0; j < J; ++j) z[rt.x(j)] = make_float2(uy[j], T[j]);
-  rows_forward_pair<NX>(lds, P.sm + 2 * hp, P.sm + 3 * hp, P.sg, P.twx, row0, tid);
+  PairBatchOut<2> mo{{P.sm, P.sm + 2 * hp}, {P.sm + hp, P.sm + 3 * hp}};
+  rows_forward_batch<NX, 2>(lds, mo, P.sg, P.twx, row0, tid);
 
   if constexpr (MODE == MODE_STEP) {
     __shared__ float red[16][2];
@@ -593,14 +654,14 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_real(const flo
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
-  float2* z = lds + rt.rl * NX;
   const long rowoff = (long)rt.y * nx;
 #pragma unroll
-  for (int j = 0; j < kRowsPerThreadSites; ++j) {
+  for (int j = 0; j < RowGeom<NX>::J; ++j) {
     const long s = rowoff + rt.x(j);
-    z[rt.x(j)] = make_float2(a[s], b ? b[s] : 0.0f);
+    lds[rt.at(0, j)] = make_float2(a[s], b ? b[s] : 0.0f);
   }
-  rows_forward_pair<NX>(lds, sa, sb, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
+  PairBatchOut<1> o{{sa}, {sb}};
+  rows_forward_batch<NX, 1>(lds, o, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
 }
 
 // Packed row spectra -> real plane(s) (b may be null).
@@ -612,13 +673,13 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_inverse_real(const flo
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
-  float2* z = lds + rt.rl * NX;
   const long rowoff = (long)rt.y * nx;
-  rows_inverse_pair<NX>(lds, sa, sb, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
+  PairBatch<1> in{{sa}, {sb}};
+  rows_inverse_batch<NX, 1>(lds, in, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
 #pragma unroll
-  for (int j = 0; j < kRowsPerThreadSites; ++j) {
+  for (int j = 0; j < RowGeom<NX>::J; ++j) {
     const long s = rowoff + rt.x(j);
-    const float2 v = z[rt.x(j)];
+    const float2 v = lds[rt.at(0, j)];
     a[s] = v.x;
     if (b) b[s] = v.y;
   }

@@ -66,45 +66,47 @@ struct Model {
   float scale;  // 1 / (nx ny): normalisation of the inverse 2D transform
 };
 
-// Weights of the rest particle and the four speed groups at temperature T.
-__device__ __forceinline__ void weights(float T, float& F0, float& F1, float& F2, float& F3, float& F4) {
-  const double t = T;
-  double F[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double* c = c_wpoly.c[k];
-    F[k] = t * (c[0] + t * (c[1] + t * (c[2] + t * c[3])));
-  }
-  F0 = static_cast<float>(1.0 - 8.0 * (F[0] + F[1] + F[2] + F[3]));
-  F1 = static_cast<float>(F[0]);
-  F2 = static_cast<float>(F[1]);
-  F3 = static_cast<float>(F[2]);
-  F4 = static_cast<float>(F[3]);
+// Weight F_k(T) of speed group k (0-based), Eq. (4), in FP64.
+__device__ __forceinline__ double group_weight(double t, int k) {
+  const double* c = c_wpoly.c[k];
+  return t * (c[0] + t * (c[1] + t * (c[2] + t * c[3])));
 }
 
-// Everything about one site that the 33-velocity loop needs.
+// Weight of the rest particle, Eq. (5): F_0 = 1 - 8 (F_1 + F_2 + F_3 + F_4).
+__device__ __forceinline__ float rest_weight(float T) {
+  const double t = T;
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sum += group_weight(t, k);
+  return static_cast<float>(1.0 - 8.0 * sum);
+}
+
+// What the 33-velocity loop keeps per site: the moments and the force polynomial
+// A + B.(v-u) + (C+Cq)|v-u|^2 = s0 + sx vx + sy vy + cc |v|^2 (Eqs. (11), (20)).
 struct Site {
-  float rho, ux, uy, invT;
-  float base, g;             // 1 - u^2/2T + u^4/8T^2  and  1 - u^2/2T
-  float F0, F1, F2, F3, F4;  // weights
-  float s0, sx, sy, cc;      // force factor: A + B.(v-u) + (C+Cq)|v-u|^2 = s0 + sx vx + sy vy + cc |v|^2
+  float rho, ux, uy, T;
+  float s0, sx, sy, cc;
 };
 
-__device__ __forceinline__ void site_equilibrium(Site& s, float rho, float ux, float uy, float T) {
+// Per-site factors of Eq. (3) for one speed group.
+struct GroupEq {
+  float rF;    // rho F_k
+  float invT;  // 1/T
+  float g;     // 1 - u^2/2T
+  float base;  // 1 - u^2/2T + u^4/8T^2
+};
+
+__device__ __forceinline__ void site_init(Site& s, float rho, float ux, float uy, float T) {
   s.rho = rho;
   s.ux = ux;
   s.uy = uy;
-  s.invT = 1.0f / T;
-  const float u2 = ux * ux + uy * uy;
-  s.g = 1.0f - 0.5f * u2 * s.invT;
-  s.base = s.g + 0.125f * u2 * u2 * s.invT * s.invT;
-  weights(T, s.F0, s.F1, s.F2, s.F3, s.F4);
+  s.T = T;
   s.s0 = s.sx = s.sy = s.cc = 0.0f;
 }
 
 // Force coefficients A, B, C + C_q (Eqs. (20)-(23)) folded into the polynomial in v.
-__device__ __forceinline__ void site_force(Site& s, float T, float Bx, float By, float cc) {
-  const float A = -2.0f * cc * T;
+__device__ __forceinline__ void site_force(Site& s, float Bx, float By, float cc) {
+  const float A = -2.0f * cc * s.T;
   const float u2 = s.ux * s.ux + s.uy * s.uy;
   s.s0 = A - (Bx * s.ux + By * s.uy) + cc * u2;
   s.sx = Bx - 2.0f * cc * s.ux;
@@ -112,19 +114,29 @@ __device__ __forceinline__ void site_force(Site& s, float T, float Bx, float By,
   s.cc = cc;
 }
 
-__device__ __forceinline__ float group_weight(const Site& s, int k) {
-  return k == 0 ? s.F1 : (k == 1 ? s.F2 : (k == 2 ? s.F3 : s.F4));
+__device__ __forceinline__ GroupEq group_eq(const Site& s, float Fk) {
+  GroupEq e;
+  e.invT = 1.0f / s.T;
+  const float u2 = s.ux * s.ux + s.uy * s.uy;
+  e.g = 1.0f - 0.5f * u2 * e.invT;
+  e.base = e.g + 0.125f * u2 * u2 * e.invT * e.invT;
+  e.rF = s.rho * Fk;
+  return e;
 }
 
-// Eq. (3) for a moving population with velocity (vx, vy) and group weight Fk.
-__device__ __forceinline__ float feq_moving(const Site& s, float Fk, float vx, float vy) {
-  const float w = (vx * s.ux + vy * s.uy) * s.invT;
-  const float poly = s.base + s.g * (w + 0.5f * w * w) + w * w * w * (1.0f / 6.0f) +
+// Eq. (3) for a moving population with velocity (vx, vy).
+__device__ __forceinline__ float feq_moving(const Site& s, const GroupEq& e, float vx, float vy) {
+  const float w = (vx * s.ux + vy * s.uy) * e.invT;
+  const float poly = e.base + e.g * (w + 0.5f * w * w) + w * w * w * (1.0f / 6.0f) +
                      w * w * w * w * (1.0f / 24.0f);
-  return s.rho * Fk * poly;
+  return e.rF * poly;
 }
 
-__device__ __forceinline__ float feq_rest(const Site& s) { return s.rho * s.F0 * s.base; }
+// Eq. (3) for the rest particle (v = 0).
+__device__ __forceinline__ float feq_rest(const Site& s) {
+  const GroupEq e = group_eq(s, rest_weight(s.T));
+  return e.rF * e.base;
+}
 
 // f^{n+1} = f - dt C - omega (f - feq) + dt I with I = -(s0 + sx vx + sy vy + cc |v|^2) feq.
 // The increment is formed first and added once: f is rounded to FP32 a single time and

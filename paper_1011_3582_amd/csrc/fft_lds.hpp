@@ -1,7 +1,7 @@
 // In-LDS Stockham FFTs for gfx950, used by every kernel of the solver.
 //
-// A transform of length N (a power of two) is a sequence of radix-16 passes, preceded
-// by one radix-2, -4 or -8 pass when log2 N is not a multiple of 4.  Each pass reads
+// A transform of length N (a power of two) is a sequence of radix-16 (or radix-8) passes,
+// preceded by one smaller-radix pass when log2 N is not a multiple of 4 (or 3).  Each pass reads
 // its butterfly inputs from LDS into registers, waits at a barrier, multiplies by the
 // twiddles, does the butterfly in registers and writes the outputs back in place
 // (Stockham autosort: natural order in, natural order out).  With radix 16 a 1024-point
@@ -179,21 +179,21 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
   __syncthreads();
 }
 
-// Radix of the pass with span P: the remainder pass (2, 4 or 8) first, radix 16 after.
-template <int N, int P>
+// Radix of the pass with span P: the remainder pass first, radix MAXR (8 or 16) after.
+template <int N, int P, int MAXR>
 constexpr int pass_radix() {
-  constexpr int l = ilog2(N);
-  if (P == 1 && (l % 4) != 0) return 1 << (l % 4);
-  return 16;
+  constexpr int l = ilog2(N), m = ilog2(MAXR);
+  if (P == 1 && (l % m) != 0) return 1 << (l % m);
+  return MAXR;
 }
 
-template <int N, int P, int DIR, int NTH, int NB, bool TFAST>
+template <int N, int P, int DIR, int NTH, int NB, bool TFAST, int MAXR>
 __device__ __forceinline__ void fft_passes(float2* lds, int off, int st, int si, const float2* __restrict__ tw,
                                            int tid) {
   if constexpr (P < N) {
-    constexpr int R = pass_radix<N, P>();
+    constexpr int R = pass_radix<N, P, MAXR>();
     stockham_pass<N, R, P, DIR, NTH, NB, TFAST>(lds, off, st, si, tw, tid);
-    fft_passes<N, P * R, DIR, NTH, NB, TFAST>(lds, off, st, si, tw, tid);
+    fft_passes<N, P * R, DIR, NTH, NB, TFAST, MAXR>(lds, off, st, si, tw, tid);
   }
 }
 
@@ -201,11 +201,12 @@ __device__ __forceinline__ void fft_passes(float2* lds, int off, int st, int si,
 // lds[swz(off + t * st + i * si)] (the swizzle is applied to the whole index, so `off`
 // must be passed here rather than folded into the pointer).  Callers must have a barrier
 // between their last write of the data and this call; the call ends with a barrier.
-template <int N, int DIR, int NTH, int NB, bool TFAST>
+template <int N, int DIR, int NTH, int NB, bool TFAST, int MAXR = 16>
 __device__ __forceinline__ void fft_lds(float2* lds, int off, int st, int si, const float2* __restrict__ tw,
                                         int tid) {
   static_assert((N & (N - 1)) == 0 && N >= 2, "power-of-two length");
-  fft_passes<N, 1, DIR, NTH, NB, TFAST>(lds, off, st, si, tw, tid);
+  static_assert(MAXR == 8 || MAXR == 16, "radix");
+  fft_passes<N, 1, DIR, NTH, NB, TFAST, MAXR>(lds, off, st, si, tw, tid);
 }
 
 }  // namespace fftlb

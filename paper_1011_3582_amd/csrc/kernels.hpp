@@ -31,16 +31,18 @@ namespace fftlb {
 constexpr int lds_alloc(int n) { return (n + 31) / 32 * 32; }
 
 // Row-kernel geometry.  Each thread owns J sites of its row (J = 2, or 4 for 2048-point
-// rows), a block holds RB rows (at least 64 threads), and row transforms are done NPB
-// plane pairs at a time: a batch is NPB * RB complex transforms of length NX, so with
-// radix-16 passes each thread does one 16-point butterfly per pass (NPB = 16 / J).
+// rows), a block holds RB rows (at least 64 threads), and row transforms are done four
+// plane pairs at a time: a batch is 4 RB complex transforms of length NX, i.e. 4 J values
+// per thread, so each pass is one butterfly of radix RADIX = 4 J per thread.  Radix 8
+// (rather than 16) keeps the transform's registers small enough for two blocks per CU.
 template <int NX>
 struct RowGeom {
   static constexpr int J = NX >= 2048 ? 4 : 2;
   static constexpr int TPR = NX / J;
   static constexpr int RB = (TPR >= 64) ? 1 : 64 / TPR;
   static constexpr int NT = RB * TPR;
-  static constexpr int NPB = 16 / J;
+  static constexpr int NPB = 4;
+  static constexpr int RADIX = 4 * J;
   static constexpr int LDS = lds_alloc(NPB * RB * NX);  // float2 elements (<= 64 KB)
 };
 
@@ -191,7 +193,7 @@ __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<
                                                    const float2* twx, int row0, int tid) {
   rows_load_batch<NX, NP>(lds, in, sg, row0, tid);
   __syncthreads();
-  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false>(lds, 0, NX, 1, twx, tid);
+  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, RowGeom<NX>::RADIX>(lds, 0, NX, 1, twx, tid);
 }
 
 // Forward row transforms of slots already written (unsynchronised) and store of the packed
@@ -200,7 +202,7 @@ template <int NX, int NP>
 __device__ __forceinline__ void rows_forward_batch(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
                                                    const float2* twx, int row0, int tid) {
   __syncthreads();
-  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false>(lds, 0, NX, 1, twx, tid);
+  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, RowGeom<NX>::RADIX>(lds, 0, NX, 1, twx, tid);
   rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
   __syncthreads();
 }
@@ -598,6 +600,8 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
           bad |= nonfinite(fa) | nonfinite(fb);
           lds[li] = make_float2(fa, fb);
         }
+        // keep one pair's loads in flight at a time: bounds the live registers
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     rows_forward_batch<NX, G::NPB>(lds, io, P.sg, P.twx, row0, tid);

@@ -71,7 +71,7 @@ typedef struct fftlb_config {
 
 typedef struct fftlb_handle fftlb_handle;
 
-/* Bytes of device workspace fftlb_init needs for `cfg` (about 94 * nx * ny * 4 bytes).
+/* Bytes of device workspace fftlb_init needs for `cfg` (about 88 * nx * ny * 4 bytes).
  * Returns FFTLB_EINVAL for an unsupported configuration. */
 int fftlb_workspace_bytes(const fftlb_config* cfg, size_t* bytes);
 

@@ -83,7 +83,7 @@ Layout make_layout(int nx, int ny) {
   L.f = take(33 * plane);
   L.sf = take(32 * plane);
   L.sm = take(4 * plane);
-  L.s1 = take(11 * plane);
+  L.s1 = take(6 * plane);
   L.s2i = take(5 * plane);
   L.s2o = take(3 * plane);
   L.macro = take(4 * plane);
@@ -128,7 +128,8 @@ struct fftlb_handle {
   float* kapy;
   int nblk_rows;
   int64_t steps;
-  hipStream_t cap;
+  hipStream_t cap, cap2;   // capture streams (the second carries the concurrent branch)
+  hipEvent_t fork, join;
   hipGraphExec_t g1, gN;
 };
 
@@ -179,7 +180,7 @@ struct ColConv {
       return FFTLB_EINVAL;
     } else {
       constexpr int NT = col_threads(NY, CW);
-      const int nblocks = 32 * ((h->nx / 2) / CW);
+      const int nblocks = 24 * ((h->nx / 2) / CW);   // 24 populations with v_y != 0
       hipLaunchKernelGGL((k_col_conv<NY, CW, NT>), dim3(nblocks), dim3(NT), lds_alloc(NY * CW) * sizeof(float2), s,
                          h->P.sf, h->twy, h->kapx, h->kapy, h->nx, h->tw, h->M.scale);
       return FFTLB_OK;
@@ -266,7 +267,7 @@ template <int NX>
 struct RowInvReal {
   static int run(hipStream_t s, fftlb_handle* h, const float2* sa, const float2* sb, float* a, float* b) {
     hipLaunchKernelGGL(k_rows_inverse_real<NX>, dim3(h->nblk_rows), dim3(RowGeom<NX>::NT),
-                       RowGeom<NX>::LDS * sizeof(float2), s, sa, sb, a, b, h->P.sg, h->P.twx, h->nx);
+                       RowGeom<NX>::LDS * sizeof(float2), s, sa, sb, a, b, h->P.sg, h->P.twx, h->P.kapx, h->nx);
     return FFTLB_OK;
   }
 };
@@ -298,15 +299,15 @@ int launch_stage1(fftlb_handle* h, hipStream_t s) {
   float2* sm = h->P.sm;
   float2* s1 = h->P.s1;
   ColLaunch L{};
-  // rho -> D_x rho, D_y rho, lap rho
-  L.g[0] = group({sm}, {s1, s1 + hp, s1 + 2 * hp}, {{MK_IKX}, {MK_IKY}, {MK_LAP}});
-  // ux, uy -> D_x ux, D_y ux, D_x uy, D_y uy, D_x theta, D_y theta
-  L.g[1] = group({sm + hp, sm + 2 * hp},
-                 {s1 + 3 * hp, s1 + 4 * hp, s1 + 5 * hp, s1 + 6 * hp, s1 + 7 * hp, s1 + 8 * hp},
-                 {{MK_IKX, MK_NONE}, {MK_IKY, MK_NONE}, {MK_NONE, MK_IKX}, {MK_NONE, MK_IKY},
-                  {MK_KXX, MK_KXY}, {MK_KXY, MK_KYY}});
-  // T -> D_x T, D_y T
-  L.g[2] = group({sm + 3 * hp}, {s1 + 9 * hp, s1 + 10 * hp}, {{MK_IKX}, {MK_IKY}});
+  // Only the y-derivatives need the column pass; x-derivatives are formed in the stage-2
+  // row kernel from the moment spectra.  s1 = [D_y rho, D_yy rho, D_y ux, D_y uy, D_y theta, D_y T]
+  // rho -> D_y rho, D_yy rho
+  L.g[0] = group({sm}, {s1, s1 + hp}, {{MK_IKY}, {MK_KYY}});
+  // ux, uy -> D_y ux, D_y uy, D_y theta = D_y D_x ux + D_yy uy
+  L.g[1] = group({sm + hp, sm + 2 * hp}, {s1 + 2 * hp, s1 + 3 * hp, s1 + 4 * hp},
+                 {{MK_IKY, MK_NONE}, {MK_NONE, MK_IKY}, {MK_KXY, MK_KYY}});
+  // T -> D_y T
+  L.g[2] = group({sm + 3 * hp}, {s1 + 5 * hp}, {{MK_IKY}});
   return dispatch_ny<ColMulti>(h->ny, multi_cols(h->ny, h->tw), s, h, L, 3, 2);
 }
 
@@ -346,11 +347,26 @@ int enqueue_step(fftlb_handle* h, hipStream_t s) {
   return FFTLB_OK;
 }
 
+// The step as captured into a graph: the convection column pass (stage 0) runs on a
+// second branch, concurrently with the force pipeline (stages 1-3); the collide
+// (stage 4) joins both.
+int enqueue_step_forked(fftlb_handle* h, hipStream_t s) {
+  int rc;
+  HIP_TRY(hipEventRecord(h->fork, s));
+  HIP_TRY(hipStreamWaitEvent(h->cap2, h->fork, 0));
+  if ((rc = enqueue_stage(h, 0, h->cap2))) return rc;
+  HIP_TRY(hipEventRecord(h->join, h->cap2));
+  for (int k = 1; k <= 3; ++k)
+    if ((rc = enqueue_stage(h, k, s))) return rc;
+  HIP_TRY(hipStreamWaitEvent(s, h->join, 0));
+  return enqueue_stage(h, 4, s);
+}
+
 int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
   int rc = FFTLB_OK;
-  for (int i = 0; i < nsteps && rc == FFTLB_OK; ++i) rc = enqueue_step(h, h->cap);
+  for (int i = 0; i < nsteps && rc == FFTLB_OK; ++i) rc = enqueue_step_forked(h, h->cap);
   hipError_t le = hipGetLastError();
   hipError_t ee = hipStreamEndCapture(h->cap, &graph);
   if (rc != FFTLB_OK) {
@@ -413,7 +429,8 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   h->L = L;
   h->steps = 0;
   h->g1 = h->gN = nullptr;
-  h->cap = nullptr;
+  h->cap = h->cap2 = nullptr;
+  h->fork = h->join = nullptr;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return FFTLB_EHIP;
@@ -429,6 +446,7 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   P.macro = reinterpret_cast<float*>(ws + L.macro);
   P.cpl = reinterpret_cast<float*>(ws + L.cpl);
   P.twx = reinterpret_cast<const float2*>(ws + L.twx);
+  P.kapx = reinterpret_cast<const float*>(ws + L.kx);
   P.part_d = reinterpret_cast<double*>(ws + L.pd);
   P.part_f = reinterpret_cast<float*>(ws + L.pf);
   P.in0 = P.in1 = P.in2 = P.in3 = nullptr;
@@ -470,11 +488,18 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
     DeviceGuard dg(h->device);
     auto fail = [&](int code) {
       if (h->cap) (void)hipStreamDestroy(h->cap);
+      if (h->cap2) (void)hipStreamDestroy(h->cap2);
+      if (h->fork) (void)hipEventDestroy(h->fork);
+      if (h->join) (void)hipEventDestroy(h->join);
       delete h;
       return code;
     };
-    if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
-      set_error("hipStreamCreateWithFlags", hipErrorUnknown);
+    // default-priority streams; events without timing
+    if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->cap2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess) {
+      set_error("stream/event creation", hipErrorUnknown);
       return fail(FFTLB_EHIP);
     }
     hipError_t e;
@@ -583,6 +608,7 @@ int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, vo
   int rc;
   if ((rc = dispatch_nx<RowFwdReal>(h->nx, s, h, g, (const float*)nullptr, src, (float2*)nullptr))) return rc;
   ColLaunch L{};
+  // the derivative entry point runs every operator through the full 2D pass
   const int kind = op == 0 ? MK_IKX : (op == 1 ? MK_IKY : MK_LAP);
   L.g[0] = group({src}, {dst}, {{kind}});
   if ((rc = dispatch_ny<ColMulti>(h->ny, multi_cols(h->ny, h->tw), s, h, L, 1, 1))) return rc;
@@ -600,6 +626,9 @@ int fftlb_destroy(fftlb_handle* h) {
     if (h->g1) (void)hipGraphExecDestroy(h->g1);
     if (h->gN) (void)hipGraphExecDestroy(h->gN);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->cap2) (void)hipStreamDestroy(h->cap2);
+    if (h->fork) (void)hipEventDestroy(h->fork);
+    if (h->join) (void)hipEventDestroy(h->join);
   }
   delete h;
   return FFTLB_OK;

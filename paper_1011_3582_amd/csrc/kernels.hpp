@@ -66,6 +66,7 @@ struct Planes {
   float* macro;      // [4][ny][nx] rho, ux, uy, T (real)
   float* cpl;        // [ny][nx] coefficient C of Eq. (22)
   const float2* twx; // row twiddles, nx entries
+  const float* kapx; // windowed k_x, nx/2 entries
   double* part_d;    // [blocks][6] stage-2 partials: mass, px, py, energy, max|u|, nonfinite
   float* part_f;     // [blocks][2] collide partials: max |sum_q C_q|, nonfinite
   const float* in0;  // init: rho0, ux0, uy0, T0 / set: f
@@ -111,12 +112,45 @@ struct RowThread {
   }
 };
 
-// A batch of up to four plane pairs: pair p transforms planes (a[p], b[p]) as z = a + i b.
+// A batch of up to four plane pairs: pair p transforms z = a + i b.  Each of a and b is a
+// row-spectral linear combination of at most two stored spectra, term = c m(kx) S with
+//   m = 1 (TERM_ONE), i k_x (TERM_IKX) or -k_x^2 (TERM_KXX),
+// k_x the windowed wavenumber (zero at kx = 0 and at the Nyquist column packed with it).
+// A derivative along x alone never needs a column transform: it is a row-spectral product.
+enum : int { TERM_ONE = 0, TERM_IKX = 1, TERM_KXX = 2 };
+
 template <int NP>
 struct PairBatch {
-  const float2* a[NP];
-  const float2* b[NP];   // may be null
+  const float2* s[NP][2][2];  // [pair][a, b][term]; null = absent
+  float c[NP][2][2];
+  int kind[NP][2][2];
 };
+
+template <int NP>
+__device__ __forceinline__ PairBatch<NP> plain_batch(const float2* const (&a)[NP], const float2* const (&b)[NP]) {
+  PairBatch<NP> r;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    r.s[p][0][0] = a[p];
+    r.s[p][1][0] = b[p];
+    r.s[p][0][1] = r.s[p][1][1] = nullptr;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        r.c[p][h][t] = 1.0f;
+        r.kind[p][h][t] = TERM_ONE;
+      }
+  }
+  return r;
+}
+
+template <int NP>
+__device__ __forceinline__ void set_term(PairBatch<NP>& b, int p, int h, int t, const float2* s, float c, int kind) {
+  b.s[p][h][t] = s;
+  b.c[p][h][t] = c;
+  b.kind[p][h][t] = kind;
+}
 
 template <int NP>
 struct PairBatchOut {
@@ -124,24 +158,52 @@ struct PairBatchOut {
   float2* b[NP];         // may be null
 };
 
+// Value of one side of a pair at (row spectrum index gi, column k), k = 0 packed.
+template <int NP>
+__device__ __forceinline__ float2 combo_value(const PairBatch<NP>& in, int p, int h, int gi, int k, float kx) {
+  float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const float2* __restrict__ S = in.s[p][h][t];
+    if (!S) continue;
+    const float2 v = S[gi];
+    const float c = in.c[p][h][t];
+    const int kd = in.kind[p][h][t];
+    if (kd == TERM_ONE) {
+      acc.x += c * v.x;
+      acc.y += c * v.y;
+    } else if (k != 0) {   // both packed entries of column 0 have k_x = 0
+      if (kd == TERM_IKX) {
+        acc.x -= c * kx * v.y;
+        acc.y += c * kx * v.x;
+      } else {
+        const float m = -c * kx * kx;
+        acc.x += m * v.x;
+        acc.y += m * v.y;
+      }
+    }
+  }
+  return acc;
+}
+
 // LDS slot p <- Z(k) = A(k) + i B(k), k = 0..NX-1, for every row of the block, from the
-// packed half spectra of planes a[p], b[p]; Hermitian completion of the upper half.
+// packed half spectra described by `in`; Hermitian completion of the upper half.
+// kapx (nx/2 windowed k_x values) must always be a valid table.
 template <int NX, int NP>
 __device__ __forceinline__ void rows_load_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
-                                                int row0, int tid) {
+                                                const float* __restrict__ kapx, int row0, int tid) {
   constexpr int H = NX / 2;
   constexpr int RB = RowGeom<NX>::RB;
   constexpr int NT = RowGeom<NX>::NT;
   tid = opaque(tid);
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    const float2* __restrict__ A = in.a[p];
-    const float2* __restrict__ B = in.b[p];
     for (int e = tid; e < RB * H; e += NT) {
       const int rl = e / H, k = e % H;
       const int gi = sg.idx(row0 + rl, k);
-      const float2 a = A[gi];
-      const float2 b = B ? B[gi] : make_float2(0.0f, 0.0f);
+      const float kx = kapx[k];
+      const float2 a = combo_value(in, p, 0, gi, k, kx);
+      const float2 b = combo_value(in, p, 1, gi, k, kx);
       const int z = (p * RB + rl) * NX;
       if (k == 0) {
         lds[swz(z)] = make_float2(a.x, b.x);
@@ -151,6 +213,7 @@ __device__ __forceinline__ void rows_load_batch(float2* lds, const PairBatch<NP>
         lds[swz(z + NX - k)] = make_float2(a.x + b.y, b.x - a.y);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -190,8 +253,8 @@ __device__ __forceinline__ void rows_store_batch(const float2* lds, const PairBa
 // Inverse row transforms of a batch; afterwards slot p holds a_p(x) + i b_p(x).
 template <int NX, int NP>
 __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
-                                                   const float2* twx, int row0, int tid) {
-  rows_load_batch<NX, NP>(lds, in, sg, row0, tid);
+                                                   const float2* twx, const float* kapx, int row0, int tid) {
+  rows_load_batch<NX, NP>(lds, in, sg, kapx, row0, tid);
   __syncthreads();
   fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, RowGeom<NX>::RADIX>(lds, 0, NX, 1, twx, tid);
 }
@@ -218,8 +281,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return (b % 8) * (nblocks / 8) + b / 8;
 }
 
-// Convection: for each of the 32 moving populations, column FFT, multiply by
-// i (v_x k_m(kx) + v_y k_m(ky)) * scale, inverse column FFT, in place.
+// Convection: for each of the 24 moving populations with v_y != 0 (directions i != 1, 5),
+// column FFT, multiply by i (v_x k_m(kx) + v_y k_m(ky)) * scale, inverse column FFT, in
+// place.  The 8 populations moving along +-x need no column transform (see k_rows_collide).
+__device__ __forceinline__ int conv_column_plane(int j) {
+  // j = 0..23 -> population q - 1 = 8 k + i - 1 with i - 1 in {1, 2, 3, 5, 6, 7}
+  const int k = j / 6, r = j % 6;
+  return 8 * k + (r < 3 ? r + 1 : r + 2);
+}
+
 template <int NY, int CW, int NT>
 __global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, const float2* __restrict__ twy,
                                                  const float* __restrict__ kapx,
@@ -228,7 +298,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, c
   const int tid = threadIdx.x;
   const int nsub = (nx / 2) / CW;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int p = b / nsub, sub = b % nsub;
+  const int p = conv_column_plane(b / nsub), sub = b % nsub;
   const int c0 = sub * CW;
   float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
   for (int e = tid; e < NY * CW; e += NT) {
@@ -357,36 +427,56 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model
     uy[j] = P.macro[2 * P.plane + s];
     T[j] = P.macro[3 * P.plane + s];
   }
-  // the 11 stage-1 derivatives: rx, ry, lap, dxux, dyux, dxuy, dyuy, thx, thy, Tx, Ty
+  // The 11 stage-1 derivatives d = rx, ry, lap, dxux, dyux, dxuy, dyuy, thx, thy, Tx, Ty.
+  // x-derivatives are row-spectral products of the moment spectra R, Ux, Uy, Th (scaled by
+  // 1/nx for the unnormalised inverse row transform); the column pass supplied
+  // s1 = [D_y rho, D_yy rho, D_y ux, D_y uy, D_y theta, D_y T], already normalised.
   float d[11][J];
-  if constexpr (G::NPB >= 6) {
-    PairBatch<6> b{{P.s1, P.s1 + 2 * hp, P.s1 + 4 * hp, P.s1 + 6 * hp, P.s1 + 8 * hp, P.s1 + 10 * hp},
-                   {P.s1 + hp, P.s1 + 3 * hp, P.s1 + 5 * hp, P.s1 + 7 * hp, P.s1 + 9 * hp, nullptr}};
-    rows_inverse_batch<NX, 6>(lds, b, P.sg, P.twx, row0, tid);
+  {
+    const float inx = 1.0f / P.nx;
+    const float2 *R = P.sm, *Ux = P.sm + hp, *Uy = P.sm + 2 * hp, *Th = P.sm + 3 * hp;
+    const float2* s1 = P.s1;
+    PairBatch<4> b;
+    {
+      const float2* a[4] = {nullptr, nullptr, nullptr, nullptr};
+      b = plain_batch<4>(a, a);
+    }
+    set_term(b, 0, 0, 0, R, inx, TERM_IKX);                 // rx
+    set_term(b, 0, 1, 0, s1, 1.0f, TERM_ONE);               // ry
+    set_term(b, 1, 0, 0, R, inx, TERM_KXX);                 // lap = D_xx rho + D_yy rho
+    set_term(b, 1, 0, 1, s1 + hp, 1.0f, TERM_ONE);
+    set_term(b, 1, 1, 0, Ux, inx, TERM_IKX);                // dxux
+    set_term(b, 2, 0, 0, s1 + 2 * hp, 1.0f, TERM_ONE);      // dyux
+    set_term(b, 2, 1, 0, Ux, inx, TERM_KXX);                // thx = D_x(D_x ux + D_y uy)
+    set_term(b, 2, 1, 1, s1 + 3 * hp, 1.0f, TERM_IKX);
+    set_term(b, 3, 0, 0, Uy, inx, TERM_IKX);                // dxuy
+    set_term(b, 3, 1, 0, s1 + 3 * hp, 1.0f, TERM_ONE);      // dyuy
+    rows_inverse_batch<NX, 4>(lds, b, P.sg, P.twx, P.kapx, row0, tid);
 #pragma unroll
-    for (int p = 0; p < 6; ++p)
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const float2 v = lds[rt.at(p, j)];
-        d[2 * p][j] = v.x;
-        if (2 * p + 1 < 11) d[2 * p + 1][j] = v.y;
-      }
+    for (int j = 0; j < J; ++j) {
+      float2 v = lds[rt.at(0, j)];
+      d[0][j] = v.x;
+      d[1][j] = v.y;
+      v = lds[rt.at(1, j)];
+      d[2][j] = v.x;
+      d[3][j] = v.y;
+      v = lds[rt.at(2, j)];
+      d[4][j] = v.x;
+      d[7][j] = v.y;
+      v = lds[rt.at(3, j)];
+      d[5][j] = v.x;
+      d[6][j] = v.y;
+    }
     __syncthreads();
-  } else {
-    PairBatch<4> b1{{P.s1, P.s1 + 2 * hp, P.s1 + 4 * hp, P.s1 + 6 * hp},
-                    {P.s1 + hp, P.s1 + 3 * hp, P.s1 + 5 * hp, P.s1 + 7 * hp}};
-    rows_inverse_batch<NX, 4>(lds, b1, P.sg, P.twx, row0, tid);
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const float2 v = lds[rt.at(p, j)];
-        d[2 * p][j] = v.x;
-        d[2 * p + 1][j] = v.y;
-      }
-    __syncthreads();
-    PairBatch<2> b2{{P.s1 + 8 * hp, P.s1 + 10 * hp}, {P.s1 + 9 * hp, nullptr}};
-    rows_inverse_batch<NX, 2>(lds, b2, P.sg, P.twx, row0, tid);
+    PairBatch<2> b2;
+    {
+      const float2* a[2] = {nullptr, nullptr};
+      b2 = plain_batch<2>(a, a);
+    }
+    set_term(b2, 0, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);     // thy
+    set_term(b2, 0, 1, 0, Th, inx, TERM_IKX);               // Tx
+    set_term(b2, 1, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);     // Ty
+    rows_inverse_batch<NX, 2>(lds, b2, P.sg, P.twx, P.kapx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const float2 v = lds[rt.at(0, j)];
@@ -489,8 +579,9 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
 
   Site st[J];
   if constexpr (MODE == MODE_STEP) {
-    PairBatch<2> b{{P.s2o, P.s2o + 2 * hp}, {P.s2o + hp, nullptr}};
-    rows_inverse_batch<NX, 2>(lds, b, P.sg, P.twx, row0, tid);
+    const float2* a2[2] = {P.s2o, P.s2o + 2 * hp};
+    const float2* b2[2] = {P.s2o + hp, nullptr};
+    rows_inverse_batch<NX, 2>(lds, plain_batch<2>(a2, b2), P.sg, P.twx, P.kapx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const long s = rowoff + rt.x(j);
@@ -545,13 +636,23 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
       io.b[p] = S + (2 * p + 1) * hp;
     }
     if constexpr (MODE == MODE_STEP) {
-      PairBatch<G::NPB> in;
+      const float2* ia[G::NPB];
+      const float2* ib[G::NPB];
 #pragma unroll
       for (int p = 0; p < G::NPB; ++p) {
-        in.a[p] = io.a[p];
-        in.b[p] = io.b[p];
+        ia[p] = io.a[p];
+        ib[p] = io.b[p];
       }
-      rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, P.twx, row0, tid);
+      PairBatch<G::NPB> in = plain_batch<G::NPB>(ia, ib);
+      // directions i = 1 and 5 (v along +-x) skip the column pass: their convection term
+      // v_x D_x f is the row-spectral product i v_x k_x S / nx
+#pragma unroll
+      for (int g = 0; g < GPR; ++g) {
+        const int qx0 = q0 + 8 * g, qx4 = qx0 + 4;
+        set_term(in, 4 * g + 0, 0, 0, io.a[4 * g + 0], c_vel.vx[qx0] / P.nx, TERM_IKX);
+        set_term(in, 4 * g + 2, 0, 0, io.a[4 * g + 2], c_vel.vx[qx4] / P.nx, TERM_IKX);
+      }
+      rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, P.twx, P.kapx, row0, tid);
     }
 #pragma unroll
     for (int g = 0; g < GPR; ++g) {
@@ -673,13 +774,14 @@ template <int NX>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_inverse_real(const float2* sa, const float2* sb,
                                                                        float* __restrict__ a, float* __restrict__ b,
                                                                        SpecGeom sg, const float2* __restrict__ twx,
-                                                                       int nx) {
+                                                                       const float* __restrict__ kapx, int nx) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
   const long rowoff = (long)rt.y * nx;
-  PairBatch<1> in{{sa}, {sb}};
-  rows_inverse_batch<NX, 1>(lds, in, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
+  const float2* a1[1] = {sa};
+  const float2* b1[1] = {sb};
+  rows_inverse_batch<NX, 1>(lds, plain_batch<1>(a1, b1), sg, twx, kapx, blockIdx.x * RowGeom<NX>::RB, tid);
 #pragma unroll
   for (int j = 0; j < RowGeom<NX>::J; ++j) {
     const long s = rowoff + rt.x(j);

@@ -27,8 +27,8 @@ def test_config_struct_matches_header_layout():
 @pytest.mark.parametrize("nx,ny", [(64, 64), (1024, 1024), (512, 4), (8, 32), (2048, 16)])
 def test_workspace_bytes_valid(nx, ny):
     b = F.workspace_bytes(nx, ny)
-    # 93 float planes of nx*ny plus small tables and partials
-    assert 93 * nx * ny * 4 <= b <= 93 * nx * ny * 4 + 64 * 1024 + 64 * ny
+    # 88 float planes of nx*ny plus small tables and partials
+    assert 88 * nx * ny * 4 <= b <= 88 * nx * ny * 4 + 64 * 1024 + 64 * ny
 
 
 @pytest.mark.parametrize("change", [

@@ -7,11 +7,13 @@
 // (Stockham autosort: natural order in, natural order out).  With radix 16 a 1024-point
 // transform takes three passes, and a thread holds 16 complex values per pass.
 //
-// Layout: element i of transform t lives at lds[swz(t * st + i * si)], where swz() XORs
-// the low five index bits with the next five: a bijection inside every aligned block of
-// 32 elements that spreads the strided stores of the first passes over the LDS banks
-// (two 64-bit accesses per bank row at worst) without enlarging the buffer.  With TFAST the consecutive threads of a block walk
-// consecutive transforms (column kernels, transforms interleaved with stride 1);
+// Layout: element i of transform t lives at lds[pad(off + t * st + i * SI)], where pad()
+// inserts one empty slot after every 32 elements so that the strided accesses of the
+// passes spread over the LDS banks.  When the caller's layout keeps off + t * st a
+// multiple of 32 (ALIGNED), the 2R accesses of a butterfly are one runtime base address
+// plus compile-time offsets, which the hardware takes as immediate offsets: the address
+// arithmetic does not grow with the radix.  With TFAST the consecutive threads of a block
+// walk consecutive transforms (column kernels, transforms interleaved with stride SI);
 // otherwise consecutive butterflies of one transform (row kernels, contiguous transforms).
 //
 // Twiddles come from a table tw[j] = exp(-2 pi i j / N) computed in FP64 on the host.
@@ -33,8 +35,9 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// Bank swizzle of an LDS element index (see the file comment).
-__device__ __forceinline__ int swz(int e) { return e ^ ((e >> 5) & 31); }
+// Padded LDS element index (see the file comment) and the padded size of n elements.
+__host__ __device__ constexpr int pad(int e) { return e + (e >> 5); }
+__host__ __device__ constexpr int padded_size(int n) { return n + (n >> 5) + 1; }
 
 // Returns v unchanged but opaque to the optimiser.  Index arithmetic derived from the
 // result is recomputed where it is used instead of being hoisted out of loops and kept
@@ -134,8 +137,13 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restri
 
 // One Stockham pass of radix R over NB transforms of length N, span P (product of the
 // radices of the passes before it), executed by NTH threads.
-template <int N, int R, int P, int DIR, int NTH, int NB, bool TFAST>
-__device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off, int st, int si,
+//
+// Offsets.  With the base index B = off + t st + (i or j0) SI a multiple-of-32 apart from
+// a value below the butterfly's span, pad(B + o_r) = pad(B) + pad(o_r) for the load
+// offsets o_r = r (N/R) SI and the store offsets o_r = r P SI (N, R, P, SI powers of two),
+// so pad(o_r) is a compile-time constant.
+template <int N, int R, int P, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED>
+__device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off, int st,
                                               const float2* __restrict__ tw, int tid) {
   constexpr int NBF = N / R;               // butterflies per transform
   constexpr int TOT = NBF * NB;            // butterflies per pass
@@ -158,8 +166,14 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
     base[s] = off + t * st;
     idx[s] = i;
     if (EXACT || b < TOT) {
+      if constexpr (ALIGNED) {
+        const float2* src = lds + pad(base[s] + i * SI);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[s][r] = lds[swz(base[s] + (i + r * NBF) * si)];
+        for (int r = 0; r < R; ++r) v[s][r] = src[pad(r * NBF * SI)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[s][r] = lds[pad(base[s] + (i + r * NBF) * SI)];
+      }
     }
   }
   __syncthreads();
@@ -172,8 +186,14 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
       if constexpr (P > 1) apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
       dft<R, DIR>(v[s]);
       const int j0 = (i - k) * R + k;
+      if constexpr (ALIGNED) {
+        float2* dst = lds + pad(base[s] + j0 * SI);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[swz(base[s] + (j0 + r * P) * si)] = v[s][out_slot<R>(r)];
+        for (int r = 0; r < R; ++r) dst[pad(r * P * SI)] = v[s][out_slot<R>(r)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[pad(base[s] + (j0 + r * P) * SI)] = v[s][out_slot<R>(r)];
+      }
     }
   }
   __syncthreads();
@@ -187,26 +207,24 @@ constexpr int pass_radix() {
   return MAXR;
 }
 
-template <int N, int P, int DIR, int NTH, int NB, bool TFAST, int MAXR>
-__device__ __forceinline__ void fft_passes(float2* lds, int off, int st, int si, const float2* __restrict__ tw,
-                                           int tid) {
+template <int N, int P, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR>
+__device__ __forceinline__ void fft_passes(float2* lds, int off, int st, const float2* __restrict__ tw, int tid) {
   if constexpr (P < N) {
     constexpr int R = pass_radix<N, P, MAXR>();
-    stockham_pass<N, R, P, DIR, NTH, NB, TFAST>(lds, off, st, si, tw, tid);
-    fft_passes<N, P * R, DIR, NTH, NB, TFAST, MAXR>(lds, off, st, si, tw, tid);
+    stockham_pass<N, R, P, DIR, NTH, NB, TFAST, SI, ALIGNED>(lds, off, st, tw, tid);
+    fft_passes<N, P * R, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR>(lds, off, st, tw, tid);
   }
 }
 
 // Full length-N transform of NB sequences in LDS; element i of transform t is at
-// lds[swz(off + t * st + i * si)] (the swizzle is applied to the whole index, so `off`
-// must be passed here rather than folded into the pointer).  Callers must have a barrier
-// between their last write of the data and this call; the call ends with a barrier.
-template <int N, int DIR, int NTH, int NB, bool TFAST, int MAXR = 16>
-__device__ __forceinline__ void fft_lds(float2* lds, int off, int st, int si, const float2* __restrict__ tw,
-                                        int tid) {
+// lds[pad(off + t * st + i * SI)].  ALIGNED asserts that off + t * st is always a multiple
+// of 32 (see stockham_pass).  Callers must have a barrier between their last write of the
+// data and this call; the call ends with a barrier.
+template <int N, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR = 16>
+__device__ __forceinline__ void fft_lds(float2* lds, int off, int st, const float2* __restrict__ tw, int tid) {
   static_assert((N & (N - 1)) == 0 && N >= 2, "power-of-two length");
   static_assert(MAXR == 8 || MAXR == 16, "radix");
-  fft_passes<N, 1, DIR, NTH, NB, TFAST, MAXR>(lds, off, st, si, tw, tid);
+  fft_passes<N, 1, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR>(lds, off, st, tw, tid);
 }
 
 }  // namespace fftlb

@@ -196,7 +196,8 @@ struct ColMulti {
     } else {
       constexpr int NT = col_threads(NY, CW);
       const int nsub = (h->nx / 2) / CW;
-      const size_t lds = (size_t)(lds_alloc(NY * CW * maxin) + lds_alloc(NY * CW)) * sizeof(float2);
+      (void)maxin;  // the work block sits after room for three inputs
+      const size_t lds = (size_t)lds_alloc(4 * NY * CW) * sizeof(float2);
       hipLaunchKernelGGL((k_col_multi<NY, CW, NT>), dim3(nsub, ngroups), dim3(NT), lds, s, L, h->twy, h->kapx,
                          h->kapy, h->nx, h->tw, h->M.scale);
       return FFTLB_OK;

@@ -27,8 +27,8 @@
 
 namespace fftlb {
 
-// LDS allocation (in float2) rounded up to whole 32-element swizzle blocks.
-constexpr int lds_alloc(int n) { return (n + 31) / 32 * 32; }
+// LDS allocation (in float2) of n padded elements (see fft_lds.hpp).
+constexpr int lds_alloc(int n) { return padded_size(n); }
 
 // Row-kernel geometry.  Each thread owns J sites of its row (J = 2, or 4 for 2048-point
 // rows), a block holds RB rows (at least 64 threads), and row transforms are done four
@@ -108,7 +108,7 @@ struct RowThread {
   __device__ __forceinline__ int x(int j) const { return lt + j * RowGeom<NX>::TPR; }
   // LDS element of site x(j) in batch slot `slot`
   __device__ __forceinline__ int at(int slot, int j) const {
-    return swz((slot * RowGeom<NX>::RB + rl) * NX + x(j));
+    return pad((slot * RowGeom<NX>::RB + rl) * NX + x(j));
   }
 };
 
@@ -206,11 +206,11 @@ __device__ __forceinline__ void rows_load_batch(float2* lds, const PairBatch<NP>
       const float2 b = combo_value(in, p, 1, gi, k, kx);
       const int z = (p * RB + rl) * NX;
       if (k == 0) {
-        lds[swz(z)] = make_float2(a.x, b.x);
-        lds[swz(z + H)] = make_float2(a.y, b.y);
+        lds[pad(z)] = make_float2(a.x, b.x);
+        lds[pad(z + H)] = make_float2(a.y, b.y);
       } else {
-        lds[swz(z + k)] = make_float2(a.x - b.y, a.y + b.x);
-        lds[swz(z + NX - k)] = make_float2(a.x + b.y, b.x - a.y);
+        lds[pad(z + k)] = make_float2(a.x - b.y, a.y + b.x);
+        lds[pad(z + NX - k)] = make_float2(a.x + b.y, b.x - a.y);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -232,14 +232,14 @@ __device__ __forceinline__ void rows_store_batch(const float2* lds, const PairBa
     for (int e = tid; e < RB * H; e += NT) {
       const int rl = e / H, k = e % H;
       const int z = (p * RB + rl) * NX;
-      const float2 Z = lds[swz(z + k)];
+      const float2 Z = lds[pad(z + k)];
       float2 A, B;
       if (k == 0) {
-        const float2 W = lds[swz(z + H)];
+        const float2 W = lds[pad(z + H)];
         A = make_float2(Z.x, W.x);
         B = make_float2(Z.y, W.y);
       } else {
-        const float2 W = lds[swz(z + NX - k)];
+        const float2 W = lds[pad(z + NX - k)];
         A = make_float2(0.5f * (Z.x + W.x), 0.5f * (Z.y - W.y));
         B = make_float2(0.5f * (Z.y + W.y), 0.5f * (W.x - Z.x));
       }
@@ -256,7 +256,7 @@ __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<
                                                    const float2* twx, const float* kapx, int row0, int tid) {
   rows_load_batch<NX, NP>(lds, in, sg, kapx, row0, tid);
   __syncthreads();
-  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, RowGeom<NX>::RADIX>(lds, 0, NX, 1, twx, tid);
+  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
 }
 
 // Forward row transforms of slots already written (unsynchronised) and store of the packed
@@ -265,7 +265,7 @@ template <int NX, int NP>
 __device__ __forceinline__ void rows_forward_batch(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
                                                    const float2* twx, int row0, int tid) {
   __syncthreads();
-  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, RowGeom<NX>::RADIX>(lds, 0, NX, 1, twx, tid);
+  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
   rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
   __syncthreads();
 }
@@ -303,22 +303,22 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, c
   float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
-    lds[swz(e)] = g[y * tw + c];
+    lds[pad(e)] = g[y * tw + c];
   }
   __syncthreads();
-  fft_lds<NY, -1, NT, CW, true>(lds, 0, 1, CW, twy, tid);
+  fft_lds<NY, -1, NT, CW, true, CW, (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
   const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
     const float m = (vx * kapx[c0 + c] + vy * kapy[y]) * scale;
-    const float2 v = lds[swz(e)];
-    lds[swz(e)] = make_float2(-m * v.y, m * v.x);
+    const float2 v = lds[pad(e)];
+    lds[pad(e)] = make_float2(-m * v.y, m * v.x);
   }
   __syncthreads();
-  fft_lds<NY, +1, NT, CW, true>(lds, 0, 1, CW, twy, tid);
+  fft_lds<NY, +1, NT, CW, true, CW, (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
-    g[y * tw + c] = lds[swz(e)];
+    g[y * tw + c] = lds[pad(e)];
   }
 }
 
@@ -355,30 +355,31 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* 
   const ColGroup& G = L.g[blockIdx.y];
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
   const long off = (long)(c0 / tw) * NY * tw + (c0 % tw);
-  const int W = G.nin * CW;  // LDS row width of the input block
+  constexpr int BLK = NY * CW;  // input p occupies elements [p BLK, (p + 1) BLK)
+  constexpr bool AL = (BLK % 32 == 0);
   for (int p = 0; p < G.nin; ++p) {
     const float2* g = G.in[p] + off;
-    for (int e = tid; e < NY * CW; e += NT) {
+    for (int e = tid; e < BLK; e += NT) {
       const int y = e / CW, c = e % CW;
-      lds[swz(y * W + p * CW + c)] = g[y * tw + c];
+      lds[pad(p * BLK + e)] = g[y * tw + c];
     }
   }
   __syncthreads();
-  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true>(lds, p * CW, 1, W, twy, tid);
-  float2* work = lds + lds_alloc(NY * W);
+  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true, CW, AL>(lds, p * BLK, 1, twy, tid);
+  const int wb = 3 * BLK;  // work block (after the largest input set)
   for (int o = 0; o < G.nout; ++o) {
-    for (int e = tid; e < NY * CW; e += NT) {
+    for (int e = tid; e < BLK; e += NT) {
       const int y = e / CW, c = e % CW;
       const float kx = kapx[c0 + c], ky = kapy[y];
       float re = 0.0f, im = 0.0f;
       for (int p = 0; p < G.nin; ++p) {
         const int kd = G.kind[o][p];
         if (kd == MK_NONE) continue;
-        const float2 v = lds[swz(y * W + p * CW + c)];
+        const float2 v = lds[pad(p * BLK + e)];
         if (kd == MK_IKX || kd == MK_IKY) {
-          const float k = kd == MK_IKX ? kx : ky;
-          re -= k * v.y;
-          im += k * v.x;
+          const float kk = kd == MK_IKX ? kx : ky;
+          re -= kk * v.y;
+          im += kk * v.x;
         } else {
           const float m = kd == MK_KXX ? -kx * kx
                         : kd == MK_KYY ? -ky * ky
@@ -388,14 +389,14 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* 
           im += m * v.y;
         }
       }
-      work[swz(e)] = make_float2(re * scale, im * scale);
+      lds[pad(wb + e)] = make_float2(re * scale, im * scale);
     }
     __syncthreads();
-    fft_lds<NY, +1, NT, CW, true>(work, 0, 1, CW, twy, tid);
+    fft_lds<NY, +1, NT, CW, true, CW, AL>(lds, wb, 1, twy, tid);
     float2* g = G.out[o] + off;
-    for (int e = tid; e < NY * CW; e += NT) {
+    for (int e = tid; e < BLK; e += NT) {
       const int y = e / CW, c = e % CW;
-      g[y * tw + c] = work[swz(e)];
+      g[y * tw + c] = lds[pad(wb + e)];
     }
     __syncthreads();
   }

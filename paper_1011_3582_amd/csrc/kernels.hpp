@@ -621,7 +621,6 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
     P.f[s] = fn;
     m0[j] = fn;
     mx[j] = my[j] = me[j] = rs[j] = 0.0f;
-    bad |= nonfinite(fn);
   }
   // moving populations: each round covers GPR speed groups (8 GPR populations, 4 GPR
   // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1)
@@ -699,7 +698,6 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
           mx[j] += vxa * fa + vxb * fb;
           my[j] += vya * fa + vyb * fb;
           me[j] += v2 * (fa + fb);
-          bad |= nonfinite(fa) | nonfinite(fb);
           lds[li] = make_float2(fa, fb);
         }
         // keep one pair's loads in flight at a time: bounds the live registers
@@ -722,6 +720,8 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
     P.macro[2 * P.plane + s] = uy;
     P.macro[3 * P.plane + s] = T;
     rmax = fmaxf(rmax, fabsf(rs[j]));
+    // a non-finite population anywhere in the sums makes a moment non-finite
+    bad |= nonfinite(r) | nonfinite(me[j]) | nonfinite(mx[j]) | nonfinite(my[j]);
     lds[rt.at(0, j)] = make_float2(r, ux);
     lds[rt.at(1, j)] = make_float2(uy, T);
   }

@@ -64,6 +64,42 @@ def measured_traffic(nx, ny):
     return rec.get("bytes_per_launch")
 
 
+def write_traffic(fetch_csv, write_csv, calib_mib, nx, ny):
+    """Turn two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
+    a run with --calib-copy-mib into the dominant kernel's HBM bytes per launch.  Each
+    counter is scaled by what it reads for the largest plain device copy of the same run
+    (calib_mib MiB read and written)."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals = {}
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] == counter:
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    want = f"{STAGE_KERNELS[DOMINANT]}<{nx}, 0>"
+    rec = {"source_hash": kernel_source_hash(), "nx": nx, "ny": ny, "kernel": want,
+           "calib_copy_kib": calib_mib * 1024}
+    total = 0.0
+    for key, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        vals = per_kernel(path, key)
+        copy = max(v for k, vs in vals.items() if "copyBuffer" in k for v in vs)
+        scale = calib_mib * 1024 / copy
+        mine = [v for k, vs in vals.items() if want in k for v in vs]
+        if not mine:
+            raise SystemExit(f"no dispatch of {want} in {path}")
+        kib = statistics.mean(mine)
+        rec[key] = {"kib_per_dispatch": kib, "dispatches": len(mine), "copy_kib": copy, "scale": scale}
+        total += kib * scale * 1024
+    rec["bytes_per_launch"] = total
+    rec["algorithmic_bytes_per_launch"] = STAGE_FLOATS_PER_SITE[DOMINANT] * 4 * nx * ny
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def cpu_baseline(fields, params, nx, ny):
     """FP64 oracle, as it stands, on one step of the same workload (single-threaded)."""
     import numpy as np
@@ -88,7 +124,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (traffic calibration under rocprofv3)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, args.calib_copy_mib or 1024, 1024, 1024)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)

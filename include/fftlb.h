@@ -51,7 +51,8 @@ extern "C" {
 /* Model and discretisation parameters (Sec. 2.2; the paper's values are listed in
  * its Sec. 3.5: dx = dy = 1/256, dt = 1e-5, tau = 1e-2, K = 1e-5, H = 0, zeta = 0,
  * q = -0.004, window k4; EOS a = 9/8, b = 1/3).
- *  nx, ny        grid size; each a power of two, 8 <= nx <= 2048, 4 <= ny <= 2048.
+ *  nx, ny        grid size; each a power of two (8 <= nx <= 2048, 4 <= ny <= 2048) or
+ *                3 * 2^p with 48 <= n <= 768; ny a multiple of max(1, 64 / (nx / 2)).
  *  dx, dy, dt    lattice spacings and time step, > 0.
  *  tau           BGK relaxation time, > 0; +inf switches the collision off.
  *  K, H          gradient coefficient M = K + H T of the pressure tensor (Eq. (19)), >= 0.

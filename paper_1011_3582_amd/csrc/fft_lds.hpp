@@ -1,7 +1,8 @@
 // In-LDS Stockham FFTs for gfx950, used by every kernel of the solver.
 //
-// A transform of length N (a power of two) is a sequence of radix-16 (or radix-8) passes,
-// preceded by one smaller-radix pass when log2 N is not a multiple of 4 (or 3).  Each pass reads
+// A transform of length N = 2^p or 3 * 2^p is a sequence of radix-16 (or radix-8) passes,
+// preceded by a radix-3 pass when 3 divides N and by one smaller power-of-two pass when
+// log2 of the power-of-two part is not a multiple of 4 (or 3).  Each pass reads
 // its butterfly inputs from LDS into registers, waits at a barrier, multiplies by the
 // twiddles, does the butterfly in registers and writes the outputs back in place
 // (Stockham autosort: natural order in, natural order out).  With radix 16 a 1024-point
@@ -34,6 +35,9 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
 }
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+// Transform lengths handled here: 2^p, or 3 * 2^p (one radix-3 pass first).
+constexpr bool fft_length_ok(int n) { return n >= 2 && (is_pow2(n) || (n % 3 == 0 && is_pow2(n / 3))); }
 
 // Padded LDS element index (see the file comment) and the padded size of n elements.
 __host__ __device__ constexpr int pad(int e) { return e + (e >> 5); }
@@ -65,6 +69,20 @@ __device__ __forceinline__ void dft2(float2& a, float2& b) {
   b = csub(t, b);
 }
 
+// 3-point DFT: y0 = a + b + c, y1,2 = a - (b + c)/2 -+ DIR-signed i (sqrt(3)/2)(b - c)
+template <int DIR>
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+  constexpr float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+  const float2 t1 = cadd(b, c);
+  const float2 t2 = make_float2(a.x - 0.5f * t1.x, a.y - 0.5f * t1.y);
+  const float2 d = csub(b, c);
+  // forward: y1 = t2 - i h d, y2 = t2 + i h d; inverse: the conjugate rotation
+  const float2 r = DIR < 0 ? make_float2(h * d.y, -h * d.x) : make_float2(-h * d.y, h * d.x);
+  a = cadd(a, t1);
+  b = cadd(t2, r);
+  c = csub(t2, r);
+}
+
 template <int DIR>
 __device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
   const float2 a = cadd(x0, x2), b = csub(x0, x2);
@@ -90,6 +108,8 @@ template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
   if constexpr (R == 2) {
     dft2<DIR>(v[0], v[1]);
+  } else if constexpr (R == 3) {
+    dft3<DIR>(v[0], v[1], v[2]);
   } else if constexpr (R == 4) {
     dft4<DIR>(v[0], v[1], v[2], v[3]);
   } else {
@@ -182,7 +202,7 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
     const int b = tid + s * NTH;
     if (EXACT || b < TOT) {
       const int i = idx[s];
-      const int k = i & (P - 1);
+      const int k = i % P;  // P is a compile-time constant (a shift and mask when a power of two)
       if constexpr (P > 1) apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
       dft<R, DIR>(v[s]);
       const int j0 = (i - k) * R + k;
@@ -199,11 +219,14 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
   __syncthreads();
 }
 
-// Radix of the pass with span P: the remainder pass first, radix MAXR (8 or 16) after.
+// Radix of the pass with span P: for N = 3 * 2^p a radix-3 pass first; then the remainder
+// pass of the power-of-two part, then radix MAXR (8 or 16).
 template <int N, int P, int MAXR>
 constexpr int pass_radix() {
-  constexpr int l = ilog2(N), m = ilog2(MAXR);
-  if (P == 1 && (l % m) != 0) return 1 << (l % m);
+  constexpr bool three = !is_pow2(N);
+  if (three && P == 1) return 3;
+  constexpr int l = ilog2(three ? N / 3 : N), m = ilog2(MAXR);
+  if (P == (three ? 3 : 1) && (l % m) != 0) return 1 << (l % m);
   return MAXR;
 }
 
@@ -222,8 +245,10 @@ __device__ __forceinline__ void fft_passes(float2* lds, int off, int st, const f
 // data and this call; the call ends with a barrier.
 template <int N, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR = 16>
 __device__ __forceinline__ void fft_lds(float2* lds, int off, int st, const float2* __restrict__ tw, int tid) {
-  static_assert((N & (N - 1)) == 0 && N >= 2, "power-of-two length");
+  static_assert(fft_length_ok(N), "length 2^p or 3 * 2^p");
   static_assert(MAXR == 8 || MAXR == 16, "radix");
+  // the compile-time offsets need power-of-two spans (see stockham_pass)
+  static_assert(!ALIGNED || is_pow2(N), "aligned offsets need a power-of-two length");
   fft_passes<N, 1, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR>(lds, off, st, tw, tid);
 }
 

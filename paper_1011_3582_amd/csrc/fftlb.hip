@@ -31,9 +31,12 @@ void set_error(const char* what, hipError_t e) {
     }                                                        \
   } while (0)
 
-bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
-
 constexpr int kMaxN = 2048;
+
+// Grid sizes with compiled kernels: powers of two, and 3 * 2^p from 48 to 768.
+bool size_supported(int n) { return is_pow2(n) || (n % 3 == 0 && is_pow2(n / 3) && n >= 48 && n <= 768); }
+
+int floor_pow2(int n) { return n < 1 ? 0 : 1 << ilog2(n); }
 constexpr int kStepsPerGraph = 16;
 
 int row_rows_per_block(int nx) {
@@ -41,16 +44,18 @@ int row_rows_per_block(int nx) {
   return tpr >= 64 ? 1 : 64 / tpr;
 }
 
-int tile_width(int nx) { return std::min(16, nx / 2); }
+// Spectral tile width: the largest power of two <= 16 that divides nx/2.
+int tile_width(int nx) { return std::min(16, (nx / 2) & -(nx / 2)); }
 
-// Columns per block of the column kernels: the LDS block is ny * cw * 8 bytes per buffer,
-// kept within 64 KB (1 buffer for the convection pass, up to 4 for the derivative groups).
-int conv_cols(int ny, int tw) { return std::min(tw, std::max(1, std::min(16, 8192 / ny))); }
-int multi_cols(int ny, int tw) { return std::min(tw, std::max(1, std::min(16, 2048 / ny))); }
+// Columns per block of the column kernels (a power of two dividing the tile width): the LDS
+// block is ny * cw * 8 bytes per buffer, kept within 64 KB (1 buffer for the convection
+// pass, up to 4 for the derivative groups).
+int conv_cols(int ny, int tw) { return std::min(tw, floor_pow2(std::max(1, std::min(16, 8192 / ny)))); }
+int multi_cols(int ny, int tw) { return std::min(tw, floor_pow2(std::max(1, std::min(16, 2048 / ny)))); }
 
 bool config_ok(const fftlb_config* c) {
   if (!c) return false;
-  if (!is_pow2(c->nx) || !is_pow2(c->ny)) return false;
+  if (!size_supported(c->nx) || !size_supported(c->ny)) return false;
   if (c->nx < 8 || c->nx > kMaxN || c->ny < 4 || c->ny > kMaxN) return false;
   if (c->ny % row_rows_per_block(c->nx)) return false;
   auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
@@ -159,6 +164,11 @@ int dispatch_nx(int nx, A&&... a) {
   switch (nx) {
     case 8: return F<8>::run(a...);
     case 16: return F<16>::run(a...);
+    case 48: return F<48>::run(a...);
+    case 96: return F<96>::run(a...);
+    case 192: return F<192>::run(a...);
+    case 384: return F<384>::run(a...);
+    case 768: return F<768>::run(a...);
     case 32: return F<32>::run(a...);
     case 64: return F<64>::run(a...);
     case 128: return F<128>::run(a...);
@@ -223,6 +233,11 @@ int dispatch_ny(int ny, int cw, A&&... a) {
     case 4: return dispatch_cw<F, 4>(cw, a...);
     case 8: return dispatch_cw<F, 8>(cw, a...);
     case 16: return dispatch_cw<F, 16>(cw, a...);
+    case 48: return dispatch_cw<F, 48>(cw, a...);
+    case 96: return dispatch_cw<F, 96>(cw, a...);
+    case 192: return dispatch_cw<F, 192>(cw, a...);
+    case 384: return dispatch_cw<F, 384>(cw, a...);
+    case 768: return dispatch_cw<F, 768>(cw, a...);
     case 32: return dispatch_cw<F, 32>(cw, a...);
     case 64: return dispatch_cw<F, 64>(cw, a...);
     case 128: return dispatch_cw<F, 128>(cw, a...);

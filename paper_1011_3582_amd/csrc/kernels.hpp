@@ -256,7 +256,7 @@ __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<
                                                    const float2* twx, const float* kapx, int row0, int tid) {
   rows_load_batch<NX, NP>(lds, in, sg, kapx, row0, tid);
   __syncthreads();
-  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
+  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
 }
 
 // Forward row transforms of slots already written (unsynchronised) and store of the packed
@@ -265,7 +265,7 @@ template <int NX, int NP>
 __device__ __forceinline__ void rows_forward_batch(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
                                                    const float2* twx, int row0, int tid) {
   __syncthreads();
-  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
+  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
   rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
   __syncthreads();
 }
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, c
     lds[pad(e)] = g[y * tw + c];
   }
   __syncthreads();
-  fft_lds<NY, -1, NT, CW, true, CW, (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
+  fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
   const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, c
     lds[pad(e)] = make_float2(-m * v.y, m * v.x);
   }
   __syncthreads();
-  fft_lds<NY, +1, NT, CW, true, CW, (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
+  fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
     g[y * tw + c] = lds[pad(e)];
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* 
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
   const long off = (long)(c0 / tw) * NY * tw + (c0 % tw);
   constexpr int BLK = NY * CW;  // input p occupies elements [p BLK, (p + 1) BLK)
-  constexpr bool AL = (BLK % 32 == 0);
+  constexpr bool AL = is_pow2(NY) && (BLK % 32 == 0);
   for (int p = 0; p < G.nin; ++p) {
     const float2* g = G.in[p] + off;
     for (int e = tid; e < BLK; e += NT) {

@@ -32,7 +32,8 @@ def test_workspace_bytes_valid(nx, ny):
 
 
 @pytest.mark.parametrize("change", [
-    dict(nx=96), dict(nx=4), dict(ny=2), dict(nx=4096), dict(ny=3000), dict(nx=8, ny=8),
+    dict(nx=80), dict(nx=24), dict(ny=1536), dict(nx=4), dict(ny=2), dict(nx=4096), dict(ny=3000),
+    dict(nx=8, ny=8), dict(nx=48, ny=9),
     dict(dt=0.0), dict(dx=-1.0), dict(tau=0.0), dict(tau=math.nan), dict(K=-1.0), dict(b=-0.1),
     dict(filter_order=5), dict(filter_order=-1), dict(reserved=1), dict(q=math.inf),
 ])

@@ -60,7 +60,9 @@ def relerr(a, b):
     return float(np.abs(np.asarray(a, np.float64) - b).max() / np.abs(b).max())
 
 
-SHAPES = [(64, 64), (32, 128), (128, 32), (4, 512), (32, 8), (16, 256)]
+SHAPES = [(64, 64), (32, 128), (128, 32), (4, 512), (32, 8), (16, 256),
+          # lengths 3 * 2^p (a radix-3 pass in every transform)
+          (96, 48), (48, 96), (192, 192), (384, 16), (64, 384), (768, 8)]
 
 
 def _fields_for(ny, nx, seed=0):
@@ -121,7 +123,8 @@ def test_derivative_of_sinusoid_is_exact_in_fp32():
     assert np.abs(got - ref).max() < 3e-6 * kap
 
 
-@pytest.mark.parametrize("case", ["slab64", "smooth64", "slab_4x512", "smooth_128x32", "smooth_32x8"])
+@pytest.mark.parametrize("case", ["slab64", "smooth64", "slab_4x512", "smooth_128x32", "smooth_32x8",
+                                  "smooth_96x48", "smooth_192", "slab_16x384"])
 def test_one_step_from_shared_state(case):
     if case == "slab64":
         fld = W.slab_64()
@@ -131,6 +134,12 @@ def test_one_step_from_shared_state(case):
         fld = W.slab(512, 4, t_ratio=0.9, width=4.0, noise=1e-3, seed=1)
     elif case == "smooth_128x32":
         fld = W.smooth_random(32, 128, seed=4, T0=1.3)
+    elif case == "smooth_96x48":
+        fld = W.smooth_random(48, 96, seed=6, T0=1.25)
+    elif case == "smooth_192":
+        fld = W.smooth_random(192, 192, seed=7, T0=1.2)
+    elif case == "slab_16x384":
+        fld = W.slab(384, 16, t_ratio=0.85, width=3.0, noise=1e-3, seed=8)
     else:
         fld = W.slab(8, 32, t_ratio=0.9, width=1.5, noise=1e-3, seed=5)
     p = F.Params()

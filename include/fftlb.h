@@ -119,9 +119,79 @@ int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, vo
  * counts as a step). */
 int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream);
 
+/* Column-pass plan of a handle: spectral columns per block of the convection pass and of
+ * the derivative passes (powers of two up to 16, at most the tile width min(16, the
+ * largest power of two dividing nx/2), and within 64 KB of LDS: ny * conv_cols <= 8192,
+ * 4 * ny * multi_cols <= 8192), and the largest radix of the column transforms (8 or 16).
+ * fftlb_init picks the widest tiles and radix 16; a new plan takes effect at the next call
+ * (the captured step graphs are rebuilt).  Plans change speed only: the results of any
+ * two plans agree to FP32 rounding of the column transforms. */
+typedef struct fftlb_plan {
+  int32_t conv_cols, multi_cols, col_radix;
+  int32_t reserved; /* must be 0 */
+} fftlb_plan;
+int fftlb_get_plan(const fftlb_handle* h, fftlb_plan* plan);
+int fftlb_set_plan(fftlb_handle* h, const fftlb_plan* plan);
+
+/* Autotuner: time every column plan of the handle's grid size (`reps` launches each, on
+ * `stream`, synchronising) on the handle's current state and set the fastest.  The state
+ * is restored afterwards (the spectra are recomputed from f), so the trajectory is
+ * unchanged.  With `cache_path` (a text file, NULL for none) a plan already stored there
+ * for this device architecture and grid size is used without timing, and a newly timed
+ * plan is appended.  *best (may be NULL) receives the plan. */
+int fftlb_autotune(fftlb_handle* h, int32_t reps, const char* cache_path, void* stream, fftlb_plan* best);
+
 /* Release the handle (host memory and captured graphs); the workspace is untouched.
  * Synchronises the device first, since captured graphs may still run on caller streams. */
 int fftlb_destroy(fftlb_handle* h);
+
+/* ------------------------------------------------------------------------------------
+ * Batches: up to FFTLB_MAX_BATCH independent instances, of any mix of supported grid
+ * sizes and parameters, advanced together.  Each launch of a step kernel covers every
+ * running instance of one grid size; fftlb_batch_run replays one captured HIP graph of
+ * `poll_every` steps of all running instances followed by an on-device poll that retires
+ * converged instances (their blocks exit at once in later launches), so the host only
+ * reads the retirement flags between replays.  The residual is global [4] of
+ * fftlb_moments: dt max_sites |sum_q v_q.grad f_q| = max |rho^{n+1} - rho^n| in exact
+ * arithmetic (the collision and the force conserve mass), formed from the right-hand
+ * side so that it does not stagnate at FP32 resolution.
+ * ------------------------------------------------------------------------------------ */
+#define FFTLB_MAX_BATCH 1024
+typedef struct fftlb_batch fftlb_batch;
+
+/* Device workspace for a batch of n configurations (the sum of the instances'
+ * workspaces plus bookkeeping). */
+int fftlb_batch_workspace_bytes(int32_t n, const fftlb_config* cfgs, size_t* bytes);
+
+/* Initialise n instances on `workspace` as fftlb_init does for each; rho0[i] .. T0[i] are
+ * host arrays of n device pointers to instance i's [ny][nx] initial fields (read during
+ * the call only).  Synchronises `stream`. */
+int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, size_t ws_bytes,
+                       const float* const* rho0, const float* const* ux0, const float* const* uy0,
+                       const float* const* T0, void* stream, fftlb_batch** out);
+
+/* fftlb_autotune for each grid size of the batch (on its first instance), applied to
+ * every instance of that size. */
+int fftlb_batch_autotune(fftlb_batch* b, int32_t reps, const char* cache_path, void* stream);
+
+/* Advance every running instance until all have retired or at least `max_steps` more
+ * steps were taken (a multiple of poll_every, 1..1000).  An instance retires as
+ * converged (state 1) when its residual is below `tol` at `consecutive` successive polls,
+ * or as unstable (state 2) at a non-finite value.  Synchronises `stream`. */
+int fftlb_batch_run(fftlb_batch* b, double tol, int32_t consecutive, int32_t poll_every, int64_t max_steps,
+                    void* stream);
+
+/* Host arrays of n entries (each may be NULL): steps taken, steps at the first of the
+ * `consecutive` polls below tol (-1 unless converged), last polled residual, state
+ * (0 running, 1 converged, 2 non-finite).  Synchronises the device. */
+int fftlb_batch_status(fftlb_batch* b, int64_t* steps, int64_t* steps_to_tol, double* residual, int32_t* state);
+
+/* The handle of instance i (owned by the batch: fftlb_moments, fftlb_get_state, ... work
+ * on it; do not destroy it). */
+int fftlb_batch_instance(fftlb_batch* b, int32_t i, fftlb_handle** h);
+
+/* Release the batch and its instance handles; the workspace is untouched. */
+int fftlb_batch_destroy(fftlb_batch* b);
 
 /* Static string for an error code, and the thread's last detailed HIP error message. */
 const char* fftlb_strerror(int code);

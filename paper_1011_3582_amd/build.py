@@ -1,6 +1,11 @@
-"""Build the HIP library libfftlb.so for gfx950 in-tree with hipcc."""
+"""Build the HIP library libfftlb.so for gfx950 in-tree with hipcc.
+
+The kernels are split over several translation units (csrc/*.hip: the API, and the row
+and column kernels by grid size), compiled in parallel and linked into one library."""
 from __future__ import annotations
 
+import concurrent.futures as cf
+import glob
 import os
 import shutil
 import subprocess
@@ -12,9 +17,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfftlb.so")
+OBJ = os.path.join(PKG, "_build")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed FP32 instructions stay off: plain float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -28,22 +34,36 @@ def hipcc() -> str:
     return path
 
 
-def build(verbose: bool = True) -> str:
-    """Compile csrc/fftlb.hip into libfftlb.so (always recompiles)."""
-    src = os.path.join(CSRC, "fftlb.hip")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, src, "-o", tmp]
-    t0 = time.time()
+def _compile(src: str) -> tuple[str, str]:
+    obj = os.path.join(OBJ, os.path.basename(src).replace(".hip", ".o"))
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfftlb.so")
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj, res.stderr
+
+
+def build(verbose: bool = True, jobs: int | None = None) -> str:
+    """Compile every csrc/*.hip and link libfftlb.so (always recompiles)."""
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_compile, srcs))
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", *[o for o, _ in results], "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed linking libfftlb.so")
     os.replace(tmp, LIB)
     if verbose:
-        warn = [l for l in res.stderr.splitlines() if "warning" in l and "packed-fp32-ops" not in l]
+        warn = [l for _, e in results for l in e.splitlines() if "warning" in l and "packed-fp32-ops" not in l]
         for l in warn[:20]:
             print(l)
-        print(f"built {LIB} in {time.time() - t0:.1f} s")
+        print(f"built {LIB} from {len(srcs)} sources in {time.time() - t0:.1f} s")
     return LIB
 
 

@@ -1,5 +1,6 @@
 // C ABI of the FFT-LB solver: argument checking, workspace layout, tables, kernel
-// dispatch over grid sizes, and HIP-graph capture of the time step.
+// dispatch over grid sizes, HIP-graph capture of the time step, column-plan autotuning
+// and batches of instances of uneven grid sizes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,10 +8,12 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "fftlb.h"
-#include "kernels.hpp"
+#include "launch.hpp"
+#include "reduce.hpp"
 
 using namespace fftlb;
 
@@ -31,13 +34,20 @@ void set_error(const char* what, hipError_t e) {
     }                                                        \
   } while (0)
 
+#define RC_TRY(call)          \
+  do {                        \
+    const int rc_ = (call);   \
+    if (rc_) return rc_;      \
+  } while (0)
+
 constexpr int kMaxN = 2048;
+constexpr int kStepsPerGraph = 16;
+constexpr int kMaxPollEvery = 1000;
 
 // Grid sizes with compiled kernels: powers of two, and 3 * 2^p from 48 to 768.
 bool size_supported(int n) { return is_pow2(n) || (n % 3 == 0 && is_pow2(n / 3) && n >= 48 && n <= 768); }
 
 int floor_pow2(int n) { return n < 1 ? 0 : 1 << ilog2(n); }
-constexpr int kStepsPerGraph = 16;
 
 int row_rows_per_block(int nx) {
   const int tpr = nx / (nx >= 2048 ? 4 : 2);  // threads per row, as in RowGeom
@@ -47,11 +57,20 @@ int row_rows_per_block(int nx) {
 // Spectral tile width: the largest power of two <= 16 that divides nx/2.
 int tile_width(int nx) { return std::min(16, (nx / 2) & -(nx / 2)); }
 
-// Columns per block of the column kernels (a power of two dividing the tile width): the LDS
-// block is ny * cw * 8 bytes per buffer, kept within 64 KB (1 buffer for the convection
-// pass, up to 4 for the derivative groups).
-int conv_cols(int ny, int tw) { return std::min(tw, floor_pow2(std::max(1, std::min(16, 8192 / ny)))); }
-int multi_cols(int ny, int tw) { return std::min(tw, floor_pow2(std::max(1, std::min(16, 2048 / ny)))); }
+// Largest column counts per block the LDS budget allows: one buffer of ny * cw float2 for the
+// convection pass, four for the derivative passes (three inputs and a work block).
+int conv_cols_max(int ny, int tw) { return std::min(tw, floor_pow2(std::max(1, std::min(16, kColLdsElems / ny)))); }
+int multi_cols_max(int ny, int tw) {
+  return std::min(tw, floor_pow2(std::max(1, std::min(16, kColLdsElems / (4 * ny)))));
+}
+
+ColPlan default_plan(int ny, int tw) { return ColPlan{conv_cols_max(ny, tw), multi_cols_max(ny, tw), 16}; }
+
+bool plan_ok(const ColPlan& p, int ny, int tw) {
+  auto cw_ok = [&](int cw, int mx) { return cw >= 1 && is_pow2(cw) && cw <= mx; };
+  return cw_ok(p.conv_cw, conv_cols_max(ny, tw)) && cw_ok(p.multi_cw, multi_cols_max(ny, tw)) &&
+         (p.radix == 8 || p.radix == 16);
+}
 
 bool config_ok(const fftlb_config* c) {
   if (!c) return false;
@@ -70,8 +89,11 @@ bool config_ok(const fftlb_config* c) {
 }
 
 struct Layout {
-  size_t f, sf, sm, s1, s2i, s2o, macro, cpl, twx, twy, kx, ky, pd, pf, total;
+  size_t f, sf, spec, macro, cpl, twx, twy, kx, ky, pd, pf, total;
 };
+
+// Planes of the spectral block (contiguous, so that a column pass addresses them by index).
+enum : int { SB_SM = 0, SB_S1 = 4, SB_S2I = 10, SB_S2O = 15, SB_PLANES = 18 };
 
 size_t align_up(size_t v) { return (v + FFTLB_WORKSPACE_ALIGN - 1) / FFTLB_WORKSPACE_ALIGN * FFTLB_WORKSPACE_ALIGN; }
 
@@ -87,10 +109,7 @@ Layout make_layout(int nx, int ny) {
   };
   L.f = take(33 * plane);
   L.sf = take(32 * plane);
-  L.sm = take(4 * plane);
-  L.s1 = take(6 * plane);
-  L.s2i = take(5 * plane);
-  L.s2o = take(3 * plane);
+  L.spec = take(SB_PLANES * plane);
   L.macro = take(4 * plane);
   L.cpl = take(plane);
   L.twx = take((size_t)nx * sizeof(float2));
@@ -119,6 +138,56 @@ double windowed_k(int n, int N, double d, int m) {
   return 2.0 / d * acc;
 }
 
+ColGroup group(std::initializer_list<int> in, std::initializer_list<int> out,
+               std::initializer_list<std::initializer_list<int>> kinds) {
+  ColGroup g{};
+  g.nin = (int)in.size();
+  g.nout = (int)out.size();
+  int i = 0;
+  for (int p : in) g.in[i++] = p;
+  i = 0;
+  for (int p : out) g.out[i++] = p;
+  i = 0;
+  for (auto& row : kinds) {
+    int j = 0;
+    for (int k : row) g.kind[i][j++] = k;
+    ++i;
+  }
+  return g;
+}
+
+// Stage 1: only the y-derivatives need the column pass; x-derivatives are formed in the
+// stage-2 row kernel from the moment spectra.  Moment spectra sm = [rho, ux, uy, T];
+// s1 = [D_y rho, D_yy rho, D_y ux, D_y uy, D_y theta, D_y T] with D_y theta = D_y D_x ux + D_yy uy.
+ColLaunch stage1_groups() {
+  ColLaunch a{};
+  const int sm = SB_SM, s1 = SB_S1;
+  a.g[0] = group({sm}, {s1, s1 + 1}, {{MK_IKY}, {MK_KYY}});
+  a.g[1] = group({sm + 1, sm + 2}, {s1 + 2, s1 + 3, s1 + 4}, {{MK_IKY, MK_NONE}, {MK_NONE, MK_IKY}, {MK_KXY, MK_KYY}});
+  a.g[2] = group({sm + 3}, {s1 + 5}, {{MK_IKY}});
+  return a;
+}
+
+// Stage 2: B^x = D_x(S + Lxx) + D_y Lxy,  B^y = D_x Lxy + D_y(S + Lyy),  G = D_x gx + D_y gy.
+ColLaunch stage2_groups() {
+  ColLaunch b{};
+  const int i2 = SB_S2I, o2 = SB_S2O;
+  b.g[0] = group({i2, i2 + 1, i2 + 2}, {o2, o2 + 1}, {{MK_IKX, MK_IKY, MK_NONE}, {MK_NONE, MK_IKX, MK_IKY}});
+  b.g[1] = group({i2 + 3, i2 + 4}, {o2 + 2}, {{MK_IKX, MK_IKY}});
+  return b;
+}
+
+// fftlb_derivative: s1 plane 0 -> s1 plane 1 through the full 2D pass.
+ColLaunch derivative_group(int op) {
+  const int kinds[3] = {MK_IKX, MK_IKY, MK_LAP};
+  ColLaunch d{};
+  d.g[0] = group({SB_S1}, {SB_S1 + 1}, {{kinds[op]}});
+  return d;
+}
+
+const ColLaunch kStage1 = stage1_groups();
+const ColLaunch kStage2 = stage2_groups();
+
 }  // namespace
 
 struct fftlb_handle {
@@ -126,12 +195,9 @@ struct fftlb_handle {
   int device;
   int nx, ny, tw;
   Layout L;
-  Planes P;
-  Model M;
-  float2* twy;
-  float* kapx;
-  float* kapy;
-  int nblk_rows;
+  Inst I;
+  const Inst* self;  // &I, as a one-entry instance list
+  ColPlan plan;
   int64_t steps;
   hipStream_t cap, cap2;   // capture streams (the second carries the concurrent branch)
   hipEvent_t fork, join;
@@ -156,235 +222,121 @@ struct DeviceGuard {
 };
 
 // ---------------------------------------------------------------------------
-// Kernel dispatch over compile-time sizes
+// Dispatch over compile-time sizes
 // ---------------------------------------------------------------------------
 
-template <template <int> class F, typename... A>
-int dispatch_nx(int nx, A&&... a) {
-  switch (nx) {
-    case 8: return F<8>::run(a...);
-    case 16: return F<16>::run(a...);
-    case 48: return F<48>::run(a...);
-    case 96: return F<96>::run(a...);
-    case 192: return F<192>::run(a...);
-    case 384: return F<384>::run(a...);
-    case 768: return F<768>::run(a...);
-    case 32: return F<32>::run(a...);
-    case 64: return F<64>::run(a...);
-    case 128: return F<128>::run(a...);
-    case 256: return F<256>::run(a...);
-    case 512: return F<512>::run(a...);
-    case 1024: return F<1024>::run(a...);
-    case 2048: return F<2048>::run(a...);
+#define FFTLB_FOR_ROW_SIZES(X) \
+  X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
+#define FFTLB_FOR_COL_SIZES(X) X(4) FFTLB_FOR_ROW_SIZES(X)
+
+int rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s) {
+  switch (L.nx) {
+#define X(n) \
+  case n: return launch_rows<n>(L, kernel, in, s);
+    FFTLB_FOR_ROW_SIZES(X)
+#undef X
   }
   return FFTLB_EINVAL;
 }
 
-// radix-16 passes: one 16-point butterfly per thread per pass
-constexpr int col_threads(int ny, int cw) { return std::min(1024, std::max(64, ny * cw / 16)); }
-
-template <int NY, int CW>
-struct ColConv {
-  static int run(hipStream_t s, fftlb_handle* h) {
-    if constexpr (NY * CW > 8192) {
-      return FFTLB_EINVAL;
-    } else {
-      constexpr int NT = col_threads(NY, CW);
-      const int nblocks = 24 * ((h->nx / 2) / CW);   // 24 populations with v_y != 0
-      hipLaunchKernelGGL((k_col_conv<NY, CW, NT>), dim3(nblocks), dim3(NT), lds_alloc(NY * CW) * sizeof(float2), s,
-                         h->P.sf, h->twy, h->kapx, h->kapy, h->nx, h->tw, h->M.scale);
-      return FFTLB_OK;
-    }
-  }
-};
-
-template <int NY, int CW>
-struct ColMulti {
-  static int run(hipStream_t s, fftlb_handle* h, const ColLaunch& L, int ngroups, int maxin) {
-    if constexpr (NY * CW * 4 > 8192) {
-      return FFTLB_EINVAL;
-    } else {
-      constexpr int NT = col_threads(NY, CW);
-      const int nsub = (h->nx / 2) / CW;
-      (void)maxin;  // the work block sits after room for three inputs
-      const size_t lds = (size_t)lds_alloc(4 * NY * CW) * sizeof(float2);
-      hipLaunchKernelGGL((k_col_multi<NY, CW, NT>), dim3(nsub, ngroups), dim3(NT), lds, s, L, h->twy, h->kapx,
-                         h->kapy, h->nx, h->tw, h->M.scale);
-      return FFTLB_OK;
-    }
-  }
-};
-
-template <template <int, int> class F, int NY, typename... A>
-int dispatch_cw(int cw, A&&... a) {
-  switch (cw) {
-    case 1: return F<NY, 1>::run(a...);
-    case 2: return F<NY, 2>::run(a...);
-    case 4: return F<NY, 4>::run(a...);
-    case 8: return F<NY, 8>::run(a...);
-    case 16: return F<NY, 16>::run(a...);
+int col_conv(const StepLaunch& L, hipStream_t s) {
+  switch (L.ny) {
+#define X(n) \
+  case n: return launch_col_conv<n>(L, s);
+    FFTLB_FOR_COL_SIZES(X)
+#undef X
   }
   return FFTLB_EINVAL;
 }
 
-template <template <int, int> class F, typename... A>
-int dispatch_ny(int ny, int cw, A&&... a) {
-  switch (ny) {
-    case 4: return dispatch_cw<F, 4>(cw, a...);
-    case 8: return dispatch_cw<F, 8>(cw, a...);
-    case 16: return dispatch_cw<F, 16>(cw, a...);
-    case 48: return dispatch_cw<F, 48>(cw, a...);
-    case 96: return dispatch_cw<F, 96>(cw, a...);
-    case 192: return dispatch_cw<F, 192>(cw, a...);
-    case 384: return dispatch_cw<F, 384>(cw, a...);
-    case 768: return dispatch_cw<F, 768>(cw, a...);
-    case 32: return dispatch_cw<F, 32>(cw, a...);
-    case 64: return dispatch_cw<F, 64>(cw, a...);
-    case 128: return dispatch_cw<F, 128>(cw, a...);
-    case 256: return dispatch_cw<F, 256>(cw, a...);
-    case 512: return dispatch_cw<F, 512>(cw, a...);
-    case 1024: return dispatch_cw<F, 1024>(cw, a...);
-    case 2048: return dispatch_cw<F, 2048>(cw, a...);
+int col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+  switch (L.ny) {
+#define X(n) \
+  case n: return launch_col_multi<n>(L, groups, ngroups, s);
+    FFTLB_FOR_COL_SIZES(X)
+#undef X
   }
   return FFTLB_EINVAL;
 }
 
-template <int NX>
-struct RowStage2 {
-  static int run(hipStream_t s, fftlb_handle* h) {
-    hipLaunchKernelGGL(k_rows_stage2<NX>, dim3(h->nblk_rows), dim3(RowGeom<NX>::NT),
-                       RowGeom<NX>::LDS * sizeof(float2), s, h->P, h->M);
-    return FFTLB_OK;
+int rows_forward_real(const fftlb_handle* h, const float* a, float2* sa, hipStream_t s) {
+  const int nblk = h->I.nblk;
+  switch (h->nx) {
+#define X(n) \
+  case n: return launch_rows_forward_real<n>(nblk, a, nullptr, sa, nullptr, h->I.P.sg, h->I.P.twx, s);
+    FFTLB_FOR_ROW_SIZES(X)
+#undef X
   }
-};
+  return FFTLB_EINVAL;
+}
 
-template <int MODE>
-struct RowCollideMode {
-  template <int NX>
-  struct K {
-    static int run(hipStream_t s, fftlb_handle* h, const Planes& P) {
-      hipLaunchKernelGGL((k_rows_collide<NX, MODE>), dim3(h->nblk_rows), dim3(RowGeom<NX>::NT),
-                         RowGeom<NX>::LDS * sizeof(float2), s, P, h->M);
-      return FFTLB_OK;
-    }
-  };
-};
-
-template <int NX>
-struct RowFwdReal {
-  static int run(hipStream_t s, fftlb_handle* h, const float* a, const float* b, float2* sa, float2* sb) {
-    hipLaunchKernelGGL(k_rows_forward_real<NX>, dim3(h->nblk_rows), dim3(RowGeom<NX>::NT),
-                       RowGeom<NX>::LDS * sizeof(float2), s, a, b, sa, sb, h->P.sg, h->P.twx, h->nx);
-    return FFTLB_OK;
+int rows_inverse_real(const fftlb_handle* h, const float2* sa, float* a, hipStream_t s) {
+  const int nblk = h->I.nblk;
+  switch (h->nx) {
+#define X(n) \
+  case n: return launch_rows_inverse_real<n>(nblk, sa, nullptr, a, nullptr, h->I.P.sg, h->I.P.twx, h->I.P.kapx, s);
+    FFTLB_FOR_ROW_SIZES(X)
+#undef X
   }
-};
+  return FFTLB_EINVAL;
+}
 
-template <int NX>
-struct RowInvReal {
-  static int run(hipStream_t s, fftlb_handle* h, const float2* sa, const float2* sb, float* a, float* b) {
-    hipLaunchKernelGGL(k_rows_inverse_real<NX>, dim3(h->nblk_rows), dim3(RowGeom<NX>::NT),
-                       RowGeom<NX>::LDS * sizeof(float2), s, sa, sb, a, b, h->P.sg, h->P.twx, h->P.kapx, h->nx);
-    return FFTLB_OK;
-  }
-};
+StepLaunch single_launch(const fftlb_handle* h, const ColPlan& plan) {
+  return StepLaunch{&h->self, nullptr, 1, nullptr, h->nx, h->ny, h->tw, h->I.nblk, plan};
+}
 
 // ---------------------------------------------------------------------------
-// Step building blocks
+// The step
 // ---------------------------------------------------------------------------
-
-ColGroup group(std::initializer_list<const float2*> in, std::initializer_list<float2*> out,
-               std::initializer_list<std::initializer_list<int>> kinds) {
-  ColGroup g{};
-  g.nin = (int)in.size();
-  g.nout = (int)out.size();
-  int i = 0;
-  for (auto p : in) g.in[i++] = p;
-  i = 0;
-  for (auto p : out) g.out[i++] = p;
-  i = 0;
-  for (auto& row : kinds) {
-    int j = 0;
-    for (int k : row) g.kind[i][j++] = k;
-    ++i;
-  }
-  return g;
-}
-
-int launch_stage1(fftlb_handle* h, hipStream_t s) {
-  const long hp = (long)h->nx * h->ny / 2;
-  float2* sm = h->P.sm;
-  float2* s1 = h->P.s1;
-  ColLaunch L{};
-  // Only the y-derivatives need the column pass; x-derivatives are formed in the stage-2
-  // row kernel from the moment spectra.  s1 = [D_y rho, D_yy rho, D_y ux, D_y uy, D_y theta, D_y T]
-  // rho -> D_y rho, D_yy rho
-  L.g[0] = group({sm}, {s1, s1 + hp}, {{MK_IKY}, {MK_KYY}});
-  // ux, uy -> D_y ux, D_y uy, D_y theta = D_y D_x ux + D_yy uy
-  L.g[1] = group({sm + hp, sm + 2 * hp}, {s1 + 2 * hp, s1 + 3 * hp, s1 + 4 * hp},
-                 {{MK_IKY, MK_NONE}, {MK_NONE, MK_IKY}, {MK_KXY, MK_KYY}});
-  // T -> D_y T
-  L.g[2] = group({sm + 3 * hp}, {s1 + 5 * hp}, {{MK_IKY}});
-  return dispatch_ny<ColMulti>(h->ny, multi_cols(h->ny, h->tw), s, h, L, 3, 2);
-}
-
-int launch_stage2_cols(fftlb_handle* h, hipStream_t s) {
-  const long hp = (long)h->nx * h->ny / 2;
-  float2* i2 = h->P.s2i;
-  float2* o2 = h->P.s2o;
-  ColLaunch L{};
-  // B^x = D_x(S + Lxx) + D_y Lxy,  B^y = D_x Lxy + D_y(S + Lyy)
-  L.g[0] = group({i2, i2 + hp, i2 + 2 * hp}, {o2, o2 + hp},
-                 {{MK_IKX, MK_IKY, MK_NONE}, {MK_NONE, MK_IKX, MK_IKY}});
-  // G = D_x gx + D_y gy
-  L.g[1] = group({i2 + 3 * hp, i2 + 4 * hp}, {o2 + 2 * hp}, {{MK_IKX, MK_IKY}});
-  return dispatch_ny<ColMulti>(h->ny, multi_cols(h->ny, h->tw), s, h, L, 2, 3);
-}
 
 constexpr int kNumStages = 5;
 
 // One kernel of the step: 0 convection columns, 1 stage-1 columns, 2 stage-2 rows,
 // 3 stage-2 columns, 4 collide rows.
-int enqueue_stage(fftlb_handle* h, int stage, hipStream_t s) {
+int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
   switch (stage) {
-    case 0: return dispatch_ny<ColConv>(h->ny, conv_cols(h->ny, h->tw), s, h);
-    case 1: return launch_stage1(h, s);
-    case 2: return dispatch_nx<RowStage2>(h->nx, s, h);
-    case 3: return launch_stage2_cols(h, s);
-    case 4: return dispatch_nx<RowCollideMode<MODE_STEP>::K>(h->nx, s, h, h->P);
+    case 0: return col_conv(L, s);
+    case 1: return col_multi(L, kStage1, 3, s);
+    case 2: return rows(L, RK_STAGE2, Inputs{}, s);
+    case 3: return col_multi(L, kStage2, 2, s);
+    case 4: return rows(L, RK_COLLIDE, Inputs{}, s);
   }
   return FFTLB_EINVAL;
 }
 
-int enqueue_step(fftlb_handle* h, hipStream_t s) {
-  for (int k = 0; k < kNumStages; ++k) {
-    const int rc = enqueue_stage(h, k, s);
-    if (rc) return rc;
-  }
+// One step of every launch group in `Ls`, as captured into a graph: the convection column
+// passes (stage 0) run on a second branch, concurrently with the force pipeline (stages
+// 1-3); the collide (stage 4) joins both.
+int enqueue_step_forked(const StepLaunch* Ls, int nl, hipStream_t s, hipStream_t s2, hipEvent_t fork,
+                        hipEvent_t join) {
+  HIP_TRY(hipEventRecord(fork, s));
+  HIP_TRY(hipStreamWaitEvent(s2, fork, 0));
+  for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], 0, s2));
+  HIP_TRY(hipEventRecord(join, s2));
+  for (int k = 1; k <= 3; ++k)
+    for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], k, s));
+  HIP_TRY(hipStreamWaitEvent(s, join, 0));
+  for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], 4, s));
   return FFTLB_OK;
 }
 
-// The step as captured into a graph: the convection column pass (stage 0) runs on a
-// second branch, concurrently with the force pipeline (stages 1-3); the collide
-// (stage 4) joins both.
-int enqueue_step_forked(fftlb_handle* h, hipStream_t s) {
-  int rc;
-  HIP_TRY(hipEventRecord(h->fork, s));
-  HIP_TRY(hipStreamWaitEvent(h->cap2, h->fork, 0));
-  if ((rc = enqueue_stage(h, 0, h->cap2))) return rc;
-  HIP_TRY(hipEventRecord(h->join, h->cap2));
-  for (int k = 1; k <= 3; ++k)
-    if ((rc = enqueue_stage(h, k, s))) return rc;
-  HIP_TRY(hipStreamWaitEvent(s, h->join, 0));
-  return enqueue_stage(h, 4, s);
+int make_streams(hipStream_t* a, hipStream_t* b, hipEvent_t* fork, hipEvent_t* join) {
+  // default-priority streams; events without timing
+  if (!*a) HIP_TRY(hipStreamCreateWithFlags(a, hipStreamNonBlocking));
+  if (!*b) HIP_TRY(hipStreamCreateWithFlags(b, hipStreamNonBlocking));
+  if (!*fork) HIP_TRY(hipEventCreateWithFlags(fork, hipEventDisableTiming));
+  if (!*join) HIP_TRY(hipEventCreateWithFlags(join, hipEventDisableTiming));
+  return FFTLB_OK;
 }
 
-int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
+// Capture what `body` enqueues on the capture stream into an executable graph.
+template <typename Body>
+int capture_graph(hipStream_t cap, Body body, hipGraphExec_t* out) {
   hipGraph_t graph = nullptr;
-  HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
-  int rc = FFTLB_OK;
-  for (int i = 0; i < nsteps && rc == FFTLB_OK; ++i) rc = enqueue_step_forked(h, h->cap);
+  HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+  const int rc = body();
   hipError_t le = hipGetLastError();
-  hipError_t ee = hipStreamEndCapture(h->cap, &graph);
+  hipError_t ee = hipStreamEndCapture(cap, &graph);
   if (rc != FFTLB_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return rc;
@@ -407,12 +359,260 @@ int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
   return FFTLB_OK;
 }
 
+int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
+  RC_TRY(make_streams(&h->cap, &h->cap2, &h->fork, &h->join));
+  const StepLaunch L = single_launch(h, h->plan);
+  return capture_graph(
+      h->cap,
+      [&]() {
+        for (int i = 0; i < nsteps; ++i) RC_TRY(enqueue_step_forked(&L, 1, h->cap, h->cap2, h->fork, h->join));
+        return FFTLB_OK;
+      },
+      out);
+}
+
+void drop_graphs(fftlb_handle* h) {
+  if (h->g1) (void)hipGraphExecDestroy(h->g1);
+  if (h->gN) (void)hipGraphExecDestroy(h->gN);
+  h->g1 = h->gN = nullptr;
+}
+
 int check_launch(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(what, e);
     return FFTLB_EHIP;
   }
+  return FFTLB_OK;
+}
+
+// Recompute every spectrum and the moments from the handle's own f (set-state in place;
+// each thread reads and writes only its own sites): restores a consistent state after
+// kernels were run out of order.
+int refresh_from_f(fftlb_handle* h, hipStream_t s) {
+  Inputs in{};
+  in.a[0] = h->I.P.f;
+  RC_TRY(rows(single_launch(h, h->plan), RK_SET, in, s));
+  return check_launch("refresh");
+}
+
+// ---------------------------------------------------------------------------
+// Plan cache: a text file with one line "arch nx ny conv_cols multi_cols col_radix" per
+// grid size and device architecture.
+// ---------------------------------------------------------------------------
+
+std::string device_arch(int dev) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool cache_lookup(const char* path, const std::string& arch, int nx, int ny, ColPlan* out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char a[64];
+  int x, y, c, m, r;
+  bool found = false;
+  while (std::fscanf(f, "%63s %d %d %d %d %d", a, &x, &y, &c, &m, &r) == 6)
+    if (arch == a && x == nx && y == ny) {
+      *out = ColPlan{c, m, r};
+      found = true;  // the last entry for a size wins
+    }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& arch, int nx, int ny, const ColPlan& p) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d %d\n", arch.c_str(), nx, ny, p.conv_cw, p.multi_cw, p.radix);
+  std::fclose(f);
+}
+
+// Mean time of `reps` rounds of the given stages, after one untimed round.
+int time_stages(const StepLaunch& L, const int* stages, int ns, int reps, hipStream_t s, hipEvent_t e0,
+                hipEvent_t e1, float* ms) {
+  for (int k = 0; k < ns; ++k) RC_TRY(enqueue_stage(L, stages[k], s));
+  HIP_TRY(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r)
+    for (int k = 0; k < ns; ++k) RC_TRY(enqueue_stage(L, stages[k], s));
+  HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipEventSynchronize(e1));
+  HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+  *ms /= reps;
+  return FFTLB_OK;
+}
+
+// Time every column plan of the handle's size on its own state and keep the fastest:
+// for each radix, the best convection tile width plus the best derivative tile width.
+int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("hipEventCreate", hipErrorUnknown);
+    return FFTLB_EHIP;
+  }
+  const int conv_stage[1] = {0}, multi_stages[2] = {1, 3};
+  float best_ms = 1e30f;
+  int rc = FFTLB_OK;
+  for (int radix : {16, 8}) {
+    float bc = 1e30f, bm = 1e30f;
+    int cc = 0, cm = 0;
+    for (int cw = 1; cw <= conv_cols_max(h->ny, h->tw) && rc == FFTLB_OK; cw *= 2) {
+      float ms;
+      const ColPlan p{cw, h->plan.multi_cw, radix};
+      rc = time_stages(single_launch(h, p), conv_stage, 1, reps, s, e0, e1, &ms);
+      if (rc == FFTLB_OK && ms < bc) bc = ms, cc = cw;
+    }
+    for (int cw = 1; cw <= multi_cols_max(h->ny, h->tw) && rc == FFTLB_OK; cw *= 2) {
+      float ms;
+      const ColPlan p{h->plan.conv_cw, cw, radix};
+      rc = time_stages(single_launch(h, p), multi_stages, 2, reps, s, e0, e1, &ms);
+      if (rc == FFTLB_OK && ms < bm) bm = ms, cm = cw;
+    }
+    if (rc == FFTLB_OK && bc + bm < best_ms) {
+      best_ms = bc + bm;
+      *best = ColPlan{cc, cm, radix};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != FFTLB_OK) return rc;
+  // the timed launches repeated stages out of order: rebuild the spectra from f
+  return refresh_from_f(h, s);
+}
+
+int set_plan(fftlb_handle* h, const ColPlan& p) {
+  if (!plan_ok(p, h->ny, h->tw)) return FFTLB_EINVAL;
+  if (p.conv_cw != h->plan.conv_cw || p.multi_cw != h->plan.multi_cw || p.radix != h->plan.radix) {
+    h->plan = p;
+    drop_graphs(h);
+  }
+  return FFTLB_OK;
+}
+
+int autotune(fftlb_handle* h, int reps, const char* cache_path, hipStream_t s, ColPlan* best) {
+  const std::string arch = device_arch(h->device);
+  ColPlan p;
+  if (cache_path && cache_lookup(cache_path, arch, h->nx, h->ny, &p) && plan_ok(p, h->ny, h->tw)) {
+    *best = p;
+    return set_plan(h, p);
+  }
+  RC_TRY(tune(h, reps, s, &p));
+  if (cache_path) cache_store(cache_path, arch, h->nx, h->ny, p);
+  *best = p;
+  return set_plan(h, p);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+struct fftlb_batch {
+  int n;
+  int device;
+  std::vector<fftlb_handle*> inst;
+  PollInfo* dpoll;     // n entries: where the poll finds each instance's partials
+  BatchState st;
+  struct Group {
+    int nx, ny, tw, nblk;
+    ColPlan plan;
+    std::vector<int> members;  // all instances of this size
+  };
+  std::vector<Group> groups;
+  std::vector<int> hstate;     // last read retirement flags
+  hipStream_t cap, cap2;
+  hipEvent_t fork, join;
+  hipGraphExec_t graph;
+  int graph_poll;              // steps per replay of `graph`
+  double graph_tol;
+  int graph_consecutive;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t poll, state, below, steps, first, resid, total;
+  std::vector<size_t> ws;  // per-instance workspace offsets
+};
+
+int batch_layout(int n, const fftlb_config* cfgs, BatchLayout* out) {
+  BatchLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.poll = take(n * sizeof(PollInfo));
+  L.state = take(n * sizeof(int));
+  L.below = take(n * sizeof(int));
+  L.steps = take(n * sizeof(long long));
+  L.first = take(n * sizeof(long long));
+  L.resid = take(n * sizeof(double));
+  for (int i = 0; i < n; ++i) {
+    if (!config_ok(&cfgs[i])) return FFTLB_EINVAL;
+    L.ws.push_back(take(make_layout(cfgs[i].nx, cfgs[i].ny).total));
+  }
+  L.total = o;
+  *out = L;
+  return FFTLB_OK;
+}
+
+// Running instances per grid size: their ids and instance pointers (kept alive in `ids`
+// and `ptrs` while the launches are captured) and one launch per size.
+void batch_launches(fftlb_batch* b, std::vector<std::vector<int>>* ids, std::vector<std::vector<const Inst*>>* ptrs,
+                    std::vector<StepLaunch>* out) {
+  ids->assign(b->groups.size(), {});
+  ptrs->assign(b->groups.size(), {});
+  out->clear();
+  for (size_t k = 0; k < b->groups.size(); ++k)
+    for (int i : b->groups[k].members)
+      if (b->hstate[i] == 0) {
+        (*ids)[k].push_back(i);
+        (*ptrs)[k].push_back(&b->inst[i]->I);
+      }
+  for (size_t k = 0; k < b->groups.size(); ++k) {
+    const auto& g = b->groups[k];
+    if ((*ids)[k].empty()) continue;
+    out->push_back(StepLaunch{(*ptrs)[k].data(), (*ids)[k].data(), (int)(*ids)[k].size(), b->st.state, g.nx, g.ny,
+                              g.tw, g.nblk, g.plan});
+  }
+}
+
+int batch_capture(fftlb_batch* b, int poll, double tol, int consecutive) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  std::vector<std::vector<int>> ids;
+  std::vector<std::vector<const Inst*>> ptrs;
+  std::vector<StepLaunch> Ls;
+  batch_launches(b, &ids, &ptrs, &Ls);
+  if (Ls.empty()) return FFTLB_OK;
+  RC_TRY(make_streams(&b->cap, &b->cap2, &b->fork, &b->join));
+  RC_TRY(capture_graph(
+      b->cap,
+      [&]() {
+        for (int i = 0; i < poll; ++i)
+          RC_TRY(enqueue_step_forked(Ls.data(), (int)Ls.size(), b->cap, b->cap2, b->fork, b->join));
+        hipLaunchKernelGGL(k_batch_poll, dim3(b->n), dim3(256), 0, b->cap, b->dpoll, b->st, poll, tol, consecutive);
+        return FFTLB_OK;
+      },
+      &b->graph));
+  b->graph_poll = poll;
+  b->graph_tol = tol;
+  b->graph_consecutive = consecutive;
+  return FFTLB_OK;
+}
+
+int read_state(fftlb_batch* b, hipStream_t s, int* running) {
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(b->hstate.data(), b->st.state, b->n * sizeof(int), hipMemcpyDeviceToHost));
+  *running = (int)std::count(b->hstate.begin(), b->hstate.end(), 0);
   return FFTLB_OK;
 }
 
@@ -444,6 +644,7 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   h->tw = tile_width(cfg->nx);
   h->L = L;
   h->steps = 0;
+  h->plan = default_plan(h->ny, h->tw);
   h->g1 = h->gN = nullptr;
   h->cap = h->cap2 = nullptr;
   h->fork = h->join = nullptr;
@@ -452,32 +653,35 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
     return FFTLB_EHIP;
   }
   char* ws = static_cast<char*>(workspace);
-  Planes& P = h->P;
+  Inst& I = h->I;
+  I = Inst{};
+  Planes& P = I.P;
   P.f = reinterpret_cast<float*>(ws + L.f);
+  const long hp = (long)h->nx * h->ny / 2;  // complex values per spectral plane
   P.sf = reinterpret_cast<float2*>(ws + L.sf);
-  P.sm = reinterpret_cast<float2*>(ws + L.sm);
-  P.s1 = reinterpret_cast<float2*>(ws + L.s1);
-  P.s2i = reinterpret_cast<float2*>(ws + L.s2i);
-  P.s2o = reinterpret_cast<float2*>(ws + L.s2o);
+  I.spec = reinterpret_cast<float2*>(ws + L.spec);
+  P.sm = I.spec + SB_SM * hp;
+  P.s1 = I.spec + SB_S1 * hp;
+  P.s2i = I.spec + SB_S2I * hp;
+  P.s2o = I.spec + SB_S2O * hp;
   P.macro = reinterpret_cast<float*>(ws + L.macro);
   P.cpl = reinterpret_cast<float*>(ws + L.cpl);
   P.twx = reinterpret_cast<const float2*>(ws + L.twx);
   P.kapx = reinterpret_cast<const float*>(ws + L.kx);
   P.part_d = reinterpret_cast<double*>(ws + L.pd);
   P.part_f = reinterpret_cast<float*>(ws + L.pf);
-  P.in0 = P.in1 = P.in2 = P.in3 = nullptr;
   P.nx = h->nx;
   P.ny = h->ny;
   P.plane = (long)h->nx * h->ny;
   P.sg.ny = h->ny;
   P.sg.tw = h->tw;
   P.sg.log2tw = ilog2(h->tw);
-  h->twy = reinterpret_cast<float2*>(ws + L.twy);
-  h->kapx = reinterpret_cast<float*>(ws + L.kx);
-  h->kapy = reinterpret_cast<float*>(ws + L.ky);
-  h->nblk_rows = h->ny / row_rows_per_block(h->nx);
+  I.twy = reinterpret_cast<const float2*>(ws + L.twy);
+  I.kapy = reinterpret_cast<const float*>(ws + L.ky);
+  I.nblk = h->ny / row_rows_per_block(h->nx);
+  h->self = &h->I;
 
-  Model& M = h->M;
+  Model& M = I.M;
   M.dt = (float)cfg->dt;
   M.omega = std::isinf(cfg->tau) ? 0.0f : (float)(cfg->dt / cfg->tau);
   M.K = (float)cfg->K;
@@ -502,42 +706,30 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   int rc = FFTLB_OK;
   {
     DeviceGuard dg(h->device);
-    auto fail = [&](int code) {
-      if (h->cap) (void)hipStreamDestroy(h->cap);
-      if (h->cap2) (void)hipStreamDestroy(h->cap2);
-      if (h->fork) (void)hipEventDestroy(h->fork);
-      if (h->join) (void)hipEventDestroy(h->join);
-      delete h;
-      return code;
-    };
-    // default-priority streams; events without timing
-    if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&h->cap2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess) {
-      set_error("stream/event creation", hipErrorUnknown);
-      return fail(FFTLB_EHIP);
-    }
     hipError_t e;
     if ((e = hipMemcpyAsync(ws + L.twx, twx.data(), twx.size() * sizeof(float2), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(ws + L.twy, twy.data(), twy.size() * sizeof(float2), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(ws + L.kx, kx.data(), kx.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(ws + L.ky, ky.data(), ky.size() * sizeof(float), hipMemcpyHostToDevice, s))) {
       set_error("table upload", e);
-      return fail(FFTLB_EHIP);
+      delete h;
+      return FFTLB_EHIP;
     }
-    Planes Pi = P;
-    Pi.in0 = rho0;
-    Pi.in1 = ux0;
-    Pi.in2 = uy0;
-    Pi.in3 = T0;
-    rc = dispatch_nx<RowCollideMode<MODE_INIT>::K>(h->nx, s, h, Pi);
+    Inputs in{};
+    in.a[0] = rho0;
+    in.a[1] = ux0;
+    in.a[2] = uy0;
+    in.a[3] = T0;
+    rc = rows(single_launch(h, h->plan), RK_INIT, in, s);
     if (rc == FFTLB_OK) rc = check_launch("init kernel");
     if (rc == FFTLB_OK && (e = hipStreamSynchronize(s)) != hipSuccess) {
       set_error("hipStreamSynchronize", e);
       rc = FFTLB_EHIP;
     }
-    if (rc != FFTLB_OK) return fail(rc);
+    if (rc != FFTLB_OK) {
+      delete h;
+      return rc;
+    }
   }
   *out = h;
   return FFTLB_OK;
@@ -548,9 +740,8 @@ int fftlb_step(fftlb_handle* h, int64_t nsteps, void* stream) {
   if (nsteps == 0) return FFTLB_OK;
   DeviceGuard dg(h->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  int rc;
-  if (!h->g1 && (rc = capture(h, 1, &h->g1))) return rc;
-  if (nsteps >= kStepsPerGraph && !h->gN && (rc = capture(h, kStepsPerGraph, &h->gN))) return rc;
+  if (!h->g1) RC_TRY(capture(h, 1, &h->g1));
+  if (nsteps >= kStepsPerGraph && !h->gN) RC_TRY(capture(h, kStepsPerGraph, &h->gN));
   int64_t left = nsteps;
   while (left >= kStepsPerGraph) {
     HIP_TRY(hipGraphLaunch(h->gN, s));
@@ -568,10 +759,8 @@ int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream) 
   if (!h || stage < 0 || stage >= kNumStages || reps < 0) return FFTLB_EINVAL;
   DeviceGuard dg(h->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  for (int i = 0; i < reps; ++i) {
-    const int rc = enqueue_stage(h, stage, s);
-    if (rc) return rc;
-  }
+  const StepLaunch L = single_launch(h, h->plan);
+  for (int i = 0; i < reps; ++i) RC_TRY(enqueue_stage(L, stage, s));
   if (stage == kNumStages - 1) h->steps += reps;
   return check_launch("run_stage");
 }
@@ -583,16 +772,15 @@ int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, d
   const size_t pb = (size_t)h->nx * h->ny * sizeof(float);
   float* outs[4] = {rho, ux, uy, T};
   for (int i = 0; i < 4; ++i)
-    if (outs[i]) HIP_TRY(hipMemcpyAsync(outs[i], h->P.macro + (size_t)i * h->nx * h->ny, pb,
-                                        hipMemcpyDeviceToDevice, s));
+    if (outs[i])
+      HIP_TRY(hipMemcpyAsync(outs[i], h->I.P.macro + (size_t)i * h->nx * h->ny, pb, hipMemcpyDeviceToDevice, s));
   if (globals) {
-    int rc;
-    if ((rc = launch_stage1(h, s))) return rc;
-    if ((rc = dispatch_nx<RowStage2>(h->nx, s, h))) return rc;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->P.part_d, h->nblk_rows, h->P.part_f,
-                       h->nblk_rows, h->steps > 0 ? 1 : 0, h->cfg.dx * h->cfg.dy, h->cfg.dt, (double)h->steps,
-                       globals);
-    if ((rc = check_launch("moments"))) return rc;
+    const StepLaunch L = single_launch(h, h->plan);
+    RC_TRY(enqueue_stage(L, 1, s));
+    RC_TRY(enqueue_stage(L, 2, s));
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->I.P.part_d, h->I.nblk, h->I.P.part_f, h->I.nblk,
+                       h->steps > 0 ? 1 : 0, h->cfg.dx * h->cfg.dy, h->cfg.dt, (double)h->steps, globals);
+    RC_TRY(check_launch("moments"));
   }
   return FFTLB_OK;
 }
@@ -600,7 +788,7 @@ int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, d
 int fftlb_get_state(fftlb_handle* h, float* f, void* stream) {
   if (!h || !f) return FFTLB_EINVAL;
   DeviceGuard dg(h->device);
-  HIP_TRY(hipMemcpyAsync(f, h->P.f, (size_t)33 * h->nx * h->ny * sizeof(float), hipMemcpyDeviceToDevice,
+  HIP_TRY(hipMemcpyAsync(f, h->I.P.f, (size_t)33 * h->nx * h->ny * sizeof(float), hipMemcpyDeviceToDevice,
                          reinterpret_cast<hipStream_t>(stream)));
   return FFTLB_OK;
 }
@@ -608,29 +796,43 @@ int fftlb_get_state(fftlb_handle* h, float* f, void* stream) {
 int fftlb_set_state(fftlb_handle* h, const float* f, void* stream) {
   if (!h || !f) return FFTLB_EINVAL;
   DeviceGuard dg(h->device);
-  Planes Ps = h->P;
-  Ps.in0 = f;
-  int rc = dispatch_nx<RowCollideMode<MODE_SET>::K>(h->nx, reinterpret_cast<hipStream_t>(stream), h, Ps);
-  if (rc == FFTLB_OK) rc = check_launch("set_state");
-  return rc;
+  Inputs in{};
+  in.a[0] = f;
+  RC_TRY(rows(single_launch(h, h->plan), RK_SET, in, reinterpret_cast<hipStream_t>(stream)));
+  return check_launch("set_state");
 }
 
 int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, void* stream) {
   if (!h || !g || !out || g == out || op < 0 || op > 2) return FFTLB_EINVAL;
   DeviceGuard dg(h->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  float2* src = h->P.s1;
-  float2* dst = h->P.s1 + (long)h->nx * h->ny / 2;
-  int rc;
-  if ((rc = dispatch_nx<RowFwdReal>(h->nx, s, h, g, (const float*)nullptr, src, (float2*)nullptr))) return rc;
-  ColLaunch L{};
+  float2* src = h->I.P.s1;
+  float2* dst = h->I.P.s1 + (long)h->nx * h->ny / 2;
+  RC_TRY(rows_forward_real(h, g, src, s));
   // the derivative entry point runs every operator through the full 2D pass
-  const int kind = op == 0 ? MK_IKX : (op == 1 ? MK_IKY : MK_LAP);
-  L.g[0] = group({src}, {dst}, {{kind}});
-  if ((rc = dispatch_ny<ColMulti>(h->ny, multi_cols(h->ny, h->tw), s, h, L, 1, 1))) return rc;
-  if ((rc = dispatch_nx<RowInvReal>(h->nx, s, h, (const float2*)dst, (const float2*)nullptr, out, (float*)nullptr)))
-    return rc;
+  RC_TRY(col_multi(single_launch(h, h->plan), derivative_group(op), 1, s));
+  RC_TRY(rows_inverse_real(h, dst, out, s));
   return check_launch("derivative");
+}
+
+int fftlb_get_plan(const fftlb_handle* h, fftlb_plan* plan) {
+  if (!h || !plan) return FFTLB_EINVAL;
+  *plan = fftlb_plan{h->plan.conv_cw, h->plan.multi_cw, h->plan.radix, 0};
+  return FFTLB_OK;
+}
+
+int fftlb_set_plan(fftlb_handle* h, const fftlb_plan* plan) {
+  if (!h || !plan || plan->reserved != 0) return FFTLB_EINVAL;
+  return set_plan(h, ColPlan{plan->conv_cols, plan->multi_cols, plan->col_radix});
+}
+
+int fftlb_autotune(fftlb_handle* h, int32_t reps, const char* cache_path, void* stream, fftlb_plan* best) {
+  if (!h || reps < 1 || reps > 10000) return FFTLB_EINVAL;
+  DeviceGuard dg(h->device);
+  ColPlan p;
+  RC_TRY(autotune(h, reps, cache_path, reinterpret_cast<hipStream_t>(stream), &p));
+  if (best) *best = fftlb_plan{p.conv_cw, p.multi_cw, p.radix, 0};
+  return FFTLB_OK;
 }
 
 int fftlb_destroy(fftlb_handle* h) {
@@ -639,14 +841,180 @@ int fftlb_destroy(fftlb_handle* h) {
     DeviceGuard dg(h->device);
     // graphs may still be running on the caller's streams
     (void)hipDeviceSynchronize();
-    if (h->g1) (void)hipGraphExecDestroy(h->g1);
-    if (h->gN) (void)hipGraphExecDestroy(h->gN);
+    drop_graphs(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     if (h->cap2) (void)hipStreamDestroy(h->cap2);
     if (h->fork) (void)hipEventDestroy(h->fork);
     if (h->join) (void)hipEventDestroy(h->join);
   }
   delete h;
+  return FFTLB_OK;
+}
+
+int fftlb_batch_workspace_bytes(int32_t n, const fftlb_config* cfgs, size_t* bytes) {
+  if (n < 1 || n > FFTLB_MAX_BATCH || !cfgs || !bytes) return FFTLB_EINVAL;
+  BatchLayout L;
+  RC_TRY(batch_layout(n, cfgs, &L));
+  *bytes = L.total;
+  return FFTLB_OK;
+}
+
+int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, size_t ws_bytes,
+                       const float* const* rho0, const float* const* ux0, const float* const* uy0,
+                       const float* const* T0, void* stream, fftlb_batch** out) {
+  if (!out) return FFTLB_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n > FFTLB_MAX_BATCH || !cfgs || !rho0 || !ux0 || !uy0 || !T0) return FFTLB_EINVAL;
+  BatchLayout L;
+  RC_TRY(batch_layout(n, cfgs, &L));
+  for (int i = 0; i < n; ++i)
+    if (!rho0[i] || !ux0[i] || !uy0[i] || !T0[i]) return FFTLB_EINVAL;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % FFTLB_WORKSPACE_ALIGN)) return FFTLB_ENOSPC;
+  if (ws_bytes < L.total) return FFTLB_ENOSPC;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+
+  fftlb_batch* b = new (std::nothrow) fftlb_batch();
+  if (!b) return FFTLB_EINVAL;
+  b->n = n;
+  b->cap = b->cap2 = nullptr;
+  b->fork = b->join = nullptr;
+  b->graph = nullptr;
+  b->graph_poll = 0;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return FFTLB_EHIP;
+  }
+  b->dpoll = reinterpret_cast<PollInfo*>(ws + L.poll);
+  b->st.state = reinterpret_cast<int*>(ws + L.state);
+  b->st.below = reinterpret_cast<int*>(ws + L.below);
+  b->st.steps = reinterpret_cast<long long*>(ws + L.steps);
+  b->st.first_below = reinterpret_cast<long long*>(ws + L.first);
+  b->st.residual = reinterpret_cast<double*>(ws + L.resid);
+  b->hstate.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const fftlb_config& c = cfgs[i];
+    fftlb_handle* h = nullptr;
+    const size_t wsz = make_layout(c.nx, c.ny).total;
+    const int rc = fftlb_init(&c, ws + L.ws[i], wsz, rho0[i], ux0[i], uy0[i], T0[i], stream, &h);
+    if (rc) {
+      fftlb_batch_destroy(b);
+      return rc;
+    }
+    b->inst.push_back(h);
+    auto g = std::find_if(b->groups.begin(), b->groups.end(),
+                          [&](const fftlb_batch::Group& gg) { return gg.nx == c.nx && gg.ny == c.ny; });
+    if (g == b->groups.end()) {
+      b->groups.push_back(fftlb_batch::Group{c.nx, c.ny, h->tw, h->I.nblk, h->plan, {}});
+      g = b->groups.end() - 1;
+    }
+    g->members.push_back(i);
+  }
+  // poll table and bookkeeping: running, no polls below tol, no steps, first_below = -1
+  std::vector<PollInfo> hp(n);
+  for (int i = 0; i < n; ++i) hp[i] = PollInfo{b->inst[i]->I.P.part_f, b->inst[i]->I.nblk, b->inst[i]->I.M.dt};
+  std::vector<int> zi(n, 0);
+  std::vector<long long> zl(n, 0), ml(n, -1);
+  std::vector<double> zd(n, 0.0);
+  DeviceGuard dg(b->device);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(b->dpoll, hp.data(), n * sizeof(PollInfo), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(b->st.state, zi.data(), n * sizeof(int), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(b->st.below, zi.data(), n * sizeof(int), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(b->st.steps, zl.data(), n * sizeof(long long), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(b->st.first_below, ml.data(), n * sizeof(long long), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(b->st.residual, zd.data(), n * sizeof(double), hipMemcpyHostToDevice, s)) ||
+      (e = hipStreamSynchronize(s))) {
+    set_error("batch upload", e);
+    fftlb_batch_destroy(b);
+    return FFTLB_EHIP;
+  }
+  *out = b;
+  return FFTLB_OK;
+}
+
+int fftlb_batch_autotune(fftlb_batch* b, int32_t reps, const char* cache_path, void* stream) {
+  if (!b || reps < 1 || reps > 10000) return FFTLB_EINVAL;
+  DeviceGuard dg(b->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (auto& g : b->groups) {
+    ColPlan p;
+    RC_TRY(autotune(b->inst[g.members[0]], reps, cache_path, s, &p));
+    g.plan = p;
+    for (int i : g.members) RC_TRY(set_plan(b->inst[i], p));
+  }
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  return FFTLB_OK;
+}
+
+int fftlb_batch_run(fftlb_batch* b, double tol, int32_t consecutive, int32_t poll_every, int64_t max_steps,
+                    void* stream) {
+  if (!b || !(tol >= 0.0) || consecutive < 1 || poll_every < 1 || poll_every > kMaxPollEvery || max_steps < 0)
+    return FFTLB_EINVAL;
+  DeviceGuard dg(b->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int running;
+  RC_TRY(read_state(b, s, &running));
+  int captured_for = -1;  // running instances the current graph was captured for
+  if (b->graph && b->graph_poll == poll_every && b->graph_tol == tol && b->graph_consecutive == consecutive)
+    captured_for = running;
+  int64_t done = 0;
+  while (running > 0 && done < max_steps) {
+    if (running != captured_for) {
+      RC_TRY(batch_capture(b, poll_every, tol, consecutive));
+      captured_for = running;
+    }
+    // two replays per status read keep the device busy while the host checks
+    const int reps = (max_steps - done) > poll_every ? 2 : 1;
+    for (int r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(b->graph, s));
+    done += (int64_t)reps * poll_every;
+    RC_TRY(read_state(b, s, &running));
+  }
+  // per-instance step counters for the instance handles' globals
+  std::vector<long long> steps(b->n);
+  HIP_TRY(hipMemcpy(steps.data(), b->st.steps, b->n * sizeof(long long), hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->n; ++i) b->inst[i]->steps = steps[i];
+  return FFTLB_OK;
+}
+
+int fftlb_batch_status(fftlb_batch* b, int64_t* steps, int64_t* steps_to_tol, double* residual, int32_t* state) {
+  if (!b) return FFTLB_EINVAL;
+  DeviceGuard dg(b->device);
+  HIP_TRY(hipDeviceSynchronize());
+  std::vector<long long> v(b->n), first(b->n);
+  std::vector<int> st(b->n);
+  HIP_TRY(hipMemcpy(v.data(), b->st.steps, b->n * sizeof(long long), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(first.data(), b->st.first_below, b->n * sizeof(long long), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(st.data(), b->st.state, b->n * sizeof(int), hipMemcpyDeviceToHost));
+  if (residual) HIP_TRY(hipMemcpy(residual, b->st.residual, b->n * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->n; ++i) {
+    if (steps) steps[i] = v[i];
+    if (steps_to_tol) steps_to_tol[i] = st[i] == 1 ? first[i] : -1;
+    if (state) state[i] = st[i];
+  }
+  return FFTLB_OK;
+}
+
+int fftlb_batch_instance(fftlb_batch* b, int32_t i, fftlb_handle** h) {
+  if (!b || !h || i < 0 || i >= b->n) return FFTLB_EINVAL;
+  *h = b->inst[i];
+  return FFTLB_OK;
+}
+
+int fftlb_batch_destroy(fftlb_batch* b) {
+  if (!b) return FFTLB_EINVAL;
+  {
+    DeviceGuard dg(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->cap2) (void)hipStreamDestroy(b->cap2);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+  }
+  for (fftlb_handle* h : b->inst) fftlb_destroy(h);
+  delete b;
   return FFTLB_OK;
 }
 

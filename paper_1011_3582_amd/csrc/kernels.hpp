@@ -60,7 +60,7 @@ struct Planes {
   float* f;          // [33][ny][nx]
   float2* sf;        // [32] row spectra of f_1..f_32 (in place: convection spectra after k_col_conv)
   float2* sm;        // [4]  row spectra of rho, ux, uy, T
-  float2* s1;        // [11] stage-1 derivative spectra
+  float2* s1;        // [6]  stage-1 y-derivative spectra
   float2* s2i;       // [5]  stage-2 input spectra
   float2* s2o;       // [3]  stage-2 output spectra: B^x, B^y, G
   float* macro;      // [4][ny][nx] rho, ux, uy, T (real)
@@ -69,14 +69,73 @@ struct Planes {
   const float* kapx; // windowed k_x, nx/2 entries
   double* part_d;    // [blocks][6] stage-2 partials: mass, px, py, energy, max|u|, nonfinite
   float* part_f;     // [blocks][2] collide partials: max |sum_q C_q|, nonfinite
-  const float* in0;  // init: rho0, ux0, uy0, T0 / set: f
-  const float* in1;
-  const float* in2;
-  const float* in3;
   int nx, ny;
   long plane;        // nx * ny
   SpecGeom sg;
 };
+
+// Multiplier kinds of the multi-output column pass.
+enum : int {
+  MK_NONE = 0,
+  MK_IKX = 1,   // i k_x
+  MK_IKY = 2,   // i k_y
+  MK_KXX = 3,   // -k_x^2
+  MK_KYY = 4,   // -k_y^2
+  MK_KXY = 5,   // -k_x k_y
+  MK_LAP = 6,   // -(k_x^2 + k_y^2)
+};
+
+// One derivative group of a column pass: nin input planes, nout output planes, each output
+// the sum over inputs p of kind[o][p] applied to input p.  Planes are indices into an
+// instance's spectral block (the moment, stage-1 and stage-2 spectra, contiguous).
+struct ColGroup {
+  int in[3];
+  int out[6];
+  int nin, nout;
+  int kind[6][3];
+};
+
+struct ColLaunch {
+  ColGroup g[3];
+};
+
+// Kernel arguments are passed by value: pointers inside kernel arguments are known to
+// address global memory, so they compile to global loads and stores (pointers read from a
+// descriptor in device memory would be flat accesses, which also hold up the LDS waits).
+// A launch covers up to kRowSlots (row kernels) or kColSlots (column kernels) instances of
+// one grid size; blockIdx.y (row and convection kernels) or blockIdx.z (derivative column
+// passes) selects the slot.  A single solver is a launch of one slot.
+constexpr int kRowSlots = 8;
+constexpr int kColSlots = 32;
+
+struct RowArgs {
+  Planes P[kRowSlots];
+  Model M[kRowSlots];
+  int id[kRowSlots];   // instance ids, for the retirement flags
+  const int* state;    // per-instance retired flags of a batch (null: none)
+};
+
+struct ColInst {
+  float2* spec;        // convection: the 32 population spectra; derivatives: the spectral block
+  const float2* twy;   // column twiddles, ny entries
+  const float* kapx;   // windowed k_x, nx/2 entries
+  const float* kapy;   // windowed k_y, ny entries
+  int nx, tw, id;
+  float scale;         // 1 / (nx ny)
+};
+
+struct ColArgs {
+  ColInst c[kColSlots];
+  const int* state;
+};
+
+// Inputs of the init (rho0, ux0, uy0, T0) and set-state (f) modes of the collide kernel.
+struct Inputs {
+  const float* a[4];
+};
+
+// True when the instance of a slot has been retired by the batch poll.
+__device__ __forceinline__ bool retired(const int* state, int id) { return state && state[id]; }
 
 // ---------------------------------------------------------------------------
 // Block helpers
@@ -95,6 +154,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ bool nonfinite(float x) { return !(fabsf(x) <= 3.402823466e38f); }
+
+// x as a rounded FP32 value: keeps the compiler from fusing the multiply that produced x
+// into a later add (the moments of f^eq must be those of the stored f, exactly as when
+// the same f is loaded back by the set-state mode).
+__device__ __forceinline__ float rounded(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 
 // Row groups: thread -> (row within block, lane within row).
 template <int NX>
@@ -290,11 +357,17 @@ __device__ __forceinline__ int conv_column_plane(int j) {
   return 8 * k + (r < 3 ? r + 1 : r + 2);
 }
 
-template <int NY, int CW, int NT>
-__global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, const float2* __restrict__ twy,
-                                                 const float* __restrict__ kapx,
-                                                 const float* __restrict__ kapy, int nx, int tw, float scale) {
+template <int NY, int CW, int NT, int R>
+__global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
+  const ColInst& In = A.c[blockIdx.y];
+  if (retired(A.state, In.id)) return;
   extern __shared__ float2 lds[];
+  float2* __restrict__ spec = In.spec;
+  const float2* __restrict__ twy = In.twy;
+  const float* __restrict__ kapx = In.kapx;
+  const float* __restrict__ kapy = In.kapy;
+  const int nx = In.nx, tw = In.tw;
+  const float scale = In.scale;
   const int tid = threadIdx.x;
   const int nsub = (nx / 2) / CW;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -306,7 +379,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, c
     lds[pad(e)] = g[y * tw + c];
   }
   __syncthreads();
-  fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
+  fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
   const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
@@ -315,42 +388,26 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(float2* __restrict__ spec, c
     lds[pad(e)] = make_float2(-m * v.y, m * v.x);
   }
   __syncthreads();
-  fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0)>(lds, 0, 1, twy, tid);
+  fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
   for (int e = tid; e < NY * CW; e += NT) {
     const int y = e / CW, c = e % CW;
     g[y * tw + c] = lds[pad(e)];
   }
 }
 
-// Multiplier kinds of the multi-output column pass.
-enum : int {
-  MK_NONE = 0,
-  MK_IKX = 1,   // i k_x
-  MK_IKY = 2,   // i k_y
-  MK_KXX = 3,   // -k_x^2
-  MK_KYY = 4,   // -k_y^2
-  MK_KXY = 5,   // -k_x k_y
-  MK_LAP = 6,   // -(k_x^2 + k_y^2)
-};
-
-struct ColGroup {
-  const float2* in[3];
-  float2* out[6];
-  int nin, nout;
-  int kind[6][3];
-};
-
-struct ColLaunch {
-  ColGroup g[3];
-};
-
 // Column pass of derivative groups: forward column FFT of nin input spectra, then for
 // each output a linear combination sum_p m_op(kx, ky) X_p, inverse column FFT, store.
-template <int NY, int CW, int NT>
-__global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* __restrict__ twy,
-                                                  const float* __restrict__ kapx,
-                                                  const float* __restrict__ kapy, int nx, int tw, float scale) {
+template <int NY, int CW, int NT, int R>
+__global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
+  const ColInst& In = A.c[blockIdx.z];
+  if (retired(A.state, In.id)) return;
   extern __shared__ float2 lds[];
+  const float2* __restrict__ twy = In.twy;
+  const float* __restrict__ kapx = In.kapx;
+  const float* __restrict__ kapy = In.kapy;
+  const int tw = In.tw;
+  const float scale = In.scale;
+  const long hp = (long)(In.nx / 2) * NY;  // complex values per spectral plane
   const int tid = threadIdx.x;
   const ColGroup& G = L.g[blockIdx.y];
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
@@ -358,14 +415,14 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* 
   constexpr int BLK = NY * CW;  // input p occupies elements [p BLK, (p + 1) BLK)
   constexpr bool AL = is_pow2(NY) && (BLK % 32 == 0);
   for (int p = 0; p < G.nin; ++p) {
-    const float2* g = G.in[p] + off;
+    const float2* g = In.spec + G.in[p] * hp + off;
     for (int e = tid; e < BLK; e += NT) {
       const int y = e / CW, c = e % CW;
       lds[pad(p * BLK + e)] = g[y * tw + c];
     }
   }
   __syncthreads();
-  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true, CW, AL>(lds, p * BLK, 1, twy, tid);
+  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true, CW, AL, R>(lds, p * BLK, 1, twy, tid);
   const int wb = 3 * BLK;  // work block (after the largest input set)
   for (int o = 0; o < G.nout; ++o) {
     for (int e = tid; e < BLK; e += NT) {
@@ -392,8 +449,8 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* 
       lds[pad(wb + e)] = make_float2(re * scale, im * scale);
     }
     __syncthreads();
-    fft_lds<NY, +1, NT, CW, true, CW, AL>(lds, wb, 1, twy, tid);
-    float2* g = G.out[o] + off;
+    fft_lds<NY, +1, NT, CW, true, CW, AL, R>(lds, wb, 1, twy, tid);
+    float2* g = In.spec + G.out[o] * hp + off;
     for (int e = tid; e < BLK; e += NT) {
       const int y = e / CW, c = e % CW;
       g[y * tw + c] = lds[pad(wb + e)];
@@ -409,13 +466,13 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColLaunch L, const float2* 
 // Stage 2: derivatives at the sites, closure of Eqs. (18)-(23), forward row transforms of
 // P1 = S + Lxx, P2 = Lxy, P3 = S + Lyy, gx, gy; C to its plane; diagnostics partials.
 template <int NX>
-__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model M) {
+__device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int blk) {
   extern __shared__ float2 lds[];
   using G = RowGeom<NX>;
   constexpr int J = G::J;
   const int tid = threadIdx.x;
-  const RowThread<NX> rt(tid, blockIdx.x);
-  const int row0 = blockIdx.x * G::RB;
+  const RowThread<NX> rt(tid, blk);
+  const int row0 = blk * G::RB;
   const long rowoff = (long)rt.y * P.nx;
   const long hp = P.plane / 2;
 
@@ -553,11 +610,18 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(Planes P, Model
       um = fmaxf(um, red_f[w][0]);
       bd = fmaxf(bd, red_f[w][1]);
     }
-    double* out = P.part_d + 6 * (long)blockIdx.x;
+    double* out = P.part_d + 6 * (long)blk;
     for (int i = 0; i < 4; ++i) out[i] = sm[i];
     out[4] = um;
     out[5] = bd;
   }
+}
+
+template <int NX>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(RowArgs A) {
+  const int s = blockIdx.y;
+  if (retired(A.state, A.id[s])) return;
+  rows_stage2<NX>(A.P[s], A.M[s], blockIdx.x);
 }
 
 enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
@@ -567,14 +631,14 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 // rho, ux, uy, T for the next step.  The 32 moving populations go in four rounds of one
 // speed group (8 populations, 4 complex row transforms) each.
 template <int NX, int MODE>
-__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Model M) {
+__device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, const Inputs& in, int blk) {
   extern __shared__ float2 lds[];
   using G = RowGeom<NX>;
   constexpr int J = G::J;
   constexpr int GPR = G::NPB / 4;   // speed groups per round
   const int tid = threadIdx.x;
-  const RowThread<NX> rt(tid, blockIdx.x);
-  const int row0 = blockIdx.x * G::RB;
+  const RowThread<NX> rt(tid, blk);
+  const int row0 = blk * G::RB;
   const long rowoff = (long)rt.y * P.nx;
   const long hp = P.plane / 2;
 
@@ -600,7 +664,7 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const long s = rowoff + rt.x(j);
-      site_init(st[j], P.in0[s], P.in1[s], P.in2[s], P.in3[s]);
+      site_init(st[j], in.a[0][s], in.a[1][s], in.a[2][s], in.a[3][s]);
     }
   }
 
@@ -614,9 +678,9 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
     if constexpr (MODE == MODE_STEP) {
       fn = relax_update(st[j], M, P.f[s], feq_rest(st[j]), 0.0f, 0.0f, 0.0f, 0.0f);
     } else if constexpr (MODE == MODE_INIT) {
-      fn = feq_rest(st[j]);
+      fn = rounded(feq_rest(st[j]));
     } else {
-      fn = P.in0[s];
+      fn = in.a[0][s];
     }
     P.f[s] = fn;
     m0[j] = fn;
@@ -626,7 +690,7 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
   // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1)
 #pragma unroll 1
   for (int rd = 0; rd < 4 / GPR; ++rd) {
-    const RowThread<NX> rt(opaque(tid), blockIdx.x);
+    const RowThread<NX> rt(opaque(tid), blk);
     const int q0 = 1 + 8 * GPR * rd;
     float2* S = P.sf + (long)(q0 - 1) * hp;  // spectra of q0 .. q0 + 8 GPR - 1 are consecutive planes
     PairBatchOut<G::NPB> io;
@@ -677,8 +741,8 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
           const int li = rt.at(slot, j);
           float fa, fb;
           if constexpr (MODE == MODE_SET) {
-            fa = P.in0[(long)qa * P.plane + rowoff + x];
-            fb = P.in0[(long)qb * P.plane + rowoff + x];
+            fa = in.a[0][(long)qa * P.plane + rowoff + x];
+            fb = in.a[0][(long)qb * P.plane + rowoff + x];
           } else {
             const float ea = feq_moving(st[j], ge[j], vxa, vya);
             const float eb = feq_moving(st[j], ge[j], vxb, vyb);
@@ -688,8 +752,8 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
               fb = relax_update(st[j], M, fB[x], eb, c.y, vxb, vyb, v2);
               rs[j] += c.x + c.y;
             } else {
-              fa = ea;
-              fb = eb;
+              fa = rounded(ea);
+              fb = rounded(eb);
             }
           }
           fA[x] = fa;
@@ -745,10 +809,17 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(Planes P, Mode
         a = fmaxf(a, red[w][0]);
         bd = fmaxf(bd, red[w][1]);
       }
-      P.part_f[2 * blockIdx.x] = a;
-      P.part_f[2 * blockIdx.x + 1] = bd;
+      P.part_f[2 * blk] = a;
+      P.part_f[2 * blk + 1] = bd;
     }
   }
+}
+
+template <int NX, int MODE>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(RowArgs A, Inputs in) {
+  const int s = blockIdx.y;
+  if (retired(A.state, A.id[s])) return;
+  rows_collide<NX, MODE>(A.P[s], A.M[s], in, blockIdx.x);
 }
 
 // Real plane(s) -> packed row spectra (b may be null).
@@ -789,50 +860,6 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_inverse_real(const flo
     const float2 v = lds[rt.at(0, j)];
     a[s] = v.x;
     if (b) b[s] = v.y;
-  }
-}
-
-// Sum the per-block partials in FP64, in a fixed order, into the 8 globals.
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part_d, int nd,
-                                                  const float* __restrict__ part_f, int nf, int have_step,
-                                                  double cell, double dt, double steps,
-                                                  double* __restrict__ out) {
-  __shared__ double sd[256][4];
-  __shared__ float sf[256][4];
-  const int tid = threadIdx.x;
-  double s[4] = {0, 0, 0, 0};
-  float um = 0.0f, bd = 0.0f, rr = 0.0f;
-  for (int i = tid; i < nd; i += 256) {
-    for (int c = 0; c < 4; ++c) s[c] += part_d[6 * i + c];
-    um = fmaxf(um, (float)part_d[6 * i + 4]);
-    bd = fmaxf(bd, (float)part_d[6 * i + 5]);
-  }
-  if (have_step)
-    for (int i = tid; i < nf; i += 256) {
-      rr = fmaxf(rr, part_f[2 * i]);
-      bd = fmaxf(bd, part_f[2 * i + 1]);
-    }
-  for (int c = 0; c < 4; ++c) sd[tid][c] = s[c];
-  sf[tid][0] = um;
-  sf[tid][1] = bd;
-  sf[tid][2] = rr;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) {
-      for (int c = 0; c < 4; ++c) sd[tid][c] += sd[tid + w][c];
-      for (int c = 0; c < 3; ++c) sf[tid][c] = fmaxf(sf[tid][c], sf[tid + w][c]);
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    out[0] = sd[0][0] * cell;
-    out[1] = sd[0][1] * cell;
-    out[2] = sd[0][2] * cell;
-    out[3] = sd[0][3] * cell;
-    out[4] = (double)sf[0][2] * dt;
-    out[5] = sf[0][0];
-    out[6] = sf[0][1] > 0.0f ? 1.0 : 0.0;
-    out[7] = steps;
   }
 }
 

@@ -1,0 +1,64 @@
+// Launchers of the solver's kernels.  Each is a template over the grid size, explicitly
+// instantiated for every supported size in the kernel translation units (rows_*.hip,
+// cols_*.hip, compiled in parallel); the API layer dispatches on the runtime size.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fftlb.h"
+#include "kernels.hpp"
+
+namespace fftlb {
+
+// Column-pass plan of a grid size: spectral columns per block of the convection pass and
+// of the derivative passes, and the largest radix (8 or 16) of the column transforms.
+struct ColPlan {
+  int conv_cw, multi_cw, radix;
+};
+
+// Host-side description of one solver instance (pointers into its workspace).
+struct Inst {
+  Planes P;
+  Model M;
+  float2* spec;        // spectral block: moment (4), stage-1 (6), stage-2 in (5) and out (3) planes
+  const float2* twy;   // column twiddles
+  const float* kapy;   // windowed k_y
+  int nblk;            // row blocks
+};
+
+// One launch of a step kernel over `ninst` instances of one grid size (split into launches
+// of kRowSlots / kColSlots instances).
+struct StepLaunch {
+  const Inst* const* inst;  // host array of ninst instances
+  const int* id;            // host array of ninst instance ids (null: 0)
+  int ninst;
+  const int* state;         // device array of retired flags (null: none)
+  int nx, ny, tw, nblk;
+  ColPlan plan;
+};
+
+// Block buffers of the column kernels are kept within 64 KB (in float2 elements).
+constexpr int kColLdsElems = 8192;
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Threads of a column block: one butterfly of the largest radix per thread and pass.
+constexpr int col_threads(int ny, int cw, int radix) { return cmin(1024, cmax(64, ny * cw / radix)); }
+
+template <int NY>
+int launch_col_conv(const StepLaunch& L, hipStream_t s);
+template <int NY>
+int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s);
+
+enum : int { RK_STAGE2 = 0, RK_COLLIDE = 1, RK_INIT = 2, RK_SET = 3 };
+template <int NX>
+int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s);
+// real plane(s) -> packed row spectra, and back (b / sb may be null)
+template <int NX>
+int launch_rows_forward_real(int nblk, const float* a, const float* b, float2* sa, float2* sb, SpecGeom sg,
+                             const float2* twx, hipStream_t s);
+template <int NX>
+int launch_rows_inverse_real(int nblk, const float2* sa, const float2* sb, float* a, float* b, SpecGeom sg,
+                             const float2* twx, const float* kapx, hipStream_t s);
+
+}  // namespace fftlb

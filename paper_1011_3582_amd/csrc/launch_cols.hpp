@@ -1,0 +1,98 @@
+// Column-kernel launchers (definitions; see launch.hpp).
+#pragma once
+#include "launch.hpp"
+
+namespace fftlb {
+
+// Arguments of instances [first, first + count) of a launch: the convection pass works on
+// the population spectra, the derivative passes on the spectral block.
+inline ColArgs col_args(const StepLaunch& L, int first, int count, bool conv) {
+  ColArgs a{};
+  a.state = L.state;
+  for (int k = 0; k < count; ++k) {
+    const Inst& I = *L.inst[first + k];
+    a.c[k] = ColInst{conv ? I.P.sf : I.spec, I.twy, I.P.kapx, I.kapy, L.nx, L.tw, L.id ? L.id[first + k] : 0,
+                     I.M.scale};
+  }
+  return a;
+}
+
+template <int NY, int CW, int R>
+int col_conv_plan(const StepLaunch& L, hipStream_t s) {
+  if constexpr (NY * CW > kColLdsElems) {
+    return FFTLB_EINVAL;
+  } else {
+    constexpr int NT = col_threads(NY, CW, R);
+    const int nblocks = 24 * ((L.nx / 2) / CW);  // 24 populations with v_y != 0
+    for (int first = 0; first < L.ninst; first += kColSlots) {
+      const int count = cmin(kColSlots, L.ninst - first);
+      hipLaunchKernelGGL((k_col_conv<NY, CW, NT, R>), dim3(nblocks, count), dim3(NT),
+                         lds_alloc(NY * CW) * sizeof(float2), s, col_args(L, first, count, true));
+    }
+    return FFTLB_OK;
+  }
+}
+
+template <int NY, int CW, int R>
+int col_multi_plan(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+  if constexpr (4 * NY * CW > kColLdsElems) {
+    return FFTLB_EINVAL;
+  } else {
+    constexpr int NT = col_threads(NY, CW, R);
+    for (int first = 0; first < L.ninst; first += kColSlots) {
+      const int count = cmin(kColSlots, L.ninst - first);
+      // three input blocks and one work block
+      hipLaunchKernelGGL((k_col_multi<NY, CW, NT, R>), dim3((L.nx / 2) / CW, ngroups, count), dim3(NT),
+                         lds_alloc(4 * NY * CW) * sizeof(float2), s, col_args(L, first, count, false), groups);
+    }
+    return FFTLB_OK;
+  }
+}
+
+template <int NY, int R>
+int col_conv_cw(const StepLaunch& L, hipStream_t s) {
+  switch (L.plan.conv_cw) {
+    case 1: return col_conv_plan<NY, 1, R>(L, s);
+    case 2: return col_conv_plan<NY, 2, R>(L, s);
+    case 4: return col_conv_plan<NY, 4, R>(L, s);
+    case 8: return col_conv_plan<NY, 8, R>(L, s);
+    case 16: return col_conv_plan<NY, 16, R>(L, s);
+  }
+  return FFTLB_EINVAL;
+}
+
+template <int NY, int R>
+int col_multi_cw(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+  switch (L.plan.multi_cw) {
+    case 1: return col_multi_plan<NY, 1, R>(L, groups, ngroups, s);
+    case 2: return col_multi_plan<NY, 2, R>(L, groups, ngroups, s);
+    case 4: return col_multi_plan<NY, 4, R>(L, groups, ngroups, s);
+    case 8: return col_multi_plan<NY, 8, R>(L, groups, ngroups, s);
+    case 16: return col_multi_plan<NY, 16, R>(L, groups, ngroups, s);
+  }
+  return FFTLB_EINVAL;
+}
+
+template <int NY>
+int launch_col_conv(const StepLaunch& L, hipStream_t s) {
+  switch (L.plan.radix) {
+    case 8: return col_conv_cw<NY, 8>(L, s);
+    case 16: return col_conv_cw<NY, 16>(L, s);
+  }
+  return FFTLB_EINVAL;
+}
+
+template <int NY>
+int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+  switch (L.plan.radix) {
+    case 8: return col_multi_cw<NY, 8>(L, groups, ngroups, s);
+    case 16: return col_multi_cw<NY, 16>(L, groups, ngroups, s);
+  }
+  return FFTLB_EINVAL;
+}
+
+#define FFTLB_INSTANTIATE_COLS(NY)                                    \
+  template int launch_col_conv<NY>(const StepLaunch&, hipStream_t); \
+  template int launch_col_multi<NY>(const StepLaunch&, const ColLaunch&, int, hipStream_t);
+
+}  // namespace fftlb

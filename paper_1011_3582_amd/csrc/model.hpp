@@ -55,8 +55,9 @@ constexpr WeightPoly make_weight_poly() {
   return w;
 }
 
-__constant__ VelTable c_vel = make_vel_table();
-__constant__ WeightPoly c_wpoly = make_weight_poly();
+// internal linkage: every translation unit that launches kernels holds its own copy
+static __constant__ VelTable c_vel = make_vel_table();
+static __constant__ WeightPoly c_wpoly = make_weight_poly();
 
 // Scalar parameters handed to the kernels by value.
 struct Model {

@@ -42,6 +42,15 @@ class Config(ctypes.Structure):
                 ("filter_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Plan(ctypes.Structure):
+    """Mirror of struct fftlb_plan: column-pass tile widths and radix."""
+    _fields_ = [("conv_cols", ctypes.c_int32), ("multi_cols", ctypes.c_int32), ("col_radix", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.conv_cols, self.multi_cols, self.col_radix)
+
+
 @dataclasses.dataclass
 class Params:
     """Model parameters; defaults are the paper's (Sec. 3.5 list, k4 window) with the
@@ -69,7 +78,20 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     cfgp = ctypes.POINTER(Config)
+    planp = ctypes.POINTER(Plan)
+    fpp = ctypes.POINTER(ctypes.c_void_p)
     sig = {
+        "fftlb_get_plan": (ctypes.c_int, [vp, planp]),
+        "fftlb_set_plan": (ctypes.c_int, [vp, planp]),
+        "fftlb_autotune": (ctypes.c_int, [vp, i32, ctypes.c_char_p, vp, planp]),
+        "fftlb_batch_workspace_bytes": (ctypes.c_int, [i32, cfgp, ctypes.POINTER(sz)]),
+        "fftlb_batch_create": (ctypes.c_int, [i32, cfgp, vp, sz, fpp, fpp, fpp, fpp, vp, ctypes.POINTER(vp)]),
+        "fftlb_batch_autotune": (ctypes.c_int, [vp, i32, ctypes.c_char_p, vp]),
+        "fftlb_batch_run": (ctypes.c_int, [vp, ctypes.c_double, i32, i32, i64, vp]),
+        "fftlb_batch_status": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
+        "fftlb_batch_instance": (ctypes.c_int, [vp, i32, ctypes.POINTER(vp)]),
+        "fftlb_batch_destroy": (ctypes.c_int, [vp]),
         "fftlb_workspace_bytes": (ctypes.c_int, [cfgp, ctypes.POINTER(sz)]),
         "fftlb_init": (ctypes.c_int, [cfgp, vp, sz, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]),
         "fftlb_step": (ctypes.c_int, [vp, i64, vp]),
@@ -153,6 +175,16 @@ class Solver:
                                  _stream(self.device), ctypes.byref(h))
             _check(rc, "fftlb_init")
         self._h = h
+        self._owned = True
+
+    @classmethod
+    def _view(cls, handle, nx, ny, params, device, owner):
+        """A Solver over a handle owned by a Batch (closing it does not destroy the handle)."""
+        v = cls.__new__(cls)
+        v.params, v.device, v.nx, v.ny = params, device, nx, ny
+        v.cfg = params.config(nx, ny)
+        v._h, v._owned, v._owner = handle, False, owner
+        return v
 
     @property
     def handle(self):
@@ -212,10 +244,120 @@ class Solver:
                    "fftlb_derivative")
         return out
 
+    @property
+    def plan(self):
+        p = Plan()
+        _check(_lib.fftlb_get_plan(self.handle, ctypes.byref(p)), "fftlb_get_plan")
+        return p.as_tuple()
+
+    def set_plan(self, conv_cols: int, multi_cols: int, col_radix: int):
+        p = Plan(int(conv_cols), int(multi_cols), int(col_radix), 0)
+        _check(_lib.fftlb_set_plan(self.handle, ctypes.byref(p)), "fftlb_set_plan")
+
+    def autotune(self, reps: int = 10, cache_path: str | None = None):
+        """Time the column plans of this grid size and keep the fastest (fftlb_autotune)."""
+        p = Plan()
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_autotune(self.handle, int(reps), cache_path.encode() if cache_path else None,
+                                       _stream(self.device), ctypes.byref(p)), "fftlb_autotune")
+        return p.as_tuple()
+
     def close(self):
         if self._h is not None:
-            _lib.fftlb_destroy(self._h)
+            if self._owned:
+                _lib.fftlb_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Independent FFT-LB instances of any mix of grid sizes advanced together
+    (fftlb_batch_*): one captured graph of `poll_every` steps of every running instance,
+    with on-device retirement of converged instances.
+
+    fields: a sequence of (rho0, ux0, uy0, T0) tuples of [ny, nx] arrays; params: one
+    Params for all instances or a sequence of them."""
+
+    def __init__(self, fields, params=None, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the FFT-LB solver runs only through its HIP library")
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        n = len(fields)
+        plist = list(params) if isinstance(params, (list, tuple)) else [params or Params()] * n
+        if len(plist) != n:
+            raise ValueError("one Params per instance")
+        self.n = n
+        self.params = plist
+        self.shapes = []
+        cfgs = (Config * n)()
+        with torch.cuda.device(self.device):
+            tensors = []
+            for i, fl in enumerate(fields):
+                rho0 = torch.as_tensor(fl[0])
+                ny, nx = int(rho0.shape[0]), int(rho0.shape[1])
+                self.shapes.append((ny, nx))
+                cfgs[i] = plist[i].config(nx, ny)
+                tensors.append([_field(a, ny, nx, self.device) for a in fl])
+            nbytes = ctypes.c_size_t()
+            _check(_lib.fftlb_batch_workspace_bytes(n, cfgs, ctypes.byref(nbytes)), "fftlb_batch_workspace_bytes")
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            arrs = [(ctypes.c_void_p * n)(*[t[k].data_ptr() for t in tensors]) for k in range(4)]
+            b = ctypes.c_void_p()
+            rc = _lib.fftlb_batch_create(n, cfgs, _ptr(self.workspace), nbytes.value, *arrs, _stream(self.device),
+                                         ctypes.byref(b))
+            _check(rc, "fftlb_batch_create")
+        self._b = b
+
+    @property
+    def handle(self):
+        if self._b is None:
+            raise RuntimeError("batch is closed")
+        return self._b
+
+    def autotune(self, reps: int = 10, cache_path: str | None = None):
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_batch_autotune(self.handle, int(reps), cache_path.encode() if cache_path else None,
+                                             _stream(self.device)), "fftlb_batch_autotune")
+
+    def run(self, tol: float, consecutive: int = 3, poll_every: int = 100, max_steps: int = 10**6):
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_batch_run(self.handle, float(tol), int(consecutive), int(poll_every), int(max_steps),
+                                        _stream(self.device)), "fftlb_batch_run")
+
+    def status(self):
+        """dict of numpy arrays: steps, steps_to_tol (-1 unless converged), residual, state."""
+        import numpy as np
+        n = self.n
+        steps = (ctypes.c_int64 * n)()
+        stt = (ctypes.c_int64 * n)()
+        res = (ctypes.c_double * n)()
+        st = (ctypes.c_int32 * n)()
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_batch_status(self.handle, steps, stt, res, st), "fftlb_batch_status")
+        return {"steps": np.array(steps[:]), "steps_to_tol": np.array(stt[:]), "residual": np.array(res[:]),
+                "state": np.array(st[:])}
+
+    def instance(self, i: int) -> Solver:
+        h = ctypes.c_void_p()
+        _check(_lib.fftlb_batch_instance(self.handle, int(i), ctypes.byref(h)), "fftlb_batch_instance")
+        ny, nx = self.shapes[i]
+        return Solver._view(h, nx, ny, self.params[i], self.device, self)
+
+    def close(self):
+        if self._b is not None:
+            _lib.fftlb_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -95,7 +95,9 @@ int fftlb_step(fftlb_handle* h, int64_t nsteps, void* stream);
  * globals: device double[FFTLB_NGLOBALS] or NULL, receives
  *   [0] mass   = sum rho dx dy          [1] px = sum rho ux dx dy     [2] py = sum rho uy dx dy
  *   [3] energy = sum e_T dx dy with e_T = rho T - a rho^2 + K |grad rho|^2/2 + rho |u|^2/2 (Eq. (17))
- *   [4] residual = dt max_sites |sum_q v_q.grad f_q| of the last step taken (0 before any step)
+ *   [4] residual = dt max_sites |D.(rho u)| of the current state, D the windowed derivative:
+ *       in exact arithmetic the sum over populations of the convection terms of the next
+ *       step, i.e. max |rho^{n+1} - rho^n| (the collision and the force conserve mass)
  *   [5] max |u|   [6] 1 if any non-finite value was seen in the state, else 0   [7] steps taken. */
 int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, double* globals,
                   void* stream);
@@ -152,9 +154,10 @@ int fftlb_destroy(fftlb_handle* h);
  * `poll_every` steps of all running instances followed by an on-device poll that retires
  * converged instances (their blocks exit at once in later launches), so the host only
  * reads the retirement flags between replays.  The residual is global [4] of
- * fftlb_moments: dt max_sites |sum_q v_q.grad f_q| = max |rho^{n+1} - rho^n| in exact
- * arithmetic (the collision and the force conserve mass), formed from the right-hand
- * side so that it does not stagnate at FP32 resolution.
+ * fftlb_moments, dt max_sites |D.(rho u)| = max |rho^{n+1} - rho^n| in exact arithmetic,
+ * formed from the momentum field so that its FP32 floor is set by the rounding of rho u
+ * (far below 1e-8 at the paper's dt), not by differences of stored densities or by the
+ * rounding of the 32 convection terms whose sum it is.
  * ------------------------------------------------------------------------------------ */
 #define FFTLB_MAX_BATCH 1024
 typedef struct fftlb_batch fftlb_batch;

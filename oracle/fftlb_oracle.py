@@ -404,3 +404,12 @@ def residual(conv, p: Params) -> float:
     """dt max_sites |sum_q C_q|: the density change per step carried by convection
     (the collision and the force conserve mass at every site, Eqs. (7), (11))."""
     return float(p.dt * np.abs(conv.sum(axis=0)).max())
+
+
+def momentum_residual(f, p: Params) -> float:
+    """dt max_sites |D_x(rho u_x) + D_y(rho u_y)| of the state f: the same quantity as
+    residual() of the next step's convection terms, because the windowed derivative is
+    linear and sum_q v_q f_q = rho u (Eq. (8))."""
+    rho, ux, uy, _ = moments(f)
+    D = Deriv(f.shape[1], f.shape[2], p)
+    return float(p.dt * np.abs(D.x(rho * ux) + D.y(rho * uy)).max())

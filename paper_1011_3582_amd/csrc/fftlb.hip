@@ -185,8 +185,16 @@ ColLaunch derivative_group(int op) {
   return d;
 }
 
+// Residual pass: D.j = D_x j_x + D_y j_y from the momentum spectra in s1 planes 0, 1 into plane 2.
+ColLaunch divergence_group() {
+  ColLaunch d{};
+  d.g[0] = group({SB_S1, SB_S1 + 1}, {SB_S1 + 2}, {{MK_IKX, MK_IKY}});
+  return d;
+}
+
 const ColLaunch kStage1 = stage1_groups();
 const ColLaunch kStage2 = stage2_groups();
+const ColLaunch kDivJ = divergence_group();
 
 }  // namespace
 
@@ -302,6 +310,14 @@ int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
     case 4: return rows(L, RK_COLLIDE, Inputs{}, s);
   }
   return FFTLB_EINVAL;
+}
+
+// Residual of the current state: dt max |D.(rho u)| and a non-finite flag, into the
+// per-block partials (uses the stage-1 spectral planes, free between steps).
+int enqueue_residual(const StepLaunch& L, hipStream_t s) {
+  RC_TRY(rows(L, RK_MOMENTUM, Inputs{}, s));
+  RC_TRY(col_multi(L, kDivJ, 1, s));
+  return rows(L, RK_RESIDUAL, Inputs{}, s);
 }
 
 // One step of every launch group in `Ls`, as captured into a graph: the convection column
@@ -599,6 +615,7 @@ int batch_capture(fftlb_batch* b, int poll, double tol, int consecutive) {
       [&]() {
         for (int i = 0; i < poll; ++i)
           RC_TRY(enqueue_step_forked(Ls.data(), (int)Ls.size(), b->cap, b->cap2, b->fork, b->join));
+        for (const StepLaunch& L : Ls) RC_TRY(enqueue_residual(L, b->cap));
         hipLaunchKernelGGL(k_batch_poll, dim3(b->n), dim3(256), 0, b->cap, b->dpoll, b->st, poll, tol, consecutive);
         return FFTLB_OK;
       },
@@ -778,8 +795,9 @@ int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, d
     const StepLaunch L = single_launch(h, h->plan);
     RC_TRY(enqueue_stage(L, 1, s));
     RC_TRY(enqueue_stage(L, 2, s));
+    RC_TRY(enqueue_residual(L, s));
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->I.P.part_d, h->I.nblk, h->I.P.part_f, h->I.nblk,
-                       h->steps > 0 ? 1 : 0, h->cfg.dx * h->cfg.dy, h->cfg.dt, (double)h->steps, globals);
+                       h->cfg.dx * h->cfg.dy, h->cfg.dt, (double)h->steps, globals);
     RC_TRY(check_launch("moments"));
   }
   return FFTLB_OK;

@@ -68,7 +68,7 @@ struct Planes {
   const float2* twx; // row twiddles, nx entries
   const float* kapx; // windowed k_x, nx/2 entries
   double* part_d;    // [blocks][6] stage-2 partials: mass, px, py, energy, max|u|, nonfinite
-  float* part_f;     // [blocks][2] collide partials: max |sum_q C_q|, nonfinite
+  float* part_f;     // [blocks][2] residual-pass partials: max |D.(rho u)|, nonfinite
   int nx, ny;
   long plane;        // nx * ny
   SpecGeom sg;
@@ -668,8 +668,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     }
   }
 
-  float m0[J], mx[J], my[J], me[J], rs[J];
-  int bad = 0;
+  float m0[J], mx[J], my[J], me[J];
   // rest particle
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -684,7 +683,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     }
     P.f[s] = fn;
     m0[j] = fn;
-    mx[j] = my[j] = me[j] = rs[j] = 0.0f;
+    mx[j] = my[j] = me[j] = 0.0f;
   }
   // moving populations: each round covers GPR speed groups (8 GPR populations, 4 GPR
   // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1)
@@ -750,7 +749,6 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
               const float2 c = lds[li];
               fa = relax_update(st[j], M, fA[x], ea, c.x, vxa, vya, v2);
               fb = relax_update(st[j], M, fB[x], eb, c.y, vxb, vyb, v2);
-              rs[j] += c.x + c.y;
             } else {
               fa = rounded(ea);
               fb = rounded(eb);
@@ -771,7 +769,6 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     rows_forward_batch<NX, G::NPB>(lds, io, P.sg, P.twx, row0, tid);
   }
   // moments of the new state and their row spectra
-  float rmax = 0.0f;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const long s = rowoff + rt.x(j);
@@ -783,36 +780,11 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     P.macro[P.plane + s] = ux;
     P.macro[2 * P.plane + s] = uy;
     P.macro[3 * P.plane + s] = T;
-    rmax = fmaxf(rmax, fabsf(rs[j]));
-    // a non-finite population anywhere in the sums makes a moment non-finite
-    bad |= nonfinite(r) | nonfinite(me[j]) | nonfinite(mx[j]) | nonfinite(my[j]);
     lds[rt.at(0, j)] = make_float2(r, ux);
     lds[rt.at(1, j)] = make_float2(uy, T);
   }
   PairBatchOut<2> mo{{P.sm, P.sm + 2 * hp}, {P.sm + hp, P.sm + 3 * hp}};
   rows_forward_batch<NX, 2>(lds, mo, P.sg, P.twx, row0, tid);
-
-  if constexpr (MODE == MODE_STEP) {
-    __shared__ float red[16][2];
-    const int wave = tid / 64, lane = tid % 64;
-    rmax = wave_max(rmax);
-    const float badf = wave_max(bad ? 1.0f : 0.0f);
-    if (lane == 0) {
-      red[wave][0] = rmax;
-      red[wave][1] = badf;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      constexpr int NW = (G::NT + 63) / 64;
-      float a = 0.0f, bd = 0.0f;
-      for (int w = 0; w < NW; ++w) {
-        a = fmaxf(a, red[w][0]);
-        bd = fmaxf(bd, red[w][1]);
-      }
-      P.part_f[2 * blk] = a;
-      P.part_f[2 * blk + 1] = bd;
-    }
-  }
 }
 
 template <int NX, int MODE>
@@ -820,6 +792,75 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(RowArgs A, Inp
   const int s = blockIdx.y;
   if (retired(A.state, A.id[s])) return;
   rows_collide<NX, MODE>(A.P[s], A.M[s], in, blockIdx.x);
+}
+
+// Residual pass, step 1: momentum j = rho u of the current state and its row spectra
+// (into stage-1 spectral planes 0 and 1, free between steps).
+template <int NX>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_momentum(RowArgs A) {
+  const int slot = blockIdx.y;
+  if (retired(A.state, A.id[slot])) return;
+  extern __shared__ float2 lds[];
+  const Planes& P = A.P[slot];
+  const int tid = threadIdx.x;
+  const RowThread<NX> rt(tid, blockIdx.x);
+  const long rowoff = (long)rt.y * P.nx;
+  const long hp = P.plane / 2;
+#pragma unroll
+  for (int j = 0; j < RowGeom<NX>::J; ++j) {
+    const long s = rowoff + rt.x(j);
+    const float r = P.macro[s];
+    lds[rt.at(0, j)] = make_float2(r * P.macro[P.plane + s], r * P.macro[2 * P.plane + s]);
+  }
+  PairBatchOut<1> o{{P.s1}, {P.s1 + hp}};
+  rows_forward_batch<NX, 1>(lds, o, P.sg, P.twx, blockIdx.x * RowGeom<NX>::RB, tid);
+}
+
+// Residual pass, step 3 (after the column pass has formed the spectrum of D.j in stage-1
+// plane 2): inverse row transform, block max |dt D.j| and a non-finite flag into the
+// partials read by the global reduction and the batch poll.  In exact arithmetic D.j is the
+// sum over populations of the convection terms (the transforms are linear), so dt max|D.j|
+// is the density change of the next step; formed from j it carries FP32 rounding of j, not
+// of the 33 much larger population terms.
+template <int NX>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_residual(RowArgs A) {
+  const int slot = blockIdx.y;
+  if (retired(A.state, A.id[slot])) return;
+  extern __shared__ float2 lds[];
+  const Planes& P = A.P[slot];
+  const int tid = threadIdx.x;
+  const RowThread<NX> rt(tid, blockIdx.x);
+  const long hp = P.plane / 2;
+  const float2* a1[1] = {P.s1 + 2 * hp};
+  const float2* b1[1] = {nullptr};
+  rows_inverse_batch<NX, 1>(lds, plain_batch<1>(a1, b1), P.sg, P.twx, P.kapx, blockIdx.x * RowGeom<NX>::RB, tid);
+  float m = 0.0f;
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < RowGeom<NX>::J; ++j) {
+    const float v = lds[rt.at(0, j)].x;
+    m = fmaxf(m, fabsf(v));
+    bad |= nonfinite(v);
+  }
+  __shared__ float red[16][2];
+  const int wave = tid / 64, lane = tid % 64;
+  m = wave_max(m);
+  const float badf = wave_max(bad ? 1.0f : 0.0f);
+  if (lane == 0) {
+    red[wave][0] = m;
+    red[wave][1] = badf;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    constexpr int NW = (RowGeom<NX>::NT + 63) / 64;
+    float a = 0.0f, bd = 0.0f;
+    for (int w = 0; w < NW; ++w) {
+      a = fmaxf(a, red[w][0]);
+      bd = fmaxf(bd, red[w][1]);
+    }
+    P.part_f[2 * blockIdx.x] = a;
+    P.part_f[2 * blockIdx.x + 1] = bd;
+  }
 }
 
 // Real plane(s) -> packed row spectra (b may be null).

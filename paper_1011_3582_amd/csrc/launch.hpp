@@ -50,7 +50,7 @@ int launch_col_conv(const StepLaunch& L, hipStream_t s);
 template <int NY>
 int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s);
 
-enum : int { RK_STAGE2 = 0, RK_COLLIDE = 1, RK_INIT = 2, RK_SET = 3 };
+enum : int { RK_STAGE2 = 0, RK_COLLIDE = 1, RK_INIT = 2, RK_SET = 3, RK_MOMENTUM = 4, RK_RESIDUAL = 5 };
 template <int NX>
 int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s);
 // real plane(s) -> packed row spectra, and back (b / sb may be null)

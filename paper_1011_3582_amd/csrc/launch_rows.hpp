@@ -20,7 +20,7 @@ template <int NX>
 int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s) {
   using G = RowGeom<NX>;
   const size_t lds = G::LDS * sizeof(float2);
-  if (kernel < RK_STAGE2 || kernel > RK_SET) return FFTLB_EINVAL;
+  if (kernel < RK_STAGE2 || kernel > RK_RESIDUAL) return FFTLB_EINVAL;
   for (int first = 0; first < L.ninst; first += kRowSlots) {
     const int count = cmin(kRowSlots, L.ninst - first);
     const dim3 grid(L.nblk, count), block(G::NT);
@@ -30,6 +30,8 @@ int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s
       case RK_COLLIDE: hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP>), grid, block, lds, s, a, in); break;
       case RK_INIT: hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT>), grid, block, lds, s, a, in); break;
       case RK_SET: hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET>), grid, block, lds, s, a, in); break;
+      case RK_MOMENTUM: hipLaunchKernelGGL(k_rows_momentum<NX>, grid, block, lds, s, a); break;
+      case RK_RESIDUAL: hipLaunchKernelGGL(k_rows_residual<NX>, grid, block, lds, s, a); break;
     }
   }
   return FFTLB_OK;

@@ -6,7 +6,7 @@ namespace fftlb {
 
 // Sum the per-block partials in FP64, in a fixed order, into the 8 globals.
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part_d, int nd,
-                                                  const float* __restrict__ part_f, int nf, int have_step,
+                                                  const float* __restrict__ part_f, int nf,
                                                   double cell, double dt, double steps,
                                                   double* __restrict__ out) {
   __shared__ double sd[256][4];
@@ -19,11 +19,10 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     um = fmaxf(um, (float)part_d[6 * i + 4]);
     bd = fmaxf(bd, (float)part_d[6 * i + 5]);
   }
-  if (have_step)
-    for (int i = tid; i < nf; i += 256) {
-      rr = fmaxf(rr, part_f[2 * i]);
-      bd = fmaxf(bd, part_f[2 * i + 1]);
-    }
+  for (int i = tid; i < nf; i += 256) {
+    rr = fmaxf(rr, part_f[2 * i]);
+    bd = fmaxf(bd, part_f[2 * i + 1]);
+  }
   for (int c = 0; c < 4; ++c) sd[tid][c] = s[c];
   sf[tid][0] = um;
   sf[tid][1] = bd;
@@ -59,13 +58,13 @@ struct BatchState {
 
 // Where the poll finds an instance's collide partials.
 struct PollInfo {
-  const float* part_f;  // [nblk][2] max |sum_q C_q|, non-finite flag
+  const float* part_f;  // [nblk][2] max |D.(rho u)|, non-finite flag
   int nblk;
   float dt;
 };
 
-// One block per instance, after `nsteps` steps of every running instance: residual of the
-// last step from the collide partials (the same quantity as global [4]), and retirement
+// One block per instance, after `nsteps` steps of every running instance and the residual
+// pass: the residual (the same quantity as global [4]), and retirement
 // once it has stayed below `tol` for `consecutive` polls, or at once on a non-finite value.
 __global__ __launch_bounds__(256) void k_batch_poll(const PollInfo* __restrict__ info, BatchState b, int nsteps,
                                                     double tol, int consecutive) {

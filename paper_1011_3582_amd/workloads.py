@@ -34,8 +34,24 @@ RHO_CRIT = 1.0 / (3.0 * EOS_B)          # 0.833333...
 # them with the oracle's Maxwell construction.
 COEXISTENCE = {
     0.80: (0.199722, 1.610588),
+    0.81: (0.211738, 1.590877),
+    0.82: (0.224370, 1.570606),
+    0.83: (0.237663, 1.549730),
+    0.84: (0.251667, 1.528198),
     0.85: (0.266442, 1.505950),
+    0.86: (0.282055, 1.482919),
+    0.87: (0.298589, 1.459022),
+    0.88: (0.316139, 1.434162),
+    0.89: (0.334823, 1.408223),
     0.90: (0.354785, 1.381059),
+    0.91: (0.376205, 1.352489),
+    0.92: (0.399317, 1.322280),
+    0.93: (0.424428, 1.290125),
+    0.94: (0.451958, 1.255602),
+    0.95: (0.482512, 1.218106),
+    0.96: (0.517018, 1.176710),
+    0.97: (0.557031, 1.129857),
+    0.98: (0.605576, 1.074522),
 }
 
 
@@ -165,3 +181,28 @@ def model_params(**overrides):
 
 def thermal_speed(T) -> float:
     return math.sqrt(float(np.max(T)))
+
+
+# Batched workload: independent instances of uneven grid sizes (temperature sweep and
+# droplet-radius sweep, the paper's two benchmark set-ups of Sec. 4).
+BATCH_SIZES = (128, 192, 256, 384, 512)
+
+
+def batch_instances(n=64, seed=3, sizes=BATCH_SIZES):
+    """n instances, each drawn independently: grid N x N with N uniform over `sizes`;
+    T / T_crit uniform over 0.80, 0.81, ..., 0.98 (the coexistence table); a droplet of
+    radius uniform over 10..60 grid units (at most 0.35 N, so that it stays clear of its
+    periodic images) or a planar slab (probability 1/2 each); tanh width 4, u = 0, no noise.
+    Returns a list of (kind, N, t_ratio, radius, Fields)."""
+    rng = np.random.default_rng(seed)
+    temps = sorted(COEXISTENCE)
+    out = []
+    for _ in range(n):
+        N = int(rng.choice(sizes))
+        t = float(temps[int(rng.integers(len(temps)))])
+        if rng.uniform() < 0.5:
+            R = float(min(int(rng.integers(10, 61)), int(0.35 * N)))
+            out.append(("droplet", N, t, R, droplet(N, N, radius=R, t_ratio=t, width=4.0)))
+        else:
+            out.append(("slab", N, t, 0.0, slab(N, N, t_ratio=t, width=4.0, noise=0.0)))
+    return out

@@ -83,3 +83,32 @@ def test_step_reduces_to_bgk_without_gradients_of_force_inputs():
     parts = O.step_parts(f0, p)
     assert abs(parts.I.sum()) < 1e-12
     assert abs(parts.conv.sum()) < 1e-9
+
+
+def test_momentum_residual_equals_convection_sum():
+    """dt max|D.(rho u)| of a state equals dt max|sum_q C_q| of its convection terms: the
+    windowed derivative is linear and sum_q v_q f_q = rho u; two independent routes."""
+    p = _params()
+    rng = np.random.default_rng(11)
+    ny, nx = 24, 32
+    x = np.arange(nx)[None, :] * np.ones((ny, 1))
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * 3 * x / nx)
+    f = O.feq(rho, 0.05 * np.cos(2 * np.pi * x / nx), np.zeros((ny, nx)), np.full((ny, nx), 1.2))
+    f = f * (1.0 + 0.01 * rng.uniform(-1, 1, f.shape))      # off equilibrium, all modes present
+    parts = O.step_parts(f, p)
+    r_conv = O.residual(parts.conv, p)
+    r_mom = O.momentum_residual(f, p)
+    assert r_conv > 1e-6
+    assert r_mom == pytest.approx(r_conv, rel=1e-12)
+
+
+def test_momentum_residual_of_a_single_mode():
+    """A momentum field rho u_x = A sin(k x) with rho = 1 has D.(rho u) = A k_m cos(k x)."""
+    p = _params()
+    ny, nx, n = 8, 64, 5
+    x = np.arange(nx)[None, :] * np.ones((ny, 1))
+    k = 2 * np.pi * n / (nx * p.dx)
+    A = 0.01
+    f = O.feq(np.ones((ny, nx)), A * np.sin(k * x * p.dx), np.zeros((ny, nx)), np.full((ny, nx), 1.0))
+    km = O.kappa(nx, p.dx, p.m)[n]
+    assert O.momentum_residual(f, p) == pytest.approx(p.dt * A * km, rel=1e-9)

@@ -100,6 +100,58 @@ def write_traffic(fetch_csv, write_csv, calib_mib, nx, ny):
     print(json.dumps(rec))
 
 
+def batch_leg(args, F, W, dev):
+    """64 independent instances of uneven grid sizes (128..512 squared; droplets and slabs at
+    0.80..0.98 T_c) advanced together: aggregate site-velocity updates per second over
+    `--batch-steps` steps (residual tolerance 0, nothing retires), and optionally the
+    steps and wall time until every instance's residual is below `--equilibrium`."""
+    import numpy as np
+    import torch
+    inst = W.batch_instances(64, seed=3)
+    fields = [tuple(torch.from_numpy(a) for a in (f.rho, f.ux, f.uy, f.T)) for _, _, _, _, f in inst]
+    sites = sum(N * N for _, N, _, _, _ in inst)
+    print(f"[bench] batch: {len(inst)} instances, {sites} sites", file=sys.stderr, flush=True)
+    b = F.Batch(fields, device=dev)
+    if not args.no_autotune:
+        b.autotune(reps=5)
+    b.run(tol=0.0, poll_every=100, max_steps=100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(tol=0.0, poll_every=100, max_steps=args.batch_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps = int(b.status()["steps"][0]) - 100
+    plans = {}
+    for i, (_, N, _, _, _) in enumerate(inst):
+        plans.setdefault(str(N), list(b.instance(i).plan))
+    out = {"workload": "64 instances, N x N with N uniform over {128, 192, 256, 384, 512}, T/Tc uniform over "
+                       "0.80..0.98, droplet (R 10..60) or slab, tanh width 4 (seed 3)",
+           "instances": len(inst), "sites": sites, "steps": steps, "ms_per_step": wall / steps * 1e3,
+           "value": 33.0 * sites * steps / wall, "unit": "site·velocity updates/s", "plans": plans}
+    if args.equilibrium > 0:
+        print(f"[bench] batch to residual {args.equilibrium:g}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        done = 0
+        while done < args.equilibrium_cap:
+            b.run(tol=args.equilibrium, consecutive=3, poll_every=100, max_steps=20000)
+            done += 20000
+            st = b.status()
+            print(f"[bench]   {time.perf_counter() - t0:.0f} s: {int((st['state'] != 0).sum())} retired, "
+                  f"median residual {np.median(st['residual']):.2e}", file=sys.stderr, flush=True)
+            if (st["state"] != 0).all():
+                break
+        st = b.status()
+        conv = st["steps_to_tol"][st["state"] == 1]
+        out["time_to_equilibrium"] = {
+            "tol": args.equilibrium, "wall_s": time.perf_counter() - t0, "converged": int(len(conv)),
+            "unstable": int((st["state"] == 2).sum()), "capped": int((st["state"] == 0).sum()),
+            "steps_to_tol": {"min": int(conv.min()) if len(conv) else None,
+                             "median": float(np.median(conv)) if len(conv) else None,
+                             "max": int(conv.max()) if len(conv) else None}}
+    b.close()
+    return out
+
+
 def cpu_baseline(fields, params, nx, ny):
     """FP64 oracle, as it stands, on one step of the same workload (single-threaded)."""
     import numpy as np
@@ -122,6 +174,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default column plan")
+    ap.add_argument("--batch-steps", type=int, default=200,
+                    help="timed steps of the 64-instance batch (0: skip the batch leg)")
+    ap.add_argument("--equilibrium", type=float, default=0.0, metavar="TOL",
+                    help="also run the batch until every instance's residual is below TOL (long)")
+    ap.add_argument("--equilibrium-cap", type=int, default=2_000_000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (traffic calibration under rocprofv3)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -145,6 +203,10 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     s = F.Solver(*(torch.from_numpy(a) for a in (fields.rho, fields.ux, fields.uy, fields.T)), params, device=dev)
+    plan = s.plan
+    if not args.no_autotune:
+        print("[bench] autotune column plans", file=sys.stderr, flush=True)
+        plan = s.autotune(reps=10)
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -175,6 +237,8 @@ def main():
         kern_ms.append(a.elapsed_time(b) / args.kernel_reps)
         s.set_state(state)
     s.close()
+
+    batch = batch_leg(args, F, W, dev) if args.batch_steps > 0 else None
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -217,7 +281,10 @@ def main():
                           "kernel_ms": dict(zip(STAGES, kern_ms)),
                           "event_ms_per_step": ev_s / args.steps * 1e3},
         "globals": {k: glob[k] for k in ("mass", "energy", "residual", "umax")},
+        "plan": {"conv_cols": plan[0], "multi_cols": plan[1], "col_radix": plan[2]},
     }
+    if batch is not None:
+        out["batch"] = batch
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline (1 step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(fields, params, nx, ny)

@@ -206,3 +206,21 @@ def batch_instances(n=64, seed=3, sizes=BATCH_SIZES):
         else:
             out.append(("slab", N, t, 0.0, slab(N, N, t_ratio=t, width=4.0, noise=0.0)))
     return out
+
+
+# Warm-start network: parameter shapes (per layer W[Cout, Cin, 3, 3] then b[Cout]) and
+# their seeded initial values, shared by the GPU network and its tests.
+CNN_CHANNELS = ((3, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 2))
+
+
+def cnn_init_params(seed=0):
+    """He-normal weights (the last layer scaled by 0.1, so that the initial output stays
+    close to the input), zero biases; float32 flat vector."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, (ci, co) in enumerate(CNN_CHANNELS):
+        W = rng.standard_normal((co, ci, 3, 3)) * math.sqrt(2.0 / (ci * 9))
+        if i == len(CNN_CHANNELS) - 1:
+            W *= 0.1
+        out += [W.ravel(), np.zeros(co)]
+    return np.concatenate(out).astype(np.float32)

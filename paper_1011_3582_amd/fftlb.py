@@ -118,10 +118,14 @@ def library():
     return _lib
 
 
-def header_functions(path: str = HEADER_PATH):
-    """Names of the functions declared in include/fftlb.h."""
-    txt = open(path).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(fftlb_\w+)\s*\(", txt, re.M)))
+def header_functions(paths=None):
+    """Names of the functions declared in the library's headers (include/*.h)."""
+    import glob
+    names = set()
+    for path in paths or sorted(glob.glob(os.path.join(os.path.dirname(HEADER_PATH), "*.h"))):
+        txt = open(path).read()
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(fftlb_\w+)\s*\(", txt, re.M))
+    return sorted(names)
 
 
 def _check(rc: int, what: str):

@@ -12,7 +12,8 @@ def test_library_exports_every_declared_function():
     names = F.header_functions()
     assert {"fftlb_init", "fftlb_step", "fftlb_moments", "fftlb_get_state", "fftlb_set_state",
             "fftlb_destroy", "fftlb_workspace_bytes", "fftlb_strerror", "fftlb_derivative",
-            "fftlb_last_error"} <= set(names)
+            "fftlb_last_error", "fftlb_batch_create", "fftlb_batch_run", "fftlb_autotune", "fftlb_cnn_create",
+            "fftlb_cnn_forward", "fftlb_cnn_gradient", "fftlb_cnn_adam_step", "fftlb_cnn_warm_start"} <= set(names)
     lib = F.library()
     for n in names:
         assert hasattr(lib, n), n
@@ -67,3 +68,17 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.fftlb_get_state(None, None, None) == F.FFTLB_EINVAL
     assert lib.fftlb_destroy(None) == F.FFTLB_EINVAL
     assert lib.fftlb_strerror(F.FFTLB_ENOSPC).decode().startswith("workspace")
+
+
+def test_cnn_host_checks():
+    from paper_1011_3582_amd import cnn as N
+    lib = N.library()
+    out = ctypes.c_size_t()
+    assert lib.fftlb_cnn_workspace_bytes(256, 256, 4, ctypes.byref(out)) == F.FFTLB_OK
+    assert out.value > 4 * 32 * 256 * 256 * 4 * 3          # Z, GELU(Z) and dZ of the full-size layers
+    for h, w, n in [(6, 256, 1), (256, 254, 1), (256, 256, 0), (2, 2, 1)]:
+        assert lib.fftlb_cnn_workspace_bytes(h, w, n, ctypes.byref(out)) == F.FFTLB_EINVAL
+    c = ctypes.c_void_p()
+    assert lib.fftlb_cnn_create(64, 64, 1, None, 0, None, None, ctypes.byref(c)) == F.FFTLB_EINVAL
+    assert lib.fftlb_cnn_forward(None, None, None, 1, None) == F.FFTLB_EINVAL
+    assert N.PARAMS == 38466

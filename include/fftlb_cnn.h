@@ -73,8 +73,13 @@ int fftlb_cnn_read_buffer(const fftlb_cnn* c, int32_t layer, int32_t kind, float
 /* Warm start of one run: rho0, T0 device [h][w] initial fields, T_target the run's
  * temperature, rho_c, T_c the normalisation (critical point).  Writes the predicted
  * rho_out, T_out [h][w]: the density clamped to [1e-3 rho_c, rho_max] (rho_max below 1/b
- * keeps the equation of state finite) and scaled to the initial total mass, the
- * temperature clamped to >= 1e-2 T_c. */
+ * keeps the equation of state finite), passed once through the periodic binomial filter
+ * (1 2 1)/4 along each axis (it removes grid-scale content, which the windowed derivatives
+ * barely move) and brought to the initial total mass by adding (M0 - M) |grad rho| /
+ * sum |grad rho| (the interfaces move, the bulk densities stay; a field without
+ * interfaces is rescaled instead); the
+ * temperature uniform at the mean of the predicted temperature field (equilibria are
+ * isothermal), at least 1e-2 T_c. */
 int fftlb_cnn_warm_start(fftlb_cnn* c, const float* rho0, const float* T0, float T_target, float rho_c,
                          float T_c, float rho_max, float* rho_out, float* T_out, void* stream);
 

@@ -304,9 +304,13 @@ int fftlb_cnn_warm_start(fftlb_cnn* c, const float* rho0, const float* T0, float
   hipLaunchKernelGGL(k_ws_input, dim3(grid_for(P)), dim3(256), 0, s, rho0, T0, x, P, 1.0f / rho_c, 1.0f / T_c,
                      T_target / T_c, c->sums);
   if (forward(c, x, 1, s)) return check("cnn warm start");
-  hipLaunchKernelGGL(k_ws_output, dim3(grid_for(P)), dim3(256), 0, s, c->ptr(c->L.y), rho_out, T_out, P, rho_c,
-                     T_c, 1e-3f * rho_c, rho_max, 1e-2f * T_c, c->sums + 1);
-  hipLaunchKernelGGL(k_ws_project, dim3(grid_for(P)), dim3(256), 0, s, rho_out, P, c->sums);
+  hipLaunchKernelGGL(k_ws_output, dim3(grid_for(P)), dim3(256), 0, s, c->ptr(c->L.y), rho_out, P, rho_c, T_c,
+                     1e-3f * rho_c, rho_max, c->sums);
+  // the network input buffer is free now: it holds the filter's intermediate
+  hipLaunchKernelGGL(k_ws_smooth_x, dim3(grid_for(P)), dim3(256), 0, s, rho_out, x, c->h, c->w);
+  hipLaunchKernelGGL(k_ws_smooth_y, dim3(grid_for(P)), dim3(256), 0, s, x, rho_out, c->h, c->w);
+  hipLaunchKernelGGL(k_ws_interface, dim3(grid_for(P)), dim3(256), 0, s, rho_out, x, c->h, c->w, c->sums);
+  hipLaunchKernelGGL(k_ws_project, dim3(grid_for(P)), dim3(256), 0, s, rho_out, x, T_out, P, 1e-2f * T_c, c->sums);
   return check("cnn warm start");
 }
 

@@ -297,32 +297,96 @@ __global__ __launch_bounds__(256) void k_ws_input(const float* __restrict__ rho0
   if (threadIdx.x == 0) atomicAdd(sum, red[0]);
 }
 
-// Network output -> density and temperature, clamped to the physical range, and the FP64
-// sum of the density.
-__global__ __launch_bounds__(256) void k_ws_output(const float* __restrict__ y, float* __restrict__ rho,
-                                                   float* __restrict__ T, long P, float rc, float tc, float rmin,
-                                                   float rmax, float tmin, double* sum) {
-  __shared__ double red[256];
-  double acc = 0.0;
+// Network output -> density clamped to the physical range; FP64 sums of the density
+// (sums[1]) and of the predicted temperature (sums[2]).
+__global__ __launch_bounds__(256) void k_ws_output(const float* __restrict__ y, float* __restrict__ rho, long P,
+                                                   float rc, float tc, float rmin, float rmax, double* sums) {
+  __shared__ double red[256][2];
+  double acc = 0.0, acct = 0.0;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256) {
     const float r = fminf(fmaxf(y[i] * rc, rmin), rmax);
     rho[i] = r;
-    T[i] = fmaxf(y[P + i] * tc, tmin);
     acc += r;
+    acct += y[P + i] * tc;
+  }
+  red[threadIdx.x][0] = acc;
+  red[threadIdx.x][1] = acct;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[threadIdx.x][0] += red[threadIdx.x + w][0];
+      red[threadIdx.x][1] += red[threadIdx.x + w][1];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&sums[1], red[0][0]);
+    atomicAdd(&sums[2], red[0][1]);
+  }
+}
+
+// One pass of the periodic binomial filter (1 2 1)/4 along x then y, src -> dst (tmp holds
+// the intermediate).  It removes the grid-scale content that upsampling layers leave in a
+// prediction (the Nyquist mode exactly), which the windowed derivatives, nearly blind at
+// those wavenumbers, would otherwise carry for a long time; it conserves the total.
+__global__ __launch_bounds__(256) void k_ws_smooth_x(const float* __restrict__ src, float* __restrict__ tmp, int h,
+                                                     int w) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < (long)h * w; i += (long)gridDim.x * 256) {
+    const int y = (int)(i / w), x = (int)(i % w);
+    const long r = (long)y * w;
+    tmp[i] = 0.25f * src[r + (x + w - 1) % w] + 0.5f * src[i] + 0.25f * src[r + (x + 1) % w];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ws_smooth_y(const float* __restrict__ tmp, float* __restrict__ dst, int h,
+                                                     int w) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < (long)h * w; i += (long)gridDim.x * 256) {
+    const int y = (int)(i / w), x = (int)(i % w);
+    dst[i] = 0.25f * tmp[(long)((y + h - 1) % h) * w + x] + 0.5f * tmp[i] + 0.25f * tmp[(long)((y + 1) % h) * w + x];
+  }
+}
+
+// Interface weight w = |grad rho| (central differences, periodic) into w, and its FP64
+// total into sums[3].
+__global__ __launch_bounds__(256) void k_ws_interface(const float* __restrict__ rho, float* __restrict__ w, int h,
+                                                      int wd, double* sums) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < (long)h * wd; i += (long)gridDim.x * 256) {
+    const int y = (int)(i / wd), x = (int)(i % wd);
+    const float gx = rho[(long)y * wd + (x + 1) % wd] - rho[(long)y * wd + (x + wd - 1) % wd];
+    const float gy = rho[(long)((y + 1) % h) * wd + x] - rho[(long)((y + h - 1) % h) * wd + x];
+    const float g = 0.5f * sqrtf(gx * gx + gy * gy);
+    w[i] = g;
+    acc += g;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(sum, red[0]);
+  if (threadIdx.x == 0) atomicAdd(&sums[3], red[0]);
 }
 
-// Scale the density so that its total equals the initial total (sums[0] / sums[1]).
-__global__ __launch_bounds__(256) void k_ws_project(float* __restrict__ rho, long P, const double* sums) {
-  const float s = (float)(sums[0] / sums[1]);
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256) rho[i] *= s;
+// Restore the initial total mass M0 = sums[0] from the prediction's sums[1] by adding
+// (M0 - M) w / sum(w): the mass goes to or comes from the interfaces, which move slightly,
+// while the bulk densities stay at the predicted values (a uniform rescaling would move
+// both phases off coexistence, and that relaxes only by slow evaporation and
+// condensation).  Without interfaces (sum(w) == 0) the density is rescaled.  The
+// temperature is the mean of the prediction, uniform (the model's equilibria are
+// isothermal, and a non-uniform start would relax only by slow conduction).
+__global__ __launch_bounds__(256) void k_ws_project(float* __restrict__ rho, const float* __restrict__ w,
+                                                    float* __restrict__ T, long P, float tmin, const double* sums) {
+  const double dm = sums[0] - sums[1];
+  const bool shift = sums[3] > 1e-6 * sums[1];
+  const float a = shift ? (float)(dm / sums[3]) : 0.0f;
+  const float sc = shift ? 1.0f : (float)(sums[0] / sums[1]);
+  const float t = fmaxf((float)(sums[2] / (double)P), tmin);
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256) {
+    rho[i] = shift ? rho[i] + a * w[i] : rho[i] * sc;
+    T[i] = t;
+  }
 }
 
 }  // namespace cnn

@@ -169,4 +169,5 @@ def test_warm_start_keeps_the_mass():
     rho, T = rho.cpu().numpy(), T.cpu().numpy()
     assert rho.sum(dtype=np.float64) == pytest.approx(fld.rho.sum(dtype=np.float64), rel=1e-6)
     assert (rho > 0).all() and (T > 0).all() and rho.max() <= 0.95 / W.EOS_B * 1.01
+    assert np.ptp(T) == 0.0                           # uniform temperature
     net.close()

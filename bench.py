@@ -40,15 +40,17 @@ STAGE_FLOATS_PER_SITE = (48, 10, 20, 8, 146)
 DOMINANT = 4
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_spinodal1024.json")
-KERNEL_SOURCES = ("paper_1011_3582_amd/csrc/kernels.hpp", "paper_1011_3582_amd/csrc/fft_lds.hpp",
-                  "paper_1011_3582_amd/csrc/model.hpp", "paper_1011_3582_amd/csrc/fftlb.hip")
+CSRC = os.path.join(ROOT, "paper_1011_3582_amd", "csrc")
 
 
 def kernel_source_hash() -> str:
+    """Hash of every source the solver's kernels are built from (the warm-start network's
+    files excluded)."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hpp", ".hip")) and not name.startswith("cnn."):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
 
 

@@ -17,7 +17,9 @@
 // walk consecutive transforms (column kernels, transforms interleaved with stride SI);
 // otherwise consecutive butterflies of one transform (row kernels, contiguous transforms).
 //
-// Twiddles come from a table tw[j] = exp(-2 pi i j / N) computed in FP64 on the host.
+// Twiddles come from a table tw[j] = exp(-2 pi i j / N) computed in FP64 on the host; the
+// kernels rearrange it into per-pass tables in LDS first (TWL, see build_twiddles), so
+// that every power is one conflict-free LDS read.
 // Direction: DIR = -1 forward (kernel exp(-i k x)), DIR = +1 inverse, both unnormalised.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -132,9 +134,9 @@ __device__ __forceinline__ void dft(float2* v) {
   }
 }
 
-// Twiddles w^r (r = 1..R-1) applied to v[r], from the table entries of w, w^2, w^4, w^8
-// (exact up to their FP32 rounding); the other powers are products of at most four of
-// them, formed as they are used.
+// Twiddles w^r (r = 1..R-1) applied to v[r], from the table in global memory: only w,
+// w^2, w^4, w^8 are read (exact up to their FP32 rounding) and the other powers are
+// products of at most four of them.
 template <int R, int DIR>
 __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restrict__ tw, int stride) {
   float2 p[4];
@@ -155,6 +157,20 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restri
   }
 }
 
+// Per-pass twiddle tables in LDS (TWL): the pass with span P and radix R reads
+// T_P[(r - 1) P + k] = exp(-2 pi i r k / (P R)) for butterfly k = i mod P, so the lanes of
+// a wave (consecutive k) read consecutive entries and every power is a single LDS read (no
+// vector-memory issue, no products).  The tables of all passes of a length-N transform
+// hold fewer than N entries in total.
+template <int R, int DIR>
+__device__ __forceinline__ void apply_twiddles_lds(float2* v, const float2* tp, int P) {
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const float2 w = tp[(r - 1) * P];
+    v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
+  }
+}
+
 // One Stockham pass of radix R over NB transforms of length N, span P (product of the
 // radices of the passes before it), executed by NTH threads.
 //
@@ -162,7 +178,7 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restri
 // a value below the butterfly's span, pad(B + o_r) = pad(B) + pad(o_r) for the load
 // offsets o_r = r (N/R) SI and the store offsets o_r = r P SI (N, R, P, SI powers of two),
 // so pad(o_r) is a compile-time constant.
-template <int N, int R, int P, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED>
+template <int N, int R, int P, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, bool TWL>
 __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off, int st,
                                               const float2* __restrict__ tw, int tid) {
   constexpr int NBF = N / R;               // butterflies per transform
@@ -203,7 +219,12 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
     if (EXACT || b < TOT) {
       const int i = idx[s];
       const int k = i % P;  // P is a compile-time constant (a shift and mask when a power of two)
-      if constexpr (P > 1) apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
+      if constexpr (P > 1) {
+        if constexpr (TWL)
+          apply_twiddles_lds<R, DIR>(v[s], tw + k, P);
+        else
+          apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
+      }
       dft<R, DIR>(v[s]);
       const int j0 = (i - k) * R + k;
       if constexpr (ALIGNED) {
@@ -230,12 +251,42 @@ constexpr int pass_radix() {
   return MAXR;
 }
 
-template <int N, int P, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR>
+// Offset of the table of the pass with span PT in the per-pass tables (and, for PT = N,
+// their total size).
+template <int N, int MAXR, int PT, int P = 1>
+constexpr int tw_offset() {
+  if constexpr (P >= PT || P >= N) {
+    return 0;
+  } else {
+    constexpr int R = pass_radix<N, P, MAXR>();
+    return (P > 1 ? (R - 1) * P : 0) + tw_offset<N, MAXR, PT, P * R>();
+  }
+}
+
+// Build the per-pass tables of a length-N transform in LDS from the full table
+// tw[j] = exp(-2 pi i j / N) in global memory (callers have a barrier before first use).
+template <int N, int MAXR, int P = 1>
+__device__ __forceinline__ void build_twiddles(float2* dst, const float2* __restrict__ tw, int tid, int nth) {
+  if constexpr (P < N) {
+    constexpr int R = pass_radix<N, P, MAXR>();
+    if constexpr (P > 1) {
+      constexpr int off = tw_offset<N, MAXR, P>();
+      for (int j = tid; j < (R - 1) * P; j += nth) {
+        const int r = j / P + 1, k = j % P;
+        dst[off + j] = tw[r * k * (N / (P * R))];
+      }
+    }
+    build_twiddles<N, MAXR, P * R>(dst, tw, tid, nth);
+  }
+}
+
+template <int N, int P, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR, bool TWL>
 __device__ __forceinline__ void fft_passes(float2* lds, int off, int st, const float2* __restrict__ tw, int tid) {
   if constexpr (P < N) {
     constexpr int R = pass_radix<N, P, MAXR>();
-    stockham_pass<N, R, P, DIR, NTH, NB, TFAST, SI, ALIGNED>(lds, off, st, tw, tid);
-    fft_passes<N, P * R, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR>(lds, off, st, tw, tid);
+    stockham_pass<N, R, P, DIR, NTH, NB, TFAST, SI, ALIGNED, TWL>(
+        lds, off, st, TWL ? tw + tw_offset<N, MAXR, P>() : tw, tid);
+    fft_passes<N, P * R, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR, TWL>(lds, off, st, tw, tid);
   }
 }
 
@@ -243,13 +294,13 @@ __device__ __forceinline__ void fft_passes(float2* lds, int off, int st, const f
 // lds[pad(off + t * st + i * SI)].  ALIGNED asserts that off + t * st is always a multiple
 // of 32 (see stockham_pass).  Callers must have a barrier between their last write of the
 // data and this call; the call ends with a barrier.
-template <int N, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR = 16>
+template <int N, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR = 16, bool TWL = true>
 __device__ __forceinline__ void fft_lds(float2* lds, int off, int st, const float2* __restrict__ tw, int tid) {
   static_assert(fft_length_ok(N), "length 2^p or 3 * 2^p");
   static_assert(MAXR == 8 || MAXR == 16, "radix");
   // the compile-time offsets need power-of-two spans (see stockham_pass)
   static_assert(!ALIGNED || is_pow2(N), "aligned offsets need a power-of-two length");
-  fft_passes<N, 1, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR>(lds, off, st, tw, tid);
+  fft_passes<N, 1, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR, TWL>(lds, off, st, tw, tid);
 }
 
 }  // namespace fftlb

@@ -43,8 +43,25 @@ struct RowGeom {
   static constexpr int NT = RB * TPR;
   static constexpr int NPB = 4;
   static constexpr int RADIX = 4 * J;
-  static constexpr int LDS = lds_alloc(NPB * RB * NX);  // float2 elements (<= 64 KB)
+  static constexpr int LDS = lds_alloc(NPB * RB * NX);  // float2 elements of the data
+  static constexpr int LDS_TOTAL = LDS + NX;             // and the row twiddle table after it
 };
+
+// Per-pass twiddle tables of the row transforms in LDS after the data (callers have a
+// barrier between this and the first transform).
+template <int NX>
+__device__ __forceinline__ const float2* row_twiddles(float2* lds, const float2* __restrict__ twx, int tid) {
+  float2* dst = lds + RowGeom<NX>::LDS;
+  build_twiddles<NX, RowGeom<NX>::RADIX>(dst, twx, tid, RowGeom<NX>::NT);
+  return dst;
+}
+
+// The same for column transforms of length NY with largest radix R.
+template <int NY, int R>
+__device__ __forceinline__ const float2* col_twiddles(float2* dst, const float2* __restrict__ twy, int tid, int nth) {
+  build_twiddles<NY, R>(dst, twy, tid, nth);
+  return dst;
+}
 
 struct SpecGeom {
   int ny;       // column length
@@ -318,21 +335,23 @@ __device__ __forceinline__ void rows_store_batch(const float2* lds, const PairBa
 }
 
 // Inverse row transforms of a batch; afterwards slot p holds a_p(x) + i b_p(x).
-template <int NX, int NP>
+template <int NX, int NP, bool TWL = true>
 __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
                                                    const float2* twx, const float* kapx, int row0, int tid) {
   rows_load_batch<NX, NP>(lds, in, sg, kapx, row0, tid);
   __syncthreads();
-  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
+  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX,
+          TWL>(lds, 0, NX, twx, tid);
 }
 
 // Forward row transforms of slots already written (unsynchronised) and store of the packed
 // half spectra.  Ends with a barrier so the LDS can be reused.
-template <int NX, int NP>
+template <int NX, int NP, bool TWL = true>
 __device__ __forceinline__ void rows_forward_batch(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
                                                    const float2* twx, int row0, int tid) {
   __syncthreads();
-  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX>(lds, 0, NX, twx, tid);
+  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX,
+          TWL>(lds, 0, NX, twx, tid);
   rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
   __syncthreads();
 }
@@ -363,12 +382,13 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
   if (retired(A.state, In.id)) return;
   extern __shared__ float2 lds[];
   float2* __restrict__ spec = In.spec;
-  const float2* __restrict__ twy = In.twy;
+  const float2* twy = In.twy;
   const float* __restrict__ kapx = In.kapx;
   const float* __restrict__ kapy = In.kapy;
   const int nx = In.nx, tw = In.tw;
   const float scale = In.scale;
   const int tid = threadIdx.x;
+  twy = col_twiddles<NY, R>(lds + lds_alloc(NY * CW), twy, tid, NT);
   const int nsub = (nx / 2) / CW;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int p = conv_column_plane(b / nsub), sub = b % nsub;
@@ -402,13 +422,13 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
   const ColInst& In = A.c[blockIdx.z];
   if (retired(A.state, In.id)) return;
   extern __shared__ float2 lds[];
-  const float2* __restrict__ twy = In.twy;
   const float* __restrict__ kapx = In.kapx;
   const float* __restrict__ kapy = In.kapy;
   const int tw = In.tw;
   const float scale = In.scale;
   const long hp = (long)(In.nx / 2) * NY;  // complex values per spectral plane
   const int tid = threadIdx.x;
+  const float2* twy = col_twiddles<NY, R>(lds + lds_alloc(4 * NY * CW), In.twy, tid, NT);
   const ColGroup& G = L.g[blockIdx.y];
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
   const long off = (long)(c0 / tw) * NY * tw + (c0 % tw);
@@ -471,6 +491,9 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
   using G = RowGeom<NX>;
   constexpr int J = G::J;
   const int tid = threadIdx.x;
+  // twiddles from the global table here: an LDS copy would cost this kernel one of its
+  // four blocks per CU
+  const float2* twx = P.twx;
   const RowThread<NX> rt(tid, blk);
   const int row0 = blk * G::RB;
   const long rowoff = (long)rt.y * P.nx;
@@ -509,7 +532,7 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
     set_term(b, 2, 1, 1, s1 + 3 * hp, 1.0f, TERM_IKX);
     set_term(b, 3, 0, 0, Uy, inx, TERM_IKX);                // dxuy
     set_term(b, 3, 1, 0, s1 + 3 * hp, 1.0f, TERM_ONE);      // dyuy
-    rows_inverse_batch<NX, 4>(lds, b, P.sg, P.twx, P.kapx, row0, tid);
+    rows_inverse_batch<NX, 4, false>(lds, b, P.sg, twx, P.kapx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float2 v = lds[rt.at(0, j)];
@@ -534,7 +557,7 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
     set_term(b2, 0, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);     // thy
     set_term(b2, 0, 1, 0, Th, inx, TERM_IKX);               // Tx
     set_term(b2, 1, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);     // Ty
-    rows_inverse_batch<NX, 2>(lds, b2, P.sg, P.twx, P.kapx, row0, tid);
+    rows_inverse_batch<NX, 2, false>(lds, b2, P.sg, twx, P.kapx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const float2 v = lds[rt.at(0, j)];
@@ -585,7 +608,7 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
   }
   // forward row transforms of the five fields whose divergences the force needs
   PairBatchOut<3> o{{P.s2i, P.s2i + 2 * hp, P.s2i + 4 * hp}, {P.s2i + hp, P.s2i + 3 * hp, nullptr}};
-  rows_forward_batch<NX, 3>(lds, o, P.sg, P.twx, row0, tid);
+  rows_forward_batch<NX, 3, false>(lds, o, P.sg, twx, row0, tid);
 
   // block reduction of the diagnostics (fixed order: deterministic)
   __shared__ double red_d[16][4];
@@ -637,6 +660,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   constexpr int J = G::J;
   constexpr int GPR = G::NPB / 4;   // speed groups per round
   const int tid = threadIdx.x;
+  const float2* twx = row_twiddles<NX>(lds, P.twx, tid);
   const RowThread<NX> rt(tid, blk);
   const int row0 = blk * G::RB;
   const long rowoff = (long)rt.y * P.nx;
@@ -646,7 +670,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   if constexpr (MODE == MODE_STEP) {
     const float2* a2[2] = {P.s2o, P.s2o + 2 * hp};
     const float2* b2[2] = {P.s2o + hp, nullptr};
-    rows_inverse_batch<NX, 2>(lds, plain_batch<2>(a2, b2), P.sg, P.twx, P.kapx, row0, tid);
+    rows_inverse_batch<NX, 2>(lds, plain_batch<2>(a2, b2), P.sg, twx, P.kapx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const long s = rowoff + rt.x(j);
@@ -715,7 +739,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         set_term(in, 4 * g + 0, 0, 0, io.a[4 * g + 0], c_vel.vx[qx0] / P.nx, TERM_IKX);
         set_term(in, 4 * g + 2, 0, 0, io.a[4 * g + 2], c_vel.vx[qx4] / P.nx, TERM_IKX);
       }
-      rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, P.twx, P.kapx, row0, tid);
+      rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, twx, P.kapx, row0, tid);
     }
 #pragma unroll
     for (int g = 0; g < GPR; ++g) {
@@ -766,7 +790,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-    rows_forward_batch<NX, G::NPB>(lds, io, P.sg, P.twx, row0, tid);
+    rows_forward_batch<NX, G::NPB>(lds, io, P.sg, twx, row0, tid);
   }
   // moments of the new state and their row spectra
 #pragma unroll
@@ -784,7 +808,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     lds[rt.at(1, j)] = make_float2(uy, T);
   }
   PairBatchOut<2> mo{{P.sm, P.sm + 2 * hp}, {P.sm + hp, P.sm + 3 * hp}};
-  rows_forward_batch<NX, 2>(lds, mo, P.sg, P.twx, row0, tid);
+  rows_forward_batch<NX, 2>(lds, mo, P.sg, twx, row0, tid);
 }
 
 template <int NX, int MODE>
@@ -806,6 +830,7 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_momentum(RowArgs A) {
   const RowThread<NX> rt(tid, blockIdx.x);
   const long rowoff = (long)rt.y * P.nx;
   const long hp = P.plane / 2;
+  const float2* twx = row_twiddles<NX>(lds, P.twx, tid);
 #pragma unroll
   for (int j = 0; j < RowGeom<NX>::J; ++j) {
     const long s = rowoff + rt.x(j);
@@ -813,7 +838,7 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_momentum(RowArgs A) {
     lds[rt.at(0, j)] = make_float2(r * P.macro[P.plane + s], r * P.macro[2 * P.plane + s]);
   }
   PairBatchOut<1> o{{P.s1}, {P.s1 + hp}};
-  rows_forward_batch<NX, 1>(lds, o, P.sg, P.twx, blockIdx.x * RowGeom<NX>::RB, tid);
+  rows_forward_batch<NX, 1>(lds, o, P.sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
 }
 
 // Residual pass, step 3 (after the column pass has formed the spectrum of D.j in stage-1
@@ -831,9 +856,10 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_residual(RowArgs A) {
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
   const long hp = P.plane / 2;
+  const float2* twx = row_twiddles<NX>(lds, P.twx, tid);
   const float2* a1[1] = {P.s1 + 2 * hp};
   const float2* b1[1] = {nullptr};
-  rows_inverse_batch<NX, 1>(lds, plain_batch<1>(a1, b1), P.sg, P.twx, P.kapx, blockIdx.x * RowGeom<NX>::RB, tid);
+  rows_inverse_batch<NX, 1>(lds, plain_batch<1>(a1, b1), P.sg, twx, P.kapx, blockIdx.x * RowGeom<NX>::RB, tid);
   float m = 0.0f;
   int bad = 0;
 #pragma unroll
@@ -868,7 +894,7 @@ template <int NX>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_real(const float* __restrict__ a,
                                                                        const float* __restrict__ b,
                                                                        float2* sa, float2* sb, SpecGeom sg,
-                                                                       const float2* __restrict__ twx, int nx) {
+                                                                       const float2* twx, int nx) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
@@ -878,6 +904,7 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_real(const flo
     const long s = rowoff + rt.x(j);
     lds[rt.at(0, j)] = make_float2(a[s], b ? b[s] : 0.0f);
   }
+  twx = row_twiddles<NX>(lds, twx, tid);
   PairBatchOut<1> o{{sa}, {sb}};
   rows_forward_batch<NX, 1>(lds, o, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
 }
@@ -886,13 +913,14 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_real(const flo
 template <int NX>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_inverse_real(const float2* sa, const float2* sb,
                                                                        float* __restrict__ a, float* __restrict__ b,
-                                                                       SpecGeom sg, const float2* __restrict__ twx,
+                                                                       SpecGeom sg, const float2* twx,
                                                                        const float* __restrict__ kapx, int nx) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const RowThread<NX> rt(tid, blockIdx.x);
   const long rowoff = (long)rt.y * nx;
   const float2* a1[1] = {sa};
+  twx = row_twiddles<NX>(lds, twx, tid);
   const float2* b1[1] = {sb};
   rows_inverse_batch<NX, 1>(lds, plain_batch<1>(a1, b1), sg, twx, kapx, blockIdx.x * RowGeom<NX>::RB, tid);
 #pragma unroll

@@ -27,7 +27,7 @@ int col_conv_plan(const StepLaunch& L, hipStream_t s) {
     for (int first = 0; first < L.ninst; first += kColSlots) {
       const int count = cmin(kColSlots, L.ninst - first);
       hipLaunchKernelGGL((k_col_conv<NY, CW, NT, R>), dim3(nblocks, count), dim3(NT),
-                         lds_alloc(NY * CW) * sizeof(float2), s, col_args(L, first, count, true));
+                         (lds_alloc(NY * CW) + NY) * sizeof(float2), s, col_args(L, first, count, true));
     }
     return FFTLB_OK;
   }
@@ -43,7 +43,7 @@ int col_multi_plan(const StepLaunch& L, const ColLaunch& groups, int ngroups, hi
       const int count = cmin(kColSlots, L.ninst - first);
       // three input blocks and one work block
       hipLaunchKernelGGL((k_col_multi<NY, CW, NT, R>), dim3((L.nx / 2) / CW, ngroups, count), dim3(NT),
-                         lds_alloc(4 * NY * CW) * sizeof(float2), s, col_args(L, first, count, false), groups);
+                         (lds_alloc(4 * NY * CW) + NY) * sizeof(float2), s, col_args(L, first, count, false), groups);
     }
     return FFTLB_OK;
   }

@@ -19,14 +19,14 @@ inline RowArgs row_args(const StepLaunch& L, int first, int count) {
 template <int NX>
 int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s) {
   using G = RowGeom<NX>;
-  const size_t lds = G::LDS * sizeof(float2);
+  const size_t lds = G::LDS_TOTAL * sizeof(float2);
   if (kernel < RK_STAGE2 || kernel > RK_RESIDUAL) return FFTLB_EINVAL;
   for (int first = 0; first < L.ninst; first += kRowSlots) {
     const int count = cmin(kRowSlots, L.ninst - first);
     const dim3 grid(L.nblk, count), block(G::NT);
     const RowArgs a = row_args(L, first, count);
     switch (kernel) {
-      case RK_STAGE2: hipLaunchKernelGGL(k_rows_stage2<NX>, grid, block, lds, s, a); break;
+      case RK_STAGE2: hipLaunchKernelGGL(k_rows_stage2<NX>, grid, block, G::LDS * sizeof(float2), s, a); break;
       case RK_COLLIDE: hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP>), grid, block, lds, s, a, in); break;
       case RK_INIT: hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT>), grid, block, lds, s, a, in); break;
       case RK_SET: hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET>), grid, block, lds, s, a, in); break;
@@ -41,7 +41,7 @@ template <int NX>
 int launch_rows_forward_real(int nblk, const float* a, const float* b, float2* sa, float2* sb, SpecGeom sg,
                              const float2* twx, hipStream_t s) {
   hipLaunchKernelGGL(k_rows_forward_real<NX>, dim3(nblk), dim3(RowGeom<NX>::NT),
-                     RowGeom<NX>::LDS * sizeof(float2), s, a, b, sa, sb, sg, twx, NX);
+                     RowGeom<NX>::LDS_TOTAL * sizeof(float2), s, a, b, sa, sb, sg, twx, NX);
   return FFTLB_OK;
 }
 
@@ -49,7 +49,7 @@ template <int NX>
 int launch_rows_inverse_real(int nblk, const float2* sa, const float2* sb, float* a, float* b, SpecGeom sg,
                              const float2* twx, const float* kapx, hipStream_t s) {
   hipLaunchKernelGGL(k_rows_inverse_real<NX>, dim3(nblk), dim3(RowGeom<NX>::NT),
-                     RowGeom<NX>::LDS * sizeof(float2), s, sa, sb, a, b, sg, twx, kapx, NX);
+                     RowGeom<NX>::LDS_TOTAL * sizeof(float2), s, sa, sb, a, b, sg, twx, kapx, NX);
   return FFTLB_OK;
 }
 

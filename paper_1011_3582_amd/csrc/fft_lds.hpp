@@ -240,53 +240,61 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
   __syncthreads();
 }
 
-// Radix of the pass with span P: for N = 3 * 2^p a radix-3 pass first; then the remainder
-// pass of the power-of-two part, then radix MAXR (8 or 16).
-template <int N, int P, int MAXR>
+// Radix of the pass with span P.  Order 0: for N = 3 * 2^p a radix-3 pass first; then
+// the remainder pass of the power-of-two part, then radix MAXR (8 or 16).  Order 1 (powers
+// of two): radix MAXR first and the remainder pass last.
+template <int N, int P, int MAXR, int ORD = 0>
 constexpr int pass_radix() {
-  constexpr bool three = !is_pow2(N);
-  if (three && P == 1) return 3;
-  constexpr int l = ilog2(three ? N / 3 : N), m = ilog2(MAXR);
-  if (P == (three ? 3 : 1) && (l % m) != 0) return 1 << (l % m);
-  return MAXR;
+  if constexpr (ORD == 1) {
+    constexpr int l = ilog2(N), m = ilog2(MAXR);
+    return ((l % m) != 0 && P == (N >> (l % m))) ? (1 << (l % m)) : MAXR;
+  } else {
+    constexpr bool three = !is_pow2(N);
+    if (three && P == 1) return 3;
+    constexpr int l = ilog2(three ? N / 3 : N), m = ilog2(MAXR);
+    if (P == (three ? 3 : 1) && (l % m) != 0) return 1 << (l % m);
+    return MAXR;
+  }
 }
 
-// Offset of the table of the pass with span PT in the per-pass tables (and, for PT = N,
-// their total size).
-template <int N, int MAXR, int PT, int P = 1>
+// Offset of the table of the pass with span PT in the per-pass tables of pass order ORD
+// (and, for PT = N, their total size, always below N).
+template <int N, int MAXR, int PT, int ORD = 0, int P = 1>
 constexpr int tw_offset() {
   if constexpr (P >= PT || P >= N) {
     return 0;
   } else {
-    constexpr int R = pass_radix<N, P, MAXR>();
-    return (P > 1 ? (R - 1) * P : 0) + tw_offset<N, MAXR, PT, P * R>();
+    constexpr int R = pass_radix<N, P, MAXR, ORD>();
+    return (P > 1 ? (R - 1) * P : 0) + tw_offset<N, MAXR, PT, ORD, P * R>();
   }
 }
 
-// Build the per-pass tables of a length-N transform in LDS from the full table
-// tw[j] = exp(-2 pi i j / N) in global memory (callers have a barrier before first use).
-template <int N, int MAXR, int P = 1>
+// Build the per-pass tables of pass order ORD of a length-N transform in LDS from the full
+// table tw[j] = exp(-2 pi i j / N) in global memory (callers have a barrier before use).
+template <int N, int MAXR, int ORD = 0, int P = 1>
 __device__ __forceinline__ void build_twiddles(float2* dst, const float2* __restrict__ tw, int tid, int nth) {
   if constexpr (P < N) {
-    constexpr int R = pass_radix<N, P, MAXR>();
+    constexpr int R = pass_radix<N, P, MAXR, ORD>();
     if constexpr (P > 1) {
-      constexpr int off = tw_offset<N, MAXR, P>();
+      constexpr int off = tw_offset<N, MAXR, P, ORD>();
       for (int j = tid; j < (R - 1) * P; j += nth) {
         const int r = j / P + 1, k = j % P;
         dst[off + j] = tw[r * k * (N / (P * R))];
       }
     }
-    build_twiddles<N, MAXR, P * R>(dst, tw, tid, nth);
+    build_twiddles<N, MAXR, ORD, P * R>(dst, tw, tid, nth);
   }
 }
 
-template <int N, int P, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR, bool TWL>
+// The passes with spans P .. STOP (exclusive) of pass order ORD.
+template <int N, int P, int STOP, int ORD, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR,
+          bool TWL>
 __device__ __forceinline__ void fft_passes(float2* lds, int off, int st, const float2* __restrict__ tw, int tid) {
-  if constexpr (P < N) {
-    constexpr int R = pass_radix<N, P, MAXR>();
+  if constexpr (P < STOP) {
+    constexpr int R = pass_radix<N, P, MAXR, ORD>();
     stockham_pass<N, R, P, DIR, NTH, NB, TFAST, SI, ALIGNED, TWL>(
-        lds, off, st, TWL ? tw + tw_offset<N, MAXR, P>() : tw, tid);
-    fft_passes<N, P * R, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR, TWL>(lds, off, st, tw, tid);
+        lds, off, st, TWL ? tw + tw_offset<N, MAXR, P, ORD>() : tw, tid);
+    fft_passes<N, P * R, STOP, ORD, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR, TWL>(lds, off, st, tw, tid);
   }
 }
 
@@ -300,7 +308,17 @@ __device__ __forceinline__ void fft_lds(float2* lds, int off, int st, const floa
   static_assert(MAXR == 8 || MAXR == 16, "radix");
   // the compile-time offsets need power-of-two spans (see stockham_pass)
   static_assert(!ALIGNED || is_pow2(N), "aligned offsets need a power-of-two length");
-  fft_passes<N, 1, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR, TWL>(lds, off, st, tw, tid);
+  fft_passes<N, 1, N, 0, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR, TWL>(lds, off, st, tw, tid);
+}
+
+// Part of a transform: the passes of order ORD with spans P0 .. STOP (exclusive), for
+// callers that fuse the first or the last pass into their own load or store.
+template <int N, int P0, int STOP, int ORD, int DIR, int NTH, int NB, bool TFAST, int SI, bool ALIGNED, int MAXR,
+          bool TWL>
+__device__ __forceinline__ void fft_lds_part(float2* lds, int off, int st, const float2* __restrict__ tw, int tid) {
+  static_assert(is_pow2(N) && (MAXR == 8 || MAXR == 16), "powers of two");
+  static_assert(!ALIGNED || is_pow2(N), "aligned offsets need a power-of-two length");
+  fft_passes<N, P0, STOP, ORD, DIR, NTH, NB, TFAST, SI, ALIGNED, MAXR, TWL>(lds, off, st, tw, tid);
 }
 
 }  // namespace fftlb

@@ -44,7 +44,13 @@ struct RowGeom {
   static constexpr int NPB = 4;
   static constexpr int RADIX = 4 * J;
   static constexpr int LDS = lds_alloc(NPB * RB * NX);  // float2 elements of the data
-  static constexpr int LDS_TOTAL = LDS + NX;             // and the row twiddle table after it
+  // Lengths whose pass sequence has a radix-2 remainder pass: the forward transforms run
+  // it last and fuse it into the Hermitian store (saves one LDS round trip; fusing the
+  // inverse's first pass into the load the same way was measured slower: its stride-2 LDS
+  // writes conflict 4 ways).
+  static constexpr bool FUSE_STORE = is_pow2(NX) && NX >= 16 && pass_radix<NX, 1, RADIX>() == 2;
+  // after the data: per-pass twiddle tables of pass order 0, and of order 1 when fused
+  static constexpr int LDS_TOTAL = LDS + (FUSE_STORE ? 2 : 1) * NX;
 };
 
 // Per-pass twiddle tables of the row transforms in LDS after the data (callers have a
@@ -52,7 +58,8 @@ struct RowGeom {
 template <int NX>
 __device__ __forceinline__ const float2* row_twiddles(float2* lds, const float2* __restrict__ twx, int tid) {
   float2* dst = lds + RowGeom<NX>::LDS;
-  build_twiddles<NX, RowGeom<NX>::RADIX>(dst, twx, tid, RowGeom<NX>::NT);
+  build_twiddles<NX, RowGeom<NX>::RADIX, 0>(dst, twx, tid, RowGeom<NX>::NT);
+  if constexpr (RowGeom<NX>::FUSE_STORE) build_twiddles<NX, RowGeom<NX>::RADIX, 1>(dst + NX, twx, tid, RowGeom<NX>::NT);
   return dst;
 }
 
@@ -334,14 +341,70 @@ __device__ __forceinline__ void rows_store_batch(const float2* lds, const PairBa
   }
 }
 
-// Inverse row transforms of a batch; afterwards slot p holds a_p(x) + i b_p(x).
+// Store of the packed half spectra with the last (radix-2, span H) forward pass fused in:
+// the thread for spectral columns k and H - k computes the butterflies i = k and i = H - k
+// (inputs i, i + H, twiddle w_i = tw_last[i]; outputs X(i) = y(i) + w y(i + H) and
+// X(i + H) = y(i) - w y(i + H)), which yield X at k, N - k, H - k and H + k, and separates
+// both columns.
+template <int NX, int NP>
+__device__ __forceinline__ void rows_store_batch_r2(const float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
+                                                    const float2* tw_last, int row0, int tid) {
+  constexpr int H = NX / 2, Q = H / 2, W = Q + 1;
+  constexpr int RB = RowGeom<NX>::RB;
+  constexpr int NT = RowGeom<NX>::NT;
+  tid = opaque(tid);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    float2* __restrict__ OA = out.a[p];
+    float2* __restrict__ OB = out.b[p];
+    for (int e = tid; e < RB * W; e += NT) {
+      const int rl = e / W, k = e % W;
+      const int z = (p * RB + rl) * NX;
+      // butterfly k
+      const float2 t = cmul(lds[pad(z + k + H)], tw_last[k]);
+      const float2 u = lds[pad(z + k)];
+      const float2 Xk = cadd(u, t), Xkh = csub(u, t);   // X(k), X(k + H)
+      float2 A, B;
+      if (k == 0) {  // X(0), X(H): the packed DC and Nyquist column
+        A = make_float2(Xk.x, Xkh.x);
+        B = make_float2(Xk.y, Xkh.y);
+      } else {
+        float2 Xnk;  // X(N - k)
+        if (k == Q) {
+          Xnk = Xkh;  // N - Q = H + Q
+        } else {
+          const int k2 = H - k;
+          const float2 t2 = cmul(lds[pad(z + k2 + H)], tw_last[k2]);
+          const float2 u2 = lds[pad(z + k2)];
+          const float2 Xk2 = cadd(u2, t2);  // X(H - k)
+          Xnk = csub(u2, t2);                // X(H - k + H) = X(N - k)
+          // column H - k from X(H - k) and X(N - (H - k)) = X(H + k)
+          const float2 A2 = make_float2(0.5f * (Xk2.x + Xkh.x), 0.5f * (Xk2.y - Xkh.y));
+          const float2 B2 = make_float2(0.5f * (Xk2.y + Xkh.y), 0.5f * (Xkh.x - Xk2.x));
+          const int gi2 = sg.idx(row0 + rl, k2);
+          OA[gi2] = A2;
+          if (OB) OB[gi2] = B2;
+        }
+        A = make_float2(0.5f * (Xk.x + Xnk.x), 0.5f * (Xk.y - Xnk.y));
+        B = make_float2(0.5f * (Xk.y + Xnk.y), 0.5f * (Xnk.x - Xk.x));
+      }
+      const int gi = sg.idx(row0 + rl, k);
+      OA[gi] = A;
+      if (OB) OB[gi] = B;
+    }
+  }
+}
+
+// Inverse row transforms of a batch; afterwards slot p holds a_p(x) + i b_p(x).  twx: the
+// per-pass LDS tables (TWL) or the global table.
 template <int NX, int NP, bool TWL = true>
 __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
                                                    const float2* twx, const float* kapx, int row0, int tid) {
+  using G = RowGeom<NX>;
+  constexpr bool AL = is_pow2(NX) && (NX % 32 == 0);
   rows_load_batch<NX, NP>(lds, in, sg, kapx, row0, tid);
   __syncthreads();
-  fft_lds<NX, +1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX,
-          TWL>(lds, 0, NX, twx, tid);
+  fft_lds<NX, +1, G::NT, NP * G::RB, false, 1, AL, G::RADIX, TWL>(lds, 0, NX, twx, tid);
 }
 
 // Forward row transforms of slots already written (unsynchronised) and store of the packed
@@ -349,10 +412,20 @@ __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<
 template <int NX, int NP, bool TWL = true>
 __device__ __forceinline__ void rows_forward_batch(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
                                                    const float2* twx, int row0, int tid) {
+  using G = RowGeom<NX>;
+  constexpr bool AL = is_pow2(NX) && (NX % 32 == 0);
   __syncthreads();
-  fft_lds<NX, -1, RowGeom<NX>::NT, NP * RowGeom<NX>::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), RowGeom<NX>::RADIX,
-          TWL>(lds, 0, NX, twx, tid);
-  rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
+  if constexpr (G::FUSE_STORE) {
+    // pass order 1 (radix-2 remainder last), its tables after those of order 0
+    const float2* tw1 = TWL ? twx + NX : twx;
+    fft_lds_part<NX, 1, NX / 2, 1, -1, G::NT, NP * G::RB, false, 1, AL, G::RADIX, TWL>(lds, 0, NX, tw1, tid);
+    // twiddles of the last pass: T[k] = exp(-2 pi i k / N), or the global table itself
+    const float2* tw_last = TWL ? tw1 + tw_offset<NX, G::RADIX, NX / 2, 1>() : twx;
+    rows_store_batch_r2<NX, NP>(lds, out, sg, tw_last, row0, tid);
+  } else {
+    fft_lds<NX, -1, G::NT, NP * G::RB, false, 1, AL, G::RADIX, TWL>(lds, 0, NX, twx, tid);
+    rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
+  }
   __syncthreads();
 }
 

@@ -207,8 +207,7 @@ struct fftlb_handle {
   const Inst* self;  // &I, as a one-entry instance list
   ColPlan plan;
   int64_t steps;
-  hipStream_t cap, cap2;   // capture streams (the second carries the concurrent branch)
-  hipEvent_t fork, join;
+  hipStream_t cap;         // capture stream
   hipGraphExec_t g1, gN;
 };
 
@@ -320,28 +319,18 @@ int enqueue_residual(const StepLaunch& L, hipStream_t s) {
   return rows(L, RK_RESIDUAL, Inputs{}, s);
 }
 
-// One step of every launch group in `Ls`, as captured into a graph: the convection column
-// passes (stage 0) run on a second branch, concurrently with the force pipeline (stages
-// 1-3); the collide (stage 4) joins both.
-int enqueue_step_forked(const StepLaunch* Ls, int nl, hipStream_t s, hipStream_t s2, hipEvent_t fork,
-                        hipEvent_t join) {
-  HIP_TRY(hipEventRecord(fork, s));
-  HIP_TRY(hipStreamWaitEvent(s2, fork, 0));
-  for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], 0, s2));
-  HIP_TRY(hipEventRecord(join, s2));
-  for (int k = 1; k <= 3; ++k)
+// One step of every launch group in `Ls`, kernel after kernel.  (A graph whose convection
+// column pass ran on a concurrent branch was measured slower: the convection pass fills
+// the GPU by itself, so the branch only added dependency overhead.)
+int enqueue_step_all(const StepLaunch* Ls, int nl, hipStream_t s) {
+  for (int k = 0; k < kNumStages; ++k)
     for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], k, s));
-  HIP_TRY(hipStreamWaitEvent(s, join, 0));
-  for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], 4, s));
   return FFTLB_OK;
 }
 
-int make_streams(hipStream_t* a, hipStream_t* b, hipEvent_t* fork, hipEvent_t* join) {
-  // default-priority streams; events without timing
+// The capture stream (default priority), created on first use.
+int make_stream(hipStream_t* a) {
   if (!*a) HIP_TRY(hipStreamCreateWithFlags(a, hipStreamNonBlocking));
-  if (!*b) HIP_TRY(hipStreamCreateWithFlags(b, hipStreamNonBlocking));
-  if (!*fork) HIP_TRY(hipEventCreateWithFlags(fork, hipEventDisableTiming));
-  if (!*join) HIP_TRY(hipEventCreateWithFlags(join, hipEventDisableTiming));
   return FFTLB_OK;
 }
 
@@ -376,12 +365,12 @@ int capture_graph(hipStream_t cap, Body body, hipGraphExec_t* out) {
 }
 
 int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
-  RC_TRY(make_streams(&h->cap, &h->cap2, &h->fork, &h->join));
+  RC_TRY(make_stream(&h->cap));
   const StepLaunch L = single_launch(h, h->plan);
   return capture_graph(
       h->cap,
       [&]() {
-        for (int i = 0; i < nsteps; ++i) RC_TRY(enqueue_step_forked(&L, 1, h->cap, h->cap2, h->fork, h->join));
+        for (int i = 0; i < nsteps; ++i) RC_TRY(enqueue_step_all(&L, 1, h->cap));
         return FFTLB_OK;
       },
       out);
@@ -542,8 +531,11 @@ struct fftlb_batch {
   };
   std::vector<Group> groups;
   std::vector<int> hstate;     // last read retirement flags
-  hipStream_t cap, cap2;
-  hipEvent_t fork, join;
+  hipStream_t cap;
+  // one capture branch per grid size (up to kBranches): the sizes are independent until
+  // the poll, so their kernels may run side by side
+  hipStream_t branch[8];
+  hipEvent_t fork, join[8];
   hipGraphExec_t graph;
   int graph_poll;              // steps per replay of `graph`
   double graph_tol;
@@ -609,12 +601,25 @@ int batch_capture(fftlb_batch* b, int poll, double tol, int consecutive) {
   std::vector<StepLaunch> Ls;
   batch_launches(b, &ids, &ptrs, &Ls);
   if (Ls.empty()) return FFTLB_OK;
-  RC_TRY(make_streams(&b->cap, &b->cap2, &b->fork, &b->join));
+  RC_TRY(make_stream(&b->cap));
+  const int nb = std::min<int>((int)Ls.size(), 8);
+  if (!b->fork) HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  for (int k = 0; k < nb; ++k) {
+    RC_TRY(make_stream(&b->branch[k]));
+    if (!b->join[k]) HIP_TRY(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+  }
   RC_TRY(capture_graph(
       b->cap,
       [&]() {
-        for (int i = 0; i < poll; ++i)
-          RC_TRY(enqueue_step_forked(Ls.data(), (int)Ls.size(), b->cap, b->cap2, b->fork, b->join));
+        // `poll` steps of each grid size on its own branch, then the residual passes and the poll
+        HIP_TRY(hipEventRecord(b->fork, b->cap));
+        for (int k = 0; k < nb; ++k) HIP_TRY(hipStreamWaitEvent(b->branch[k], b->fork, 0));
+        for (size_t c = 0; c < Ls.size(); ++c)
+          for (int i = 0; i < poll; ++i) RC_TRY(enqueue_step_all(&Ls[c], 1, b->branch[c % nb]));
+        for (int k = 0; k < nb; ++k) {
+          HIP_TRY(hipEventRecord(b->join[k], b->branch[k]));
+          HIP_TRY(hipStreamWaitEvent(b->cap, b->join[k], 0));
+        }
         for (const StepLaunch& L : Ls) RC_TRY(enqueue_residual(L, b->cap));
         hipLaunchKernelGGL(k_batch_poll, dim3(b->n), dim3(256), 0, b->cap, b->dpoll, b->st, poll, tol, consecutive);
         return FFTLB_OK;
@@ -663,8 +668,7 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   h->steps = 0;
   h->plan = default_plan(h->ny, h->tw);
   h->g1 = h->gN = nullptr;
-  h->cap = h->cap2 = nullptr;
-  h->fork = h->join = nullptr;
+  h->cap = nullptr;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return FFTLB_EHIP;
@@ -861,9 +865,6 @@ int fftlb_destroy(fftlb_handle* h) {
     (void)hipDeviceSynchronize();
     drop_graphs(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
-    if (h->cap2) (void)hipStreamDestroy(h->cap2);
-    if (h->fork) (void)hipEventDestroy(h->fork);
-    if (h->join) (void)hipEventDestroy(h->join);
   }
   delete h;
   return FFTLB_OK;
@@ -895,8 +896,12 @@ int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, siz
   fftlb_batch* b = new (std::nothrow) fftlb_batch();
   if (!b) return FFTLB_EINVAL;
   b->n = n;
-  b->cap = b->cap2 = nullptr;
-  b->fork = b->join = nullptr;
+  b->cap = nullptr;
+  b->fork = nullptr;
+  for (int k = 0; k < 8; ++k) {
+    b->branch[k] = nullptr;
+    b->join[k] = nullptr;
+  }
   b->graph = nullptr;
   b->graph_poll = 0;
   if (hipGetDevice(&b->device) != hipSuccess) {
@@ -1027,9 +1032,11 @@ int fftlb_batch_destroy(fftlb_batch* b) {
     (void)hipDeviceSynchronize();
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    if (b->cap2) (void)hipStreamDestroy(b->cap2);
     if (b->fork) (void)hipEventDestroy(b->fork);
-    if (b->join) (void)hipEventDestroy(b->join);
+    for (int k = 0; k < 8; ++k) {
+      if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
+      if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
   }
   for (fftlb_handle* h : b->inst) fftlb_destroy(h);
   delete b;

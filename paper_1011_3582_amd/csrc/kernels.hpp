@@ -752,9 +752,9 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       const float r = P.macro[s], ux = P.macro[P.plane + s], uy = P.macro[2 * P.plane + s];
       const float t = P.macro[3 * P.plane + s];
       site_init(st[j], r, ux, uy, t);
-      const float rT = r * t;
-      const float cc = P.cpl[s] + gd / (2.0f * rT * t);   // C + C_q
-      site_force(st[j], bxy.x / rT, bxy.y / rT, cc);
+      const float irT = 1.0f / (r * t);
+      const float cc = P.cpl[s] + 0.5f * gd * irT * st[j].iT;   // C + C_q, C_q = G / (2 rho T^2)
+      site_force(st[j], bxy.x * irT, bxy.y * irT, cc);
     }
     __syncthreads();
   } else if constexpr (MODE == MODE_INIT) {

@@ -86,6 +86,7 @@ __device__ __forceinline__ float rest_weight(float T) {
 // A + B.(v-u) + (C+Cq)|v-u|^2 = s0 + sx vx + sy vy + cc |v|^2 (Eqs. (11), (20)).
 struct Site {
   float rho, ux, uy, T;
+  float iT;  // 1/T, formed once per site
   float s0, sx, sy, cc;
 };
 
@@ -102,6 +103,7 @@ __device__ __forceinline__ void site_init(Site& s, float rho, float ux, float uy
   s.ux = ux;
   s.uy = uy;
   s.T = T;
+  s.iT = 1.0f / T;
   s.s0 = s.sx = s.sy = s.cc = 0.0f;
 }
 
@@ -117,7 +119,7 @@ __device__ __forceinline__ void site_force(Site& s, float Bx, float By, float cc
 
 __device__ __forceinline__ GroupEq group_eq(const Site& s, float Fk) {
   GroupEq e;
-  e.invT = 1.0f / s.T;
+  e.invT = s.iT;
   const float u2 = s.ux * s.ux + s.uy * s.uy;
   e.g = 1.0f - 0.5f * u2 * e.invT;
   e.base = e.g + 0.125f * u2 * u2 * e.invT * e.invT;

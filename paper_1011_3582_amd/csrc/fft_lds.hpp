@@ -53,6 +53,30 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
+// Thread index below NT, opaque as above and unsigned with its range asserted, so that
+// divisions and remainders by powers of two in the index arithmetic are shifts and masks.
+template <int NT>
+__device__ __forceinline__ unsigned opaque_tid(int tid) {
+  const unsigned u = static_cast<unsigned>(opaque(tid));
+  __builtin_assume(u < static_cast<unsigned>(NT));
+  return u;
+}
+
+// pad() of an unsigned index.
+__device__ __forceinline__ unsigned padu(unsigned e) { return e + (e >> 5); }
+
+// f(e) for e = ut, ut + NT, ut + 2 NT, ... below N (ut < NT the thread index): unrolled,
+// with a bound test only where N is not a multiple of NT.
+template <int N, int NT, typename F>
+__device__ __forceinline__ void for_strided(unsigned ut, F&& f) {
+  constexpr int IT = (N + NT - 1) / NT;
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned e = ut + i * NT;
+    if (N % NT == 0 || e < static_cast<unsigned>(N)) f(e);
+  }
+}
+
 // exp(DIR * 2 pi i j / R) for the twiddles inside the radix-8 and radix-16 butterflies.
 template <int R, int DIR>
 __device__ __forceinline__ float2 unit_root(int j) {
@@ -171,8 +195,17 @@ __device__ __forceinline__ void apply_twiddles_lds(float2* v, const float2* tp, 
   }
 }
 
+// The same with the powers already read (w[r - 1] = T_P[(r - 1) P + k]).
+template <int R, int DIR>
+__device__ __forceinline__ void apply_twiddle_regs(float2* v, const float2* w) {
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = DIR < 0 ? cmul(v[r], w[r - 1]) : cmulc(v[r], w[r - 1]);
+}
+
 // One Stockham pass of radix R over NB transforms of length N, span P (product of the
-// radices of the passes before it), executed by NTH threads.
+// radices of the passes before it), executed by NTH threads.  The LDS twiddles (read-only)
+// are read before the pass's barrier together with the data, so that their latency is
+// not added after it.
 //
 // Offsets.  With the base index B = off + t st + (i or j0) SI a multiple-of-32 apart from
 // a value below the butterfly's span, pad(B + o_r) = pad(B) + pad(o_r) for the load
@@ -185,13 +218,16 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
   constexpr int TOT = NBF * NB;            // butterflies per pass
   constexpr int BPT = (TOT + NTH - 1) / NTH;
   constexpr bool EXACT = (TOT % NTH) == 0;
+  constexpr bool TWR = TWL && P > 1;  // twiddles read with the data
   float2 v[BPT][R];
-  int base[BPT], idx[BPT];
-  tid = opaque(tid);
+  float2 w[BPT][TWR ? R - 1 : 1];
+  unsigned base[BPT], idx[BPT];
+  const unsigned ut = opaque_tid<NTH>(tid);
+  const unsigned uoff = static_cast<unsigned>(off), ust = static_cast<unsigned>(st);
 #pragma unroll
   for (int s = 0; s < BPT; ++s) {
-    const int b = tid + s * NTH;
-    int t, i;
+    const unsigned b = ut + s * NTH;
+    unsigned t, i;
     if constexpr (TFAST) {
       t = b % NB;
       i = b / NB;
@@ -199,41 +235,44 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
       t = b / NBF;
       i = b % NBF;
     }
-    base[s] = off + t * st;
+    base[s] = uoff + t * ust;
     idx[s] = i;
     if (EXACT || b < TOT) {
       if constexpr (ALIGNED) {
-        const float2* src = lds + pad(base[s] + i * SI);
+        const float2* src = lds + padu(base[s] + i * SI);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[s][r] = src[pad(r * NBF * SI)];
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[s][r] = lds[pad(base[s] + (i + r * NBF) * SI)];
+        for (int r = 0; r < R; ++r) v[s][r] = lds[padu(base[s] + (i + r * NBF) * SI)];
+      }
+      if constexpr (TWR) {
+        const float2* tp = tw + i % P;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[s][r - 1] = tp[(r - 1) * P];
       }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < BPT; ++s) {
-    const int b = tid + s * NTH;
+    const unsigned b = ut + s * NTH;
     if (EXACT || b < TOT) {
-      const int i = idx[s];
-      const int k = i % P;  // P is a compile-time constant (a shift and mask when a power of two)
-      if constexpr (P > 1) {
-        if constexpr (TWL)
-          apply_twiddles_lds<R, DIR>(v[s], tw + k, P);
-        else
-          apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
-      }
+      const unsigned i = idx[s];
+      const unsigned k = i % P;  // P is a compile-time constant (a shift and mask when a power of two)
+      if constexpr (TWR)
+        apply_twiddle_regs<R, DIR>(v[s], w[s]);
+      else if constexpr (P > 1)
+        apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
       dft<R, DIR>(v[s]);
-      const int j0 = (i - k) * R + k;
+      const unsigned j0 = (i - k) * R + k;
       if constexpr (ALIGNED) {
-        float2* dst = lds + pad(base[s] + j0 * SI);
+        float2* dst = lds + padu(base[s] + j0 * SI);
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[pad(r * P * SI)] = v[s][out_slot<R>(r)];
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[pad(base[s] + (j0 + r * P) * SI)] = v[s][out_slot<R>(r)];
+        for (int r = 0; r < R; ++r) lds[padu(base[s] + (j0 + r * P) * SI)] = v[s][out_slot<R>(r)];
       }
     }
   }

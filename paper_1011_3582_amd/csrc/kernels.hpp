@@ -53,6 +53,14 @@ struct RowGeom {
   static constexpr int LDS_TOTAL = LDS + (FUSE_STORE ? 2 : 1) * NX;
 };
 
+// Batch slot p of the row kernels starts at LDS element p * slot_stride (padded); RB NX is
+// a multiple of 32, so pad(p RB NX + e) = p slot_stride + pad(e).
+template <int NX>
+constexpr int slot_stride() {
+  static_assert((RowGeom<NX>::RB * NX) % 32 == 0, "batch slots start at multiples of 32");
+  return pad(RowGeom<NX>::RB * NX);
+}
+
 // Per-pass twiddle tables of the row transforms in LDS after the data (callers have a
 // barrier between this and the first transform).
 template <int NX>
@@ -74,10 +82,32 @@ struct SpecGeom {
   int ny;       // column length
   int tw;       // tile width (power of two)
   int log2tw;
-  __device__ __forceinline__ int idx(int y, int k) const {
+  __device__ __forceinline__ unsigned idx(unsigned y, unsigned k) const {
     return ((k >> log2tw) * ny + y) * tw + (k & (tw - 1));
   }
 };
+
+// Element i of an array at a wave-uniform base, addressed by a 32-bit byte offset (every
+// plane is far below 4 GB): the access takes the base in scalar registers and needs no
+// 64-bit address arithmetic per lane.  The base MUST be the same in every lane of the
+// wave (it is taken from the first active lane; every caller passes kernel arguments
+// plus uniform offsets); it is then made opaque in scalar registers so that the compiler
+// cannot fold the address arithmetic of different planes into 64-bit per-lane sums.
+using gbyte = __attribute__((address_space(1))) char;  // global-memory byte
+
+template <typename T>
+__device__ __forceinline__ T& elem(T* base, unsigned i) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(base);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+  gbyte* b = (gbyte*)((static_cast<unsigned long long>(hi) << 32) | lo);
+  asm("" : "+s"(b));
+  return *(T*)(b + i * static_cast<unsigned>(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T& elem(const T* base, unsigned i) {
+  return elem(const_cast<T*>(base), i);
+}
 
 // Pointers into the workspace (and the caller's buffers for the init/set modes).
 struct Planes {
@@ -97,6 +127,20 @@ struct Planes {
   long plane;        // nx * ny
   SpecGeom sg;
 };
+
+// The workspace pointers of an instance are never null (the host fills every one):
+// asserting it lets the compiler drop the null tests of the batch helpers, whose
+// branches would otherwise split the address arithmetic of the spectral accesses.
+__device__ __forceinline__ void assume_planes(const Planes& P) {
+  __builtin_assume(P.f != nullptr);
+  __builtin_assume(P.sf != nullptr);
+  __builtin_assume(P.sm != nullptr);
+  __builtin_assume(P.s1 != nullptr);
+  __builtin_assume(P.s2i != nullptr);
+  __builtin_assume(P.s2o != nullptr);
+  __builtin_assume(P.macro != nullptr);
+  __builtin_assume(P.cpl != nullptr);
+}
 
 // Multiplier kinds of the multi-output column pass.
 enum : int {
@@ -187,19 +231,27 @@ __device__ __forceinline__ float rounded(float x) {
   return x;
 }
 
-// Row groups: thread -> (row within block, lane within row).
+// Row groups: thread -> (row within block rl, lane within row lt).  Sites are addressed
+// from the first site of the block's rows (a wave-uniform base): site(j) = rl NX + x(j).
 template <int NX>
 struct RowThread {
-  int rl, lt, y;
-  __device__ __forceinline__ RowThread(int tid, int blk) {
-    rl = tid / RowGeom<NX>::TPR;
-    lt = tid % RowGeom<NX>::TPR;
-    y = blk * RowGeom<NX>::RB + rl;
+  static constexpr int TPR = RowGeom<NX>::TPR;
+  unsigned rl, lt;
+  __device__ __forceinline__ explicit RowThread(int tid) {
+    const unsigned u = static_cast<unsigned>(tid);
+    __builtin_assume(u < static_cast<unsigned>(RowGeom<NX>::NT));
+    rl = u / TPR;
+    lt = u % TPR;
   }
-  __device__ __forceinline__ int x(int j) const { return lt + j * RowGeom<NX>::TPR; }
-  // LDS element of site x(j) in batch slot `slot`
-  __device__ __forceinline__ int at(int slot, int j) const {
-    return pad((slot * RowGeom<NX>::RB + rl) * NX + x(j));
+  __device__ __forceinline__ unsigned x(int j) const { return lt + j * TPR; }
+  __device__ __forceinline__ unsigned site(int j) const { return rl * NX + x(j); }
+  // LDS element of site x(j) in batch slot `slot` (slots start at multiples of 32)
+  __device__ __forceinline__ unsigned at(int slot, int j) const {
+    constexpr unsigned SL = slot_stride<NX>();
+    if constexpr (TPR % 32 == 0)
+      return slot * SL + padu(rl * NX + lt) + j * pad(TPR);
+    else
+      return slot * SL + padu(rl * NX + x(j));
   }
 };
 
@@ -210,68 +262,88 @@ struct RowThread {
 // A derivative along x alone never needs a column transform: it is a row-spectral product.
 enum : int { TERM_ONE = 0, TERM_IKX = 1, TERM_KXX = 2 };
 
+// Which terms are present is kept in flags of their own (`on`), so that where a batch is
+// built from set_term calls the presence is a compile-time fact and the loads need no
+// runtime tests.
 template <int NP>
 struct PairBatch {
-  const float2* s[NP][2][2];  // [pair][a, b][term]; null = absent
+  const float2* s[NP][2][2];  // [pair][a, b][term]
   float c[NP][2][2];
   int kind[NP][2][2];
+  bool on[NP][2][2];          // term present
 };
 
+// A batch with no terms (pairs left without terms load as zero).
 template <int NP>
-__device__ __forceinline__ PairBatch<NP> plain_batch(const float2* const (&a)[NP], const float2* const (&b)[NP]) {
+__device__ __forceinline__ PairBatch<NP> empty_batch() {
   PairBatch<NP> r;
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    r.s[p][0][0] = a[p];
-    r.s[p][1][0] = b[p];
-    r.s[p][0][1] = r.s[p][1][1] = nullptr;
+  for (int p = 0; p < NP; ++p)
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
+        r.s[p][h][t] = nullptr;
         r.c[p][h][t] = 1.0f;
         r.kind[p][h][t] = TERM_ONE;
+        r.on[p][h][t] = false;
       }
-  }
   return r;
 }
 
+// Term t of side h (0 = a, 1 = b) of pair p: c m(kx) s, s a valid spectrum (never null).
 template <int NP>
 __device__ __forceinline__ void set_term(PairBatch<NP>& b, int p, int h, int t, const float2* s, float c, int kind) {
   b.s[p][h][t] = s;
   b.c[p][h][t] = c;
   b.kind[p][h][t] = kind;
+  b.on[p][h][t] = true;
+}
+
+// a[p] + i b[p] as they are; a null pointer is an absent side (tested at run time).
+template <int NP>
+__device__ __forceinline__ PairBatch<NP> plain_batch(const float2* const (&a)[NP], const float2* const (&b)[NP]) {
+  PairBatch<NP> r = empty_batch<NP>();
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    r.s[p][0][0] = a[p];
+    r.s[p][1][0] = b[p];
+    r.on[p][0][0] = a[p] != nullptr;
+    r.on[p][1][0] = b[p] != nullptr;
+  }
+  return r;
 }
 
 template <int NP>
 struct PairBatchOut {
   float2* a[NP];
-  float2* b[NP];         // may be null
+  float2* b[NP];
+  bool hb[NP];           // b[p] present
 };
 
-// Value of one side of a pair at (row spectrum index gi, column k), k = 0 packed.
+// Value of one side of a pair at row-spectrum index gi.  The k_x table is zero at column 0
+// (both of its packed entries, DC and Nyquist, have k_x = 0), so the packed column needs
+// no case of its own.
 template <int NP>
-__device__ __forceinline__ float2 combo_value(const PairBatch<NP>& in, int p, int h, int gi, int k, float kx) {
+__device__ __forceinline__ float2 combo_value(const PairBatch<NP>& in, int p, int h, unsigned gi, float kx) {
   float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
+    if (!in.on[p][h][t]) continue;
     const float2* __restrict__ S = in.s[p][h][t];
-    if (!S) continue;
-    const float2 v = S[gi];
+    const float2 v = elem(S, gi);
     const float c = in.c[p][h][t];
     const int kd = in.kind[p][h][t];
     if (kd == TERM_ONE) {
       acc.x += c * v.x;
       acc.y += c * v.y;
-    } else if (k != 0) {   // both packed entries of column 0 have k_x = 0
-      if (kd == TERM_IKX) {
-        acc.x -= c * kx * v.y;
-        acc.y += c * kx * v.x;
-      } else {
-        const float m = -c * kx * kx;
-        acc.x += m * v.x;
-        acc.y += m * v.y;
-      }
+    } else if (kd == TERM_IKX) {
+      acc.x -= c * kx * v.y;
+      acc.y += c * kx * v.x;
+    } else {
+      const float m = -c * kx * kx;
+      acc.x += m * v.x;
+      acc.y += m * v.y;
     }
   }
   return acc;
@@ -279,120 +351,113 @@ __device__ __forceinline__ float2 combo_value(const PairBatch<NP>& in, int p, in
 
 // LDS slot p <- Z(k) = A(k) + i B(k), k = 0..NX-1, for every row of the block, from the
 // packed half spectra described by `in`; Hermitian completion of the upper half.
-// kapx (nx/2 windowed k_x values) must always be a valid table.
+// kapx (nx/2 windowed k_x values, zero at column 0) must always be a valid table.
+// The packed column k = 0 (A = (A(0), A(H)), B likewise, all real) is handled by masks
+// and selects rather than a branch, so that all loads of the batch form one basic block
+// (issued together, addressed from scalar bases).
 template <int NX, int NP>
 __device__ __forceinline__ void rows_load_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
                                                 const float* __restrict__ kapx, int row0, int tid) {
-  constexpr int H = NX / 2;
+  constexpr unsigned H = NX / 2;
   constexpr int RB = RowGeom<NX>::RB;
   constexpr int NT = RowGeom<NX>::NT;
-  tid = opaque(tid);
+  constexpr int SL = slot_stride<NX>();
+  const unsigned ut = opaque_tid<NT>(tid);
+  for_strided<RB * H, NT>(ut, [&](unsigned e) {
+    const unsigned rl = e / H, k = e % H;
+    const bool k0 = k == 0;
+    const float m = k0 ? 0.0f : 1.0f;
+    const unsigned gi = sg.idx(row0 + rl, k);
+    const float kx = elem(kapx, k);
+    const unsigned z = rl * NX;
+    const unsigned l0 = padu(z + k), l1 = padu(z + (k0 ? H : NX - k));
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    for (int e = tid; e < RB * H; e += NT) {
-      const int rl = e / H, k = e % H;
-      const int gi = sg.idx(row0 + rl, k);
-      const float kx = kapx[k];
-      const float2 a = combo_value(in, p, 0, gi, k, kx);
-      const float2 b = combo_value(in, p, 1, gi, k, kx);
-      const int z = (p * RB + rl) * NX;
-      if (k == 0) {
-        lds[pad(z)] = make_float2(a.x, b.x);
-        lds[pad(z + H)] = make_float2(a.y, b.y);
-      } else {
-        lds[pad(z + k)] = make_float2(a.x - b.y, a.y + b.x);
-        lds[pad(z + NX - k)] = make_float2(a.x + b.y, b.x - a.y);
-      }
+    for (int p = 0; p < NP; ++p) {
+      const float2 a = combo_value(in, p, 0, gi, kx);
+      const float2 b = combo_value(in, p, 1, gi, kx);
+      float2* L = lds + p * SL;
+      // k > 0: Z(k) = a + i b, Z(N - k) = conj(a) + i conj(b);
+      // k = 0: Z(0) = A(0) + i B(0) = (a.x, b.x), Z(H) = (a.y, b.y)
+      L[l0] = make_float2(fmaf(-m, b.y, a.x), fmaf(m, a.y, b.x));
+      L[l1] = make_float2(k0 ? a.y : a.x + b.y, k0 ? b.y : b.x - a.y);
     }
-    __builtin_amdgcn_sched_barrier(0);
-  }
+  });
 }
 
 // Packed half spectra of A = Re z and B = Im z from the forward transforms Z in LDS slots.
 template <int NX, int NP>
 __device__ __forceinline__ void rows_store_batch(const float2* lds, const PairBatchOut<NP>& out,
                                                  const SpecGeom& sg, int row0, int tid) {
-  constexpr int H = NX / 2;
+  constexpr unsigned H = NX / 2;
   constexpr int RB = RowGeom<NX>::RB;
   constexpr int NT = RowGeom<NX>::NT;
-  tid = opaque(tid);
+  constexpr int SL = slot_stride<NX>();
+  const unsigned ut = opaque_tid<NT>(tid);
+  for_strided<RB * H, NT>(ut, [&](unsigned e) {
+    const unsigned rl = e / H, k = e % H;
+    const bool k0 = k == 0;
+    const unsigned z = rl * NX;
+    const unsigned l0 = padu(z + k), l1 = padu(z + (k0 ? H : NX - k));
+    const unsigned gi = sg.idx(row0 + rl, k);
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    float2* __restrict__ OA = out.a[p];
-    float2* __restrict__ OB = out.b[p];
-    for (int e = tid; e < RB * H; e += NT) {
-      const int rl = e / H, k = e % H;
-      const int z = (p * RB + rl) * NX;
-      const float2 Z = lds[pad(z + k)];
-      float2 A, B;
-      if (k == 0) {
-        const float2 W = lds[pad(z + H)];
-        A = make_float2(Z.x, W.x);
-        B = make_float2(Z.y, W.y);
-      } else {
-        const float2 W = lds[pad(z + NX - k)];
-        A = make_float2(0.5f * (Z.x + W.x), 0.5f * (Z.y - W.y));
-        B = make_float2(0.5f * (Z.y + W.y), 0.5f * (W.x - Z.x));
-      }
-      const int gi = sg.idx(row0 + rl, k);
-      OA[gi] = A;
-      if (OB) OB[gi] = B;
+    for (int p = 0; p < NP; ++p) {
+      const float2 Z = lds[p * SL + l0], W = lds[p * SL + l1];
+      // k > 0: A = (Z + conj W) / 2, B = (Z - conj W) / (2i) with W = Z(N - k);
+      // k = 0 (W = Z(H)): A = (Z.x, W.x), B = (Z.y, W.y)
+      const float2 A = make_float2(k0 ? Z.x : 0.5f * (Z.x + W.x), k0 ? W.x : 0.5f * (Z.y - W.y));
+      const float2 B = make_float2(k0 ? Z.y : 0.5f * (Z.y + W.y), k0 ? W.y : 0.5f * (W.x - Z.x));
+      elem(out.a[p], gi) = A;
+      if (out.hb[p]) elem(out.b[p], gi) = B;
     }
-  }
+  });
 }
 
 // Store of the packed half spectra with the last (radix-2, span H) forward pass fused in:
-// the thread for spectral columns k and H - k computes the butterflies i = k and i = H - k
-// (inputs i, i + H, twiddle w_i = tw_last[i]; outputs X(i) = y(i) + w y(i + H) and
-// X(i + H) = y(i) - w y(i + H)), which yield X at k, N - k, H - k and H + k, and separates
-// both columns.
+// the thread for spectral column k (0 <= k <= Q = H/2) computes the butterflies i = k and
+// i = H - k (inputs i, i + H, twiddle w_i = tw_last[i]; outputs X(i) = y(i) + w y(i + H)
+// and X(i + H) = y(i) - w y(i + H)), which yield X at k, N - k, H - k and H + k, and
+// separates columns k and H - k.  k = Q is its own partner (both stores agree).  The
+// thread of the packed column k = 0 takes butterfly Q as its partner (in range, unused),
+// and its partner store goes to column 0 first and is overwritten by the right value.
+// No branches: all stores of the batch stay in one basic block.
 template <int NX, int NP>
 __device__ __forceinline__ void rows_store_batch_r2(const float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
                                                     const float2* tw_last, int row0, int tid) {
-  constexpr int H = NX / 2, Q = H / 2, W = Q + 1;
+  constexpr unsigned H = NX / 2, Q = H / 2, W = Q + 1;
   constexpr int RB = RowGeom<NX>::RB;
   constexpr int NT = RowGeom<NX>::NT;
-  tid = opaque(tid);
+  constexpr int SL = slot_stride<NX>();
+  const unsigned ut = opaque_tid<NT>(tid);
+  for_strided<RB * W, NT>(ut, [&](unsigned e) {
+    const unsigned rl = e / W, k = e % W;
+    const bool k0 = k == 0;
+    const unsigned k2 = k0 ? Q : H - k;
+    const unsigned z = rl * NX;
+    const unsigned lk = padu(z + k), lkh = padu(z + k + H);
+    const unsigned lk2 = padu(z + k2), lk2h = padu(z + k2 + H);
+    const float2 w1 = tw_last[k], w2 = tw_last[k2];
+    const unsigned gi = sg.idx(row0 + rl, k);
+    const unsigned gi2 = k0 ? gi : sg.idx(row0 + rl, k2);
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    float2* __restrict__ OA = out.a[p];
-    float2* __restrict__ OB = out.b[p];
-    for (int e = tid; e < RB * W; e += NT) {
-      const int rl = e / W, k = e % W;
-      const int z = (p * RB + rl) * NX;
-      // butterfly k
-      const float2 t = cmul(lds[pad(z + k + H)], tw_last[k]);
-      const float2 u = lds[pad(z + k)];
-      const float2 Xk = cadd(u, t), Xkh = csub(u, t);   // X(k), X(k + H)
-      float2 A, B;
-      if (k == 0) {  // X(0), X(H): the packed DC and Nyquist column
-        A = make_float2(Xk.x, Xkh.x);
-        B = make_float2(Xk.y, Xkh.y);
-      } else {
-        float2 Xnk;  // X(N - k)
-        if (k == Q) {
-          Xnk = Xkh;  // N - Q = H + Q
-        } else {
-          const int k2 = H - k;
-          const float2 t2 = cmul(lds[pad(z + k2 + H)], tw_last[k2]);
-          const float2 u2 = lds[pad(z + k2)];
-          const float2 Xk2 = cadd(u2, t2);  // X(H - k)
-          Xnk = csub(u2, t2);                // X(H - k + H) = X(N - k)
-          // column H - k from X(H - k) and X(N - (H - k)) = X(H + k)
-          const float2 A2 = make_float2(0.5f * (Xk2.x + Xkh.x), 0.5f * (Xk2.y - Xkh.y));
-          const float2 B2 = make_float2(0.5f * (Xk2.y + Xkh.y), 0.5f * (Xkh.x - Xk2.x));
-          const int gi2 = sg.idx(row0 + rl, k2);
-          OA[gi2] = A2;
-          if (OB) OB[gi2] = B2;
-        }
-        A = make_float2(0.5f * (Xk.x + Xnk.x), 0.5f * (Xk.y - Xnk.y));
-        B = make_float2(0.5f * (Xk.y + Xnk.y), 0.5f * (Xnk.x - Xk.x));
-      }
-      const int gi = sg.idx(row0 + rl, k);
-      OA[gi] = A;
-      if (OB) OB[gi] = B;
+    for (int p = 0; p < NP; ++p) {
+      const float2* L = lds + p * SL;
+      const float2 t = cmul(L[lkh], w1), u = L[lk];
+      const float2 Xk = cadd(u, t), Xkh = csub(u, t);     // X(k), X(k + H)
+      const float2 t2 = cmul(L[lk2h], w2), u2 = L[lk2];
+      const float2 Xk2 = cadd(u2, t2);                    // X(H - k)
+      const float2 Xn = k0 ? Xk : csub(u2, t2);           // X(N - k) (k = 0: X(0))
+      // column H - k from X(H - k) and X(N - (H - k)) = X(H + k)
+      const float2 A2 = make_float2(0.5f * (Xk2.x + Xkh.x), 0.5f * (Xk2.y - Xkh.y));
+      const float2 B2 = make_float2(0.5f * (Xk2.y + Xkh.y), 0.5f * (Xkh.x - Xk2.x));
+      // column k; for k = 0 the packed (X(0), X(H)): A = (X(0).x, X(H).x), B = (X(0).y, X(H).y)
+      const float2 A = make_float2(0.5f * (Xk.x + Xn.x), k0 ? Xkh.x : 0.5f * (Xk.y - Xn.y));
+      const float2 B = make_float2(0.5f * (Xk.y + Xn.y), k0 ? Xkh.y : 0.5f * (Xn.x - Xk.x));
+      elem(out.a[p], gi2) = A2;
+      if (out.hb[p]) elem(out.b[p], gi2) = B2;
+      elem(out.a[p], gi) = A;
+      if (out.hb[p]) elem(out.b[p], gi) = B;
     }
-  }
+  });
 }
 
 // Inverse row transforms of a batch; afterwards slot p holds a_p(x) + i b_p(x).  twx: the
@@ -458,34 +523,40 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
   const float2* twy = In.twy;
   const float* __restrict__ kapx = In.kapx;
   const float* __restrict__ kapy = In.kapy;
-  const int nx = In.nx, tw = In.tw;
+  const int nx = In.nx;
+  const unsigned tw = In.tw;
   const float scale = In.scale;
   const int tid = threadIdx.x;
+  const unsigned ut = static_cast<unsigned>(tid);
+  __builtin_assume(ut < static_cast<unsigned>(NT));
   twy = col_twiddles<NY, R>(lds + lds_alloc(NY * CW), twy, tid, NT);
   const int nsub = (nx / 2) / CW;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int p = conv_column_plane(b / nsub), sub = b % nsub;
-  const int c0 = sub * CW;
+  const unsigned c0 = sub * CW;
   float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
-  for (int e = tid; e < NY * CW; e += NT) {
-    const int y = e / CW, c = e % CW;
-    lds[pad(e)] = g[y * tw + c];
-  }
+  // element e of the block is (y, c) = (e / CW, e % CW); NT is a multiple of CW, so c and
+  // the k_x multiplier are fixed per thread
+  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
+    const unsigned y = e / CW, c = e % CW;
+    lds[padu(e)] = elem(g, y * tw + c);
+  });
   __syncthreads();
   fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
   const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
-  for (int e = tid; e < NY * CW; e += NT) {
-    const int y = e / CW, c = e % CW;
-    const float m = (vx * kapx[c0 + c] + vy * kapy[y]) * scale;
-    const float2 v = lds[pad(e)];
-    lds[pad(e)] = make_float2(-m * v.y, m * v.x);
-  }
+  const float mx = vx * elem(kapx, c0 + ut % CW);
+  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
+    const unsigned y = e / CW;
+    const float m = (mx + vy * elem(kapy, y)) * scale;
+    const float2 v = lds[padu(e)];
+    lds[padu(e)] = make_float2(-m * v.y, m * v.x);
+  });
   __syncthreads();
   fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
-  for (int e = tid; e < NY * CW; e += NT) {
-    const int y = e / CW, c = e % CW;
-    g[y * tw + c] = lds[pad(e)];
-  }
+  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
+    const unsigned y = e / CW, c = e % CW;
+    elem(g, y * tw + c) = lds[padu(e)];
+  });
 }
 
 // Column pass of derivative groups: forward column FFT of nin input spectra, then for
@@ -497,35 +568,38 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
   extern __shared__ float2 lds[];
   const float* __restrict__ kapx = In.kapx;
   const float* __restrict__ kapy = In.kapy;
-  const int tw = In.tw;
+  const unsigned tw = In.tw;
   const float scale = In.scale;
   const long hp = (long)(In.nx / 2) * NY;  // complex values per spectral plane
   const int tid = threadIdx.x;
+  const unsigned ut = static_cast<unsigned>(tid);
+  __builtin_assume(ut < static_cast<unsigned>(NT));
   const float2* twy = col_twiddles<NY, R>(lds + lds_alloc(4 * NY * CW), In.twy, tid, NT);
   const ColGroup& G = L.g[blockIdx.y];
-  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
+  const unsigned c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
   const long off = (long)(c0 / tw) * NY * tw + (c0 % tw);
   constexpr int BLK = NY * CW;  // input p occupies elements [p BLK, (p + 1) BLK)
   constexpr bool AL = is_pow2(NY) && (BLK % 32 == 0);
   for (int p = 0; p < G.nin; ++p) {
     const float2* g = In.spec + G.in[p] * hp + off;
-    for (int e = tid; e < BLK; e += NT) {
-      const int y = e / CW, c = e % CW;
-      lds[pad(p * BLK + e)] = g[y * tw + c];
-    }
+    for_strided<BLK, NT>(ut, [&](unsigned e) {
+      const unsigned y = e / CW, c = e % CW;
+      lds[padu(p * BLK + e)] = elem(g, y * tw + c);
+    });
   }
   __syncthreads();
   for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true, CW, AL, R>(lds, p * BLK, 1, twy, tid);
   const int wb = 3 * BLK;  // work block (after the largest input set)
+  const float kx = elem(kapx, c0 + ut % CW);  // NT is a multiple of CW: the column is fixed per thread
   for (int o = 0; o < G.nout; ++o) {
-    for (int e = tid; e < BLK; e += NT) {
-      const int y = e / CW, c = e % CW;
-      const float kx = kapx[c0 + c], ky = kapy[y];
+    for (unsigned e = ut; e < BLK; e += NT) {
+      const unsigned y = e / CW;
+      const float ky = elem(kapy, y);
       float re = 0.0f, im = 0.0f;
       for (int p = 0; p < G.nin; ++p) {
         const int kd = G.kind[o][p];
         if (kd == MK_NONE) continue;
-        const float2 v = lds[pad(p * BLK + e)];
+        const float2 v = lds[padu(p * BLK + e)];
         if (kd == MK_IKX || kd == MK_IKY) {
           const float kk = kd == MK_IKX ? kx : ky;
           re -= kk * v.y;
@@ -539,15 +613,15 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
           im += m * v.y;
         }
       }
-      lds[pad(wb + e)] = make_float2(re * scale, im * scale);
+      lds[padu(wb + e)] = make_float2(re * scale, im * scale);
     }
     __syncthreads();
     fft_lds<NY, +1, NT, CW, true, CW, AL, R>(lds, wb, 1, twy, tid);
     float2* g = In.spec + G.out[o] * hp + off;
-    for (int e = tid; e < BLK; e += NT) {
-      const int y = e / CW, c = e % CW;
-      g[y * tw + c] = lds[pad(wb + e)];
-    }
+    for_strided<BLK, NT>(ut, [&](unsigned e) {
+      const unsigned y = e / CW, c = e % CW;
+      elem(g, y * tw + c) = lds[padu(wb + e)];
+    });
     __syncthreads();
   }
 }
@@ -567,19 +641,20 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
   // twiddles from the global table here: an LDS copy would cost this kernel one of its
   // four blocks per CU
   const float2* twx = P.twx;
-  const RowThread<NX> rt(tid, blk);
+  const RowThread<NX> rt(tid);
   const int row0 = blk * G::RB;
-  const long rowoff = (long)rt.y * P.nx;
+  const long rb = (long)row0 * NX;  // first site of the block's rows
+  const float* mac = P.macro + rb;
   const long hp = P.plane / 2;
 
   float rho[J], ux[J], uy[J], T[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const long s = rowoff + rt.x(j);
-    rho[j] = P.macro[s];
-    ux[j] = P.macro[P.plane + s];
-    uy[j] = P.macro[2 * P.plane + s];
-    T[j] = P.macro[3 * P.plane + s];
+    const unsigned s = rt.site(j);
+    rho[j] = elem(mac, s);
+    ux[j] = elem(mac + P.plane, s);
+    uy[j] = elem(mac + 2 * P.plane, s);
+    T[j] = elem(mac + 3 * P.plane, s);
   }
   // The 11 stage-1 derivatives d = rx, ry, lap, dxux, dyux, dxuy, dyuy, thx, thy, Tx, Ty.
   // x-derivatives are row-spectral products of the moment spectra R, Ux, Uy, Th (scaled by
@@ -590,11 +665,7 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
     const float inx = 1.0f / P.nx;
     const float2 *R = P.sm, *Ux = P.sm + hp, *Uy = P.sm + 2 * hp, *Th = P.sm + 3 * hp;
     const float2* s1 = P.s1;
-    PairBatch<4> b;
-    {
-      const float2* a[4] = {nullptr, nullptr, nullptr, nullptr};
-      b = plain_batch<4>(a, a);
-    }
+    PairBatch<4> b = empty_batch<4>();
     set_term(b, 0, 0, 0, R, inx, TERM_IKX);                 // rx
     set_term(b, 0, 1, 0, s1, 1.0f, TERM_ONE);               // ry
     set_term(b, 1, 0, 0, R, inx, TERM_KXX);                 // lap = D_xx rho + D_yy rho
@@ -622,11 +693,7 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
       d[6][j] = v.y;
     }
     __syncthreads();
-    PairBatch<2> b2;
-    {
-      const float2* a[2] = {nullptr, nullptr};
-      b2 = plain_batch<2>(a, a);
-    }
+    PairBatch<2> b2 = empty_batch<2>();
     set_term(b2, 0, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);     // thy
     set_term(b2, 0, 1, 0, Th, inx, TERM_IKX);               // Tx
     set_term(b2, 1, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);     // Ty
@@ -669,7 +736,7 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
     const float num = (Pw - rT) * theta + lam_du - M.zeta * theta * theta + M.a * r * r * theta +
                       M.K * (-0.5f * grad2 * theta - r * (rx * thx + ry * thy) - cubic);
     const float C = num / (2.0f * rT * t);
-    P.cpl[rowoff + rt.x(j)] = C;
+    elem(P.cpl + rb, rt.site(j)) = C;
     const float u2 = ux[j] * ux[j] + uy[j] * uy[j];
     const double e = (double)rT - (double)M.a * r * r + 0.5 * (double)M.K * grad2 + 0.5 * (double)r * u2;
     acc[0] += r;
@@ -680,7 +747,7 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
     bad |= nonfinite(r) | nonfinite(t) | nonfinite(u2) | nonfinite(C);
   }
   // forward row transforms of the five fields whose divergences the force needs
-  PairBatchOut<3> o{{P.s2i, P.s2i + 2 * hp, P.s2i + 4 * hp}, {P.s2i + hp, P.s2i + 3 * hp, nullptr}};
+  PairBatchOut<3> o{{P.s2i, P.s2i + 2 * hp, P.s2i + 4 * hp}, {P.s2i + hp, P.s2i + 3 * hp, nullptr}, {true, true, false}};
   rows_forward_batch<NX, 3, false>(lds, o, P.sg, twx, row0, tid);
 
   // block reduction of the diagnostics (fixed order: deterministic)
@@ -717,6 +784,7 @@ template <int NX>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(RowArgs A) {
   const int s = blockIdx.y;
   if (retired(A.state, A.id[s])) return;
+  assume_planes(A.P[s]);
   rows_stage2<NX>(A.P[s], A.M[s], blockIdx.x);
 }
 
@@ -734,34 +802,37 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   constexpr int GPR = G::NPB / 4;   // speed groups per round
   const int tid = threadIdx.x;
   const float2* twx = row_twiddles<NX>(lds, P.twx, tid);
-  const RowThread<NX> rt(tid, blk);
+  const RowThread<NX> rt(tid);
   const int row0 = blk * G::RB;
-  const long rowoff = (long)rt.y * P.nx;
+  const long rb = (long)row0 * NX;  // first site of the block's rows
+  float* mac = P.macro + rb;
   const long hp = P.plane / 2;
 
   Site st[J];
   if constexpr (MODE == MODE_STEP) {
-    const float2* a2[2] = {P.s2o, P.s2o + 2 * hp};
-    const float2* b2[2] = {P.s2o + hp, nullptr};
-    rows_inverse_batch<NX, 2>(lds, plain_batch<2>(a2, b2), P.sg, twx, P.kapx, row0, tid);
+    PairBatch<2> b2 = empty_batch<2>();
+    set_term(b2, 0, 0, 0, P.s2o, 1.0f, TERM_ONE);           // B^x
+    set_term(b2, 0, 1, 0, P.s2o + hp, 1.0f, TERM_ONE);      // B^y
+    set_term(b2, 1, 0, 0, P.s2o + 2 * hp, 1.0f, TERM_ONE);  // G
+    rows_inverse_batch<NX, 2>(lds, b2, P.sg, twx, P.kapx, row0, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const long s = rowoff + rt.x(j);
+      const unsigned s = rt.site(j);
       const float2 bxy = lds[rt.at(0, j)];
       const float gd = lds[rt.at(1, j)].x;
-      const float r = P.macro[s], ux = P.macro[P.plane + s], uy = P.macro[2 * P.plane + s];
-      const float t = P.macro[3 * P.plane + s];
+      const float r = elem(mac, s), ux = elem(mac + P.plane, s), uy = elem(mac + 2 * P.plane, s);
+      const float t = elem(mac + 3 * P.plane, s);
       site_init(st[j], r, ux, uy, t);
       const float irT = 1.0f / (r * t);
-      const float cc = P.cpl[s] + 0.5f * gd * irT * st[j].iT;   // C + C_q, C_q = G / (2 rho T^2)
+      const float cc = elem(P.cpl + rb, s) + 0.5f * gd * irT * st[j].iT;   // C + C_q, C_q = G / (2 rho T^2)
       site_force(st[j], bxy.x * irT, bxy.y * irT, cc);
     }
     __syncthreads();
   } else if constexpr (MODE == MODE_INIT) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const long s = rowoff + rt.x(j);
-      site_init(st[j], in.a[0][s], in.a[1][s], in.a[2][s], in.a[3][s]);
+      const unsigned s = rt.site(j);
+      site_init(st[j], elem(in.a[0] + rb, s), elem(in.a[1] + rb, s), elem(in.a[2] + rb, s), elem(in.a[3] + rb, s));
     }
   }
 
@@ -769,16 +840,16 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // rest particle
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const long s = rowoff + rt.x(j);
+    const unsigned s = rt.site(j);
     float fn;
     if constexpr (MODE == MODE_STEP) {
-      fn = relax_update(st[j], M, P.f[s], feq_rest(st[j]), 0.0f, 0.0f, 0.0f, 0.0f);
+      fn = relax_update(st[j], M, elem(P.f + rb, s), feq_rest(st[j]), 0.0f, 0.0f, 0.0f, 0.0f);
     } else if constexpr (MODE == MODE_INIT) {
       fn = rounded(feq_rest(st[j]));
     } else {
-      fn = in.a[0][s];
+      fn = elem(in.a[0] + rb, s);
     }
-    P.f[s] = fn;
+    elem(P.f + rb, s) = fn;
     m0[j] = fn;
     mx[j] = my[j] = me[j] = 0.0f;
   }
@@ -786,7 +857,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1)
 #pragma unroll 1
   for (int rd = 0; rd < 4 / GPR; ++rd) {
-    const RowThread<NX> rt(opaque(tid), blk);
+    const RowThread<NX> rt(opaque(tid));
     const int q0 = 1 + 8 * GPR * rd;
     float2* S = P.sf + (long)(q0 - 1) * hp;  // spectra of q0 .. q0 + 8 GPR - 1 are consecutive planes
     PairBatchOut<G::NPB> io;
@@ -794,16 +865,15 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     for (int p = 0; p < G::NPB; ++p) {
       io.a[p] = S + 2 * p * hp;
       io.b[p] = S + (2 * p + 1) * hp;
+      io.hb[p] = true;
     }
     if constexpr (MODE == MODE_STEP) {
-      const float2* ia[G::NPB];
-      const float2* ib[G::NPB];
+      PairBatch<G::NPB> in = empty_batch<G::NPB>();
 #pragma unroll
       for (int p = 0; p < G::NPB; ++p) {
-        ia[p] = io.a[p];
-        ib[p] = io.b[p];
+        set_term(in, p, 0, 0, io.a[p], 1.0f, TERM_ONE);
+        set_term(in, p, 1, 0, io.b[p], 1.0f, TERM_ONE);
       }
-      PairBatch<G::NPB> in = plain_batch<G::NPB>(ia, ib);
       // directions i = 1 and 5 (v along +-x) skip the column pass: their convection term
       // v_x D_x f is the row-spectral product i v_x k_x S / nx
 #pragma unroll
@@ -829,30 +899,30 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         const int qa = q0 + 2 * slot, qb = qa + 1;
         const float vxa = c_vel.vx[qa], vya = c_vel.vy[qa];
         const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
-        float* fA = P.f + (long)qa * P.plane + rowoff;
-        float* fB = P.f + (long)qb * P.plane + rowoff;
+        float* fA = P.f + (long)qa * P.plane + rb;
+        float* fB = P.f + (long)qb * P.plane + rb;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-          const int x = rt.x(j);
-          const int li = rt.at(slot, j);
+          const unsigned x = rt.site(j);
+          const unsigned li = rt.at(slot, j);
           float fa, fb;
           if constexpr (MODE == MODE_SET) {
-            fa = in.a[0][(long)qa * P.plane + rowoff + x];
-            fb = in.a[0][(long)qb * P.plane + rowoff + x];
+            fa = elem(in.a[0] + (long)qa * P.plane + rb, x);
+            fb = elem(in.a[0] + (long)qb * P.plane + rb, x);
           } else {
             const float ea = feq_moving(st[j], ge[j], vxa, vya);
             const float eb = feq_moving(st[j], ge[j], vxb, vyb);
             if constexpr (MODE == MODE_STEP) {
               const float2 c = lds[li];
-              fa = relax_update(st[j], M, fA[x], ea, c.x, vxa, vya, v2);
-              fb = relax_update(st[j], M, fB[x], eb, c.y, vxb, vyb, v2);
+              fa = relax_update(st[j], M, elem(fA, x), ea, c.x, vxa, vya, v2);
+              fb = relax_update(st[j], M, elem(fB, x), eb, c.y, vxb, vyb, v2);
             } else {
               fa = rounded(ea);
               fb = rounded(eb);
             }
           }
-          fA[x] = fa;
-          fB[x] = fb;
+          elem(fA, x) = fa;
+          elem(fB, x) = fb;
           m0[j] += fa + fb;
           mx[j] += vxa * fa + vxb * fb;
           my[j] += vya * fa + vyb * fb;
@@ -868,19 +938,19 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // moments of the new state and their row spectra
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const long s = rowoff + rt.x(j);
+    const unsigned s = rt.site(j);
     const float r = m0[j];
     const float ir = 1.0f / r;
     const float ux = mx[j] * ir, uy = my[j] * ir;
     const float T = 0.5f * me[j] * ir - 0.5f * (ux * ux + uy * uy);
-    P.macro[s] = r;
-    P.macro[P.plane + s] = ux;
-    P.macro[2 * P.plane + s] = uy;
-    P.macro[3 * P.plane + s] = T;
+    elem(mac, s) = r;
+    elem(mac + P.plane, s) = ux;
+    elem(mac + 2 * P.plane, s) = uy;
+    elem(mac + 3 * P.plane, s) = T;
     lds[rt.at(0, j)] = make_float2(r, ux);
     lds[rt.at(1, j)] = make_float2(uy, T);
   }
-  PairBatchOut<2> mo{{P.sm, P.sm + 2 * hp}, {P.sm + hp, P.sm + 3 * hp}};
+  PairBatchOut<2> mo{{P.sm, P.sm + 2 * hp}, {P.sm + hp, P.sm + 3 * hp}, {true, true}};
   rows_forward_batch<NX, 2>(lds, mo, P.sg, twx, row0, tid);
 }
 
@@ -888,6 +958,7 @@ template <int NX, int MODE>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(RowArgs A, Inputs in) {
   const int s = blockIdx.y;
   if (retired(A.state, A.id[s])) return;
+  assume_planes(A.P[s]);
   rows_collide<NX, MODE>(A.P[s], A.M[s], in, blockIdx.x);
 }
 
@@ -899,18 +970,19 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_momentum(RowArgs A) {
   if (retired(A.state, A.id[slot])) return;
   extern __shared__ float2 lds[];
   const Planes& P = A.P[slot];
+  assume_planes(P);
   const int tid = threadIdx.x;
-  const RowThread<NX> rt(tid, blockIdx.x);
-  const long rowoff = (long)rt.y * P.nx;
+  const RowThread<NX> rt(tid);
+  const float* mac = P.macro + (long)blockIdx.x * RowGeom<NX>::RB * NX;
   const long hp = P.plane / 2;
   const float2* twx = row_twiddles<NX>(lds, P.twx, tid);
 #pragma unroll
   for (int j = 0; j < RowGeom<NX>::J; ++j) {
-    const long s = rowoff + rt.x(j);
-    const float r = P.macro[s];
-    lds[rt.at(0, j)] = make_float2(r * P.macro[P.plane + s], r * P.macro[2 * P.plane + s]);
+    const unsigned s = rt.site(j);
+    const float r = elem(mac, s);
+    lds[rt.at(0, j)] = make_float2(r * elem(mac + P.plane, s), r * elem(mac + 2 * P.plane, s));
   }
-  PairBatchOut<1> o{{P.s1}, {P.s1 + hp}};
+  PairBatchOut<1> o{{P.s1}, {P.s1 + hp}, {true}};
   rows_forward_batch<NX, 1>(lds, o, P.sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
 }
 
@@ -926,13 +998,14 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_residual(RowArgs A) {
   if (retired(A.state, A.id[slot])) return;
   extern __shared__ float2 lds[];
   const Planes& P = A.P[slot];
+  assume_planes(P);
   const int tid = threadIdx.x;
-  const RowThread<NX> rt(tid, blockIdx.x);
+  const RowThread<NX> rt(tid);
   const long hp = P.plane / 2;
   const float2* twx = row_twiddles<NX>(lds, P.twx, tid);
-  const float2* a1[1] = {P.s1 + 2 * hp};
-  const float2* b1[1] = {nullptr};
-  rows_inverse_batch<NX, 1>(lds, plain_batch<1>(a1, b1), P.sg, twx, P.kapx, blockIdx.x * RowGeom<NX>::RB, tid);
+  PairBatch<1> b1 = empty_batch<1>();
+  set_term(b1, 0, 0, 0, P.s1 + 2 * hp, 1.0f, TERM_ONE);
+  rows_inverse_batch<NX, 1>(lds, b1, P.sg, twx, P.kapx, blockIdx.x * RowGeom<NX>::RB, tid);
   float m = 0.0f;
   int bad = 0;
 #pragma unroll
@@ -970,15 +1043,15 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_real(const flo
                                                                        const float2* twx, int nx) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
-  const RowThread<NX> rt(tid, blockIdx.x);
-  const long rowoff = (long)rt.y * nx;
+  const RowThread<NX> rt(tid);
+  const long rb = (long)blockIdx.x * RowGeom<NX>::RB * NX;
 #pragma unroll
   for (int j = 0; j < RowGeom<NX>::J; ++j) {
-    const long s = rowoff + rt.x(j);
-    lds[rt.at(0, j)] = make_float2(a[s], b ? b[s] : 0.0f);
+    const unsigned s = rt.site(j);
+    lds[rt.at(0, j)] = make_float2(elem(a + rb, s), b ? elem(b + rb, s) : 0.0f);
   }
   twx = row_twiddles<NX>(lds, twx, tid);
-  PairBatchOut<1> o{{sa}, {sb}};
+  PairBatchOut<1> o{{sa}, {sb}, {sb != nullptr}};
   rows_forward_batch<NX, 1>(lds, o, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
 }
 
@@ -990,18 +1063,18 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_inverse_real(const flo
                                                                        const float* __restrict__ kapx, int nx) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
-  const RowThread<NX> rt(tid, blockIdx.x);
-  const long rowoff = (long)rt.y * nx;
+  const RowThread<NX> rt(tid);
+  const long rb = (long)blockIdx.x * RowGeom<NX>::RB * NX;
   const float2* a1[1] = {sa};
   twx = row_twiddles<NX>(lds, twx, tid);
   const float2* b1[1] = {sb};
   rows_inverse_batch<NX, 1>(lds, plain_batch<1>(a1, b1), sg, twx, kapx, blockIdx.x * RowGeom<NX>::RB, tid);
 #pragma unroll
   for (int j = 0; j < RowGeom<NX>::J; ++j) {
-    const long s = rowoff + rt.x(j);
+    const unsigned s = rt.site(j);
     const float2 v = lds[rt.at(0, j)];
-    a[s] = v.x;
-    if (b) b[s] = v.y;
+    elem(a + rb, s) = v.x;
+    if (b) elem(b + rb, s) = v.y;
   }
 }
 

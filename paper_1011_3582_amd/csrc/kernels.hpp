@@ -321,17 +321,56 @@ struct PairBatchOut {
   bool hb[NP];           // b[p] present
 };
 
-// Value of one side of a pair at row-spectrum index gi.  The k_x table is zero at column 0
+// Loading a batch is split in two so that callers can issue the global loads early:
+// rows_fetch_batch reads the raw spectral values of every present term (and k_x) into
+// registers, rows_put_batch combines them and writes the LDS slots.
+template <int NX, int NP>
+struct BatchFetch {
+  static constexpr int IT = (RowGeom<NX>::RB * (NX / 2) + RowGeom<NX>::NT - 1) / RowGeom<NX>::NT;
+  float2 v[IT][NP][2][2];
+  float kx[IT];
+};
+
+template <int NX, int NP>
+__device__ __forceinline__ BatchFetch<NX, NP> rows_fetch_batch(const PairBatch<NP>& in, const SpecGeom& sg,
+                                                               const float* __restrict__ kapx, int row0, int tid) {
+  constexpr unsigned H = NX / 2;
+  constexpr int RB = RowGeom<NX>::RB;
+  constexpr int NT = RowGeom<NX>::NT;
+  using F = BatchFetch<NX, NP>;
+  F r;
+  const unsigned ut = opaque_tid<NT>(tid);
+#pragma unroll
+  for (int it = 0; it < F::IT; ++it) {
+    const unsigned e = ut + it * NT;
+    if (RB * H % NT == 0 || e < RB * H) {
+      const unsigned rl = e / H, k = e % H;
+      const unsigned gi = sg.idx(row0 + rl, k);
+      r.kx[it] = elem(kapx, k);
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+            if (in.on[p][h][t]) r.v[it][p][h][t] = elem(in.s[p][h][t], gi);
+    }
+  }
+  return r;
+}
+
+// Value of one side of a pair from its fetched terms.  The k_x table is zero at column 0
 // (both of its packed entries, DC and Nyquist, have k_x = 0), so the packed column needs
 // no case of its own.
-template <int NP>
-__device__ __forceinline__ float2 combo_value(const PairBatch<NP>& in, int p, int h, unsigned gi, float kx) {
+template <int NX, int NP>
+__device__ __forceinline__ float2 combo_value(const PairBatch<NP>& in, const BatchFetch<NX, NP>& F, int it, int p,
+                                              int h) {
   float2 acc = make_float2(0.0f, 0.0f);
+  const float kx = F.kx[it];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     if (!in.on[p][h][t]) continue;
-    const float2* __restrict__ S = in.s[p][h][t];
-    const float2 v = elem(S, gi);
+    const float2 v = F.v[it][p][h][t];
     const float c = in.c[p][h][t];
     const int kd = in.kind[p][h][t];
     if (kd == TERM_ONE) {
@@ -350,38 +389,46 @@ __device__ __forceinline__ float2 combo_value(const PairBatch<NP>& in, int p, in
 }
 
 // LDS slot p <- Z(k) = A(k) + i B(k), k = 0..NX-1, for every row of the block, from the
-// packed half spectra described by `in`; Hermitian completion of the upper half.
-// kapx (nx/2 windowed k_x values, zero at column 0) must always be a valid table.
-// The packed column k = 0 (A = (A(0), A(H)), B likewise, all real) is handled by masks
-// and selects rather than a branch, so that all loads of the batch form one basic block
-// (issued together, addressed from scalar bases).
+// fetched packed half spectra; Hermitian completion of the upper half.  The packed column
+// k = 0 (A = (A(0), A(H)), B likewise, all real) is handled by masks and selects rather
+// than a branch, so that all accesses of the batch stay in one basic block.
 template <int NX, int NP>
-__device__ __forceinline__ void rows_load_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
-                                                const float* __restrict__ kapx, int row0, int tid) {
+__device__ __forceinline__ void rows_put_batch(float2* lds, const PairBatch<NP>& in, const BatchFetch<NX, NP>& F,
+                                               int tid) {
   constexpr unsigned H = NX / 2;
   constexpr int RB = RowGeom<NX>::RB;
   constexpr int NT = RowGeom<NX>::NT;
   constexpr int SL = slot_stride<NX>();
   const unsigned ut = opaque_tid<NT>(tid);
-  for_strided<RB * H, NT>(ut, [&](unsigned e) {
-    const unsigned rl = e / H, k = e % H;
-    const bool k0 = k == 0;
-    const float m = k0 ? 0.0f : 1.0f;
-    const unsigned gi = sg.idx(row0 + rl, k);
-    const float kx = elem(kapx, k);
-    const unsigned z = rl * NX;
-    const unsigned l0 = padu(z + k), l1 = padu(z + (k0 ? H : NX - k));
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const float2 a = combo_value(in, p, 0, gi, kx);
-      const float2 b = combo_value(in, p, 1, gi, kx);
-      float2* L = lds + p * SL;
-      // k > 0: Z(k) = a + i b, Z(N - k) = conj(a) + i conj(b);
-      // k = 0: Z(0) = A(0) + i B(0) = (a.x, b.x), Z(H) = (a.y, b.y)
-      L[l0] = make_float2(fmaf(-m, b.y, a.x), fmaf(m, a.y, b.x));
-      L[l1] = make_float2(k0 ? a.y : a.x + b.y, k0 ? b.y : b.x - a.y);
+  for (int it = 0; it < BatchFetch<NX, NP>::IT; ++it) {
+    const unsigned e = ut + it * NT;
+    if (RB * H % NT == 0 || e < RB * H) {
+      const unsigned rl = e / H, k = e % H;
+      const bool k0 = k == 0;
+      const float m = k0 ? 0.0f : 1.0f;
+      const unsigned z = rl * NX;
+      const unsigned l0 = padu(z + k), l1 = padu(z + (k0 ? H : NX - k));
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const float2 a = combo_value(in, F, it, p, 0);
+        const float2 b = combo_value(in, F, it, p, 1);
+        float2* L = lds + p * SL;
+        // k > 0: Z(k) = a + i b, Z(N - k) = conj(a) + i conj(b);
+        // k = 0: Z(0) = A(0) + i B(0) = (a.x, b.x), Z(H) = (a.y, b.y)
+        L[l0] = make_float2(fmaf(-m, b.y, a.x), fmaf(m, a.y, b.x));
+        L[l1] = make_float2(k0 ? a.y : a.x + b.y, k0 ? b.y : b.x - a.y);
+      }
     }
-  });
+  }
+}
+
+// Both steps at once.  kapx (nx/2 windowed k_x values, zero at column 0) must always be a
+// valid table.
+template <int NX, int NP>
+__device__ __forceinline__ void rows_load_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
+                                                const float* __restrict__ kapx, int row0, int tid) {
+  rows_put_batch<NX, NP>(lds, in, rows_fetch_batch<NX, NP>(in, sg, kapx, row0, tid), tid);
 }
 
 // Packed half spectra of A = Re z and B = Im z from the forward transforms Z in LDS slots.
@@ -854,7 +901,33 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     mx[j] = my[j] = me[j] = 0.0f;
   }
   // moving populations: each round covers GPR speed groups (8 GPR populations, 4 GPR
-  // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1)
+  // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1).
+  // The convection spectra of a round are the consecutive planes q0 - 1 .. q0 + 8 GPR - 2;
+  // directions i = 1 and 5 (v along +-x) skipped the column pass: their convection term
+  // v_x D_x f is the row-spectral product i v_x k_x S / nx.
+  auto conv_batch = [&](int rd) {
+    const int q0 = 1 + 8 * GPR * rd;
+    const float2* S = P.sf + (long)(q0 - 1) * hp;
+    PairBatch<G::NPB> in = empty_batch<G::NPB>();
+#pragma unroll
+    for (int p = 0; p < G::NPB; ++p) {
+      set_term(in, p, 0, 0, S + 2 * p * hp, 1.0f, TERM_ONE);
+      set_term(in, p, 1, 0, S + (2 * p + 1) * hp, 1.0f, TERM_ONE);
+    }
+#pragma unroll
+    for (int g = 0; g < GPR; ++g) {
+      const int qx0 = q0 + 8 * g, qx4 = qx0 + 4;
+      set_term(in, 4 * g + 0, 0, 0, S + (8 * g + 0) * hp, c_vel.vx[qx0] / P.nx, TERM_IKX);
+      set_term(in, 4 * g + 2, 0, 0, S + (8 * g + 4) * hp, c_vel.vx[qx4] / P.nx, TERM_IKX);
+    }
+    return in;
+  };
+  // With J = 2 the loads of a round are issued ahead: the next round's convection spectra
+  // during this round's forward transforms, f^n of the round's populations during its
+  // inverse transforms (16 registers each).
+  constexpr bool PREF = MODE == MODE_STEP && J == 2;
+  BatchFetch<NX, G::NPB> cf;
+  if constexpr (PREF) cf = rows_fetch_batch<NX, G::NPB>(conv_batch(0), P.sg, P.kapx, row0, tid);
 #pragma unroll 1
   for (int rd = 0; rd < 4 / GPR; ++rd) {
     const RowThread<NX> rt(opaque(tid));
@@ -867,22 +940,22 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       io.b[p] = S + (2 * p + 1) * hp;
       io.hb[p] = true;
     }
+    float fpre[PREF ? 2 * G::NPB : 1][J];
+    if constexpr (PREF) {
+#pragma unroll
+      for (int i = 0; i < 2 * G::NPB; ++i)
+#pragma unroll
+        for (int j = 0; j < J; ++j) fpre[i][j] = elem(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
+    }
     if constexpr (MODE == MODE_STEP) {
-      PairBatch<G::NPB> in = empty_batch<G::NPB>();
-#pragma unroll
-      for (int p = 0; p < G::NPB; ++p) {
-        set_term(in, p, 0, 0, io.a[p], 1.0f, TERM_ONE);
-        set_term(in, p, 1, 0, io.b[p], 1.0f, TERM_ONE);
+      const PairBatch<G::NPB> in = conv_batch(rd);
+      if constexpr (PREF) {
+        rows_put_batch<NX, G::NPB>(lds, in, cf, tid);
+        __syncthreads();
+        fft_lds<NX, +1, G::NT, G::NPB * G::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), G::RADIX>(lds, 0, NX, twx, tid);
+      } else {
+        rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, twx, P.kapx, row0, tid);
       }
-      // directions i = 1 and 5 (v along +-x) skip the column pass: their convection term
-      // v_x D_x f is the row-spectral product i v_x k_x S / nx
-#pragma unroll
-      for (int g = 0; g < GPR; ++g) {
-        const int qx0 = q0 + 8 * g, qx4 = qx0 + 4;
-        set_term(in, 4 * g + 0, 0, 0, io.a[4 * g + 0], c_vel.vx[qx0] / P.nx, TERM_IKX);
-        set_term(in, 4 * g + 2, 0, 0, io.a[4 * g + 2], c_vel.vx[qx4] / P.nx, TERM_IKX);
-      }
-      rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, twx, P.kapx, row0, tid);
     }
 #pragma unroll
     for (int g = 0; g < GPR; ++g) {
@@ -914,8 +987,10 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
             const float eb = feq_moving(st[j], ge[j], vxb, vyb);
             if constexpr (MODE == MODE_STEP) {
               const float2 c = lds[li];
-              fa = relax_update(st[j], M, elem(fA, x), ea, c.x, vxa, vya, v2);
-              fb = relax_update(st[j], M, elem(fB, x), eb, c.y, vxb, vyb, v2);
+              const float f0a = PREF ? fpre[2 * slot][j] : elem(fA, x);
+              const float f0b = PREF ? fpre[2 * slot + 1][j] : elem(fB, x);
+              fa = relax_update(st[j], M, f0a, ea, c.x, vxa, vya, v2);
+              fb = relax_update(st[j], M, f0b, eb, c.y, vxb, vyb, v2);
             } else {
               fa = rounded(ea);
               fb = rounded(eb);
@@ -929,9 +1004,13 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
           me[j] += v2 * (fa + fb);
           lds[li] = make_float2(fa, fb);
         }
-        // keep one pair's loads in flight at a time: bounds the live registers
-        __builtin_amdgcn_sched_barrier(0);
+        // without prefetch: keep one pair's loads in flight at a time (bounds the live
+        // registers)
+        if constexpr (!PREF) __builtin_amdgcn_sched_barrier(0);
       }
+    }
+    if constexpr (PREF) {
+      if (rd + 1 < 4 / GPR) cf = rows_fetch_batch<NX, G::NPB>(conv_batch(rd + 1), P.sg, P.kapx, row0, tid);
     }
     rows_forward_batch<NX, G::NPB>(lds, io, P.sg, twx, row0, tid);
   }

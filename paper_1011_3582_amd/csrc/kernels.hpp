@@ -507,16 +507,22 @@ __device__ __forceinline__ void rows_store_batch_r2(const float2* lds, const Pai
   });
 }
 
-// Inverse row transforms of a batch; afterwards slot p holds a_p(x) + i b_p(x).  twx: the
-// per-pass LDS tables (TWL) or the global table.
+// Inverse row transforms of the NP slots in LDS (after a barrier); afterwards slot p holds
+// a_p(x) + i b_p(x).  twx: the per-pass LDS tables (TWL) or the global table.
+template <int NX, int NP, bool TWL = true>
+__device__ __forceinline__ void rows_inverse_fft(float2* lds, const float2* twx, int tid) {
+  using G = RowGeom<NX>;
+  constexpr bool AL = is_pow2(NX) && (NX % 32 == 0);
+  fft_lds<NX, +1, G::NT, NP * G::RB, false, 1, AL, G::RADIX, TWL>(lds, 0, NX, twx, tid);
+}
+
+// Load and inverse row transforms of a batch.
 template <int NX, int NP, bool TWL = true>
 __device__ __forceinline__ void rows_inverse_batch(float2* lds, const PairBatch<NP>& in, const SpecGeom& sg,
                                                    const float2* twx, const float* kapx, int row0, int tid) {
-  using G = RowGeom<NX>;
-  constexpr bool AL = is_pow2(NX) && (NX % 32 == 0);
   rows_load_batch<NX, NP>(lds, in, sg, kapx, row0, tid);
   __syncthreads();
-  fft_lds<NX, +1, G::NT, NP * G::RB, false, 1, AL, G::RADIX, TWL>(lds, 0, NX, twx, tid);
+  rows_inverse_fft<NX, NP, TWL>(lds, twx, tid);
 }
 
 // Forward row transforms of slots already written (unsynchronised) and store of the packed
@@ -723,7 +729,17 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
     set_term(b, 2, 1, 1, s1 + 3 * hp, 1.0f, TERM_IKX);
     set_term(b, 3, 0, 0, Uy, inx, TERM_IKX);                // dxuy
     set_term(b, 3, 1, 0, s1 + 3 * hp, 1.0f, TERM_ONE);      // dyuy
-    rows_inverse_batch<NX, 4, false>(lds, b, P.sg, twx, P.kapx, row0, tid);
+    PairBatch<2> b2 = empty_batch<2>();
+    set_term(b2, 0, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);     // thy
+    set_term(b2, 0, 1, 0, Th, inx, TERM_IKX);               // Tx
+    set_term(b2, 1, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);     // Ty
+    // both batches are read at once; the second waits in registers during the first's
+    // transforms
+    const BatchFetch<NX, 4> f1 = rows_fetch_batch<NX, 4>(b, P.sg, P.kapx, row0, tid);
+    const BatchFetch<NX, 2> f2 = rows_fetch_batch<NX, 2>(b2, P.sg, P.kapx, row0, tid);
+    rows_put_batch<NX, 4>(lds, b, f1, tid);
+    __syncthreads();
+    rows_inverse_fft<NX, 4, false>(lds, twx, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float2 v = lds[rt.at(0, j)];
@@ -740,11 +756,9 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
       d[6][j] = v.y;
     }
     __syncthreads();
-    PairBatch<2> b2 = empty_batch<2>();
-    set_term(b2, 0, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);     // thy
-    set_term(b2, 0, 1, 0, Th, inx, TERM_IKX);               // Tx
-    set_term(b2, 1, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);     // Ty
-    rows_inverse_batch<NX, 2, false>(lds, b2, P.sg, twx, P.kapx, row0, tid);
+    rows_put_batch<NX, 2>(lds, b2, f2, tid);
+    __syncthreads();
+    rows_inverse_fft<NX, 2, false>(lds, twx, tid);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const float2 v = lds[rt.at(0, j)];
@@ -855,23 +869,64 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   float* mac = P.macro + rb;
   const long hp = P.plane / 2;
 
+  // moving populations: each round covers GPR speed groups (8 GPR populations, 4 GPR
+  // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1).
+  // The convection spectra of a round are the consecutive planes q0 - 1 .. q0 + 8 GPR - 2;
+  // directions i = 1 and 5 (v along +-x) skipped the column pass: their convection term
+  // v_x D_x f is the row-spectral product i v_x k_x S / nx.
+  auto conv_batch = [&](int rd) {
+    const int q0 = 1 + 8 * GPR * rd;
+    const float2* S = P.sf + (long)(q0 - 1) * hp;
+    PairBatch<G::NPB> in = empty_batch<G::NPB>();
+#pragma unroll
+    for (int p = 0; p < G::NPB; ++p) {
+      set_term(in, p, 0, 0, S + 2 * p * hp, 1.0f, TERM_ONE);
+      set_term(in, p, 1, 0, S + (2 * p + 1) * hp, 1.0f, TERM_ONE);
+    }
+#pragma unroll
+    for (int g = 0; g < GPR; ++g) {
+      const int qx0 = q0 + 8 * g, qx4 = qx0 + 4;
+      set_term(in, 4 * g + 0, 0, 0, S + (8 * g + 0) * hp, c_vel.vx[qx0] / P.nx, TERM_IKX);
+      set_term(in, 4 * g + 2, 0, 0, S + (8 * g + 4) * hp, c_vel.vx[qx4] / P.nx, TERM_IKX);
+    }
+    return in;
+  };
+  // With J = 2 the loads of a round are issued ahead: the next round's convection spectra
+  // during this round's forward transforms (the first round's during the force
+  // transforms), f^n of the round's populations during its inverse transforms (16
+  // registers each).
+  constexpr bool PREF = MODE == MODE_STEP && J == 2;
+  BatchFetch<NX, G::NPB> cf;
   Site st[J];
   if constexpr (MODE == MODE_STEP) {
     PairBatch<2> b2 = empty_batch<2>();
     set_term(b2, 0, 0, 0, P.s2o, 1.0f, TERM_ONE);           // B^x
     set_term(b2, 0, 1, 0, P.s2o + hp, 1.0f, TERM_ONE);      // B^y
     set_term(b2, 1, 0, 0, P.s2o + 2 * hp, 1.0f, TERM_ONE);  // G
-    rows_inverse_batch<NX, 2>(lds, b2, P.sg, twx, P.kapx, row0, tid);
+    const BatchFetch<NX, 2> f2 = rows_fetch_batch<NX, 2>(b2, P.sg, P.kapx, row0, tid);
+    // the site's moments and C, read while the force spectra are transformed
+    float mr[J], mux[J], muy[J], mt[J], mc[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const unsigned s = rt.site(j);
+      mr[j] = elem(mac, s);
+      mux[j] = elem(mac + P.plane, s);
+      muy[j] = elem(mac + 2 * P.plane, s);
+      mt[j] = elem(mac + 3 * P.plane, s);
+      mc[j] = elem(P.cpl + rb, s);
+    }
+    if constexpr (PREF) cf = rows_fetch_batch<NX, G::NPB>(conv_batch(0), P.sg, P.kapx, row0, tid);
+    rows_put_batch<NX, 2>(lds, b2, f2, tid);
+    __syncthreads();
+    rows_inverse_fft<NX, 2>(lds, twx, tid);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
       const float2 bxy = lds[rt.at(0, j)];
       const float gd = lds[rt.at(1, j)].x;
-      const float r = elem(mac, s), ux = elem(mac + P.plane, s), uy = elem(mac + 2 * P.plane, s);
-      const float t = elem(mac + 3 * P.plane, s);
-      site_init(st[j], r, ux, uy, t);
+      const float r = mr[j], t = mt[j];
+      site_init(st[j], r, mux[j], muy[j], t);
       const float irT = 1.0f / (r * t);
-      const float cc = elem(P.cpl + rb, s) + 0.5f * gd * irT * st[j].iT;   // C + C_q, C_q = G / (2 rho T^2)
+      const float cc = mc[j] + 0.5f * gd * irT * st[j].iT;   // C + C_q, C_q = G / (2 rho T^2)
       site_force(st[j], bxy.x * irT, bxy.y * irT, cc);
     }
     __syncthreads();
@@ -900,34 +955,6 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     m0[j] = fn;
     mx[j] = my[j] = me[j] = 0.0f;
   }
-  // moving populations: each round covers GPR speed groups (8 GPR populations, 4 GPR
-  // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1).
-  // The convection spectra of a round are the consecutive planes q0 - 1 .. q0 + 8 GPR - 2;
-  // directions i = 1 and 5 (v along +-x) skipped the column pass: their convection term
-  // v_x D_x f is the row-spectral product i v_x k_x S / nx.
-  auto conv_batch = [&](int rd) {
-    const int q0 = 1 + 8 * GPR * rd;
-    const float2* S = P.sf + (long)(q0 - 1) * hp;
-    PairBatch<G::NPB> in = empty_batch<G::NPB>();
-#pragma unroll
-    for (int p = 0; p < G::NPB; ++p) {
-      set_term(in, p, 0, 0, S + 2 * p * hp, 1.0f, TERM_ONE);
-      set_term(in, p, 1, 0, S + (2 * p + 1) * hp, 1.0f, TERM_ONE);
-    }
-#pragma unroll
-    for (int g = 0; g < GPR; ++g) {
-      const int qx0 = q0 + 8 * g, qx4 = qx0 + 4;
-      set_term(in, 4 * g + 0, 0, 0, S + (8 * g + 0) * hp, c_vel.vx[qx0] / P.nx, TERM_IKX);
-      set_term(in, 4 * g + 2, 0, 0, S + (8 * g + 4) * hp, c_vel.vx[qx4] / P.nx, TERM_IKX);
-    }
-    return in;
-  };
-  // With J = 2 the loads of a round are issued ahead: the next round's convection spectra
-  // during this round's forward transforms, f^n of the round's populations during its
-  // inverse transforms (16 registers each).
-  constexpr bool PREF = MODE == MODE_STEP && J == 2;
-  BatchFetch<NX, G::NPB> cf;
-  if constexpr (PREF) cf = rows_fetch_batch<NX, G::NPB>(conv_batch(0), P.sg, P.kapx, row0, tid);
 #pragma unroll 1
   for (int rd = 0; rd < 4 / GPR; ++rd) {
     const RowThread<NX> rt(opaque(tid));
@@ -952,7 +979,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       if constexpr (PREF) {
         rows_put_batch<NX, G::NPB>(lds, in, cf, tid);
         __syncthreads();
-        fft_lds<NX, +1, G::NT, G::NPB * G::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), G::RADIX>(lds, 0, NX, twx, tid);
+        rows_inverse_fft<NX, G::NPB>(lds, twx, tid);
       } else {
         rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, twx, P.kapx, row0, tid);
       }

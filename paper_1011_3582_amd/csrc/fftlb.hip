@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -143,6 +144,7 @@ ColGroup group(std::initializer_list<int> in, std::initializer_list<int> out,
   ColGroup g{};
   g.nin = (int)in.size();
   g.nout = (int)out.size();
+  if (!multi_shape_ok(g.nin, g.nout)) throw std::logic_error("derivative group shape without a column-pass body");
   int i = 0;
   for (int p : in) g.in[i++] = p;
   i = 0;

@@ -612,70 +612,108 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
   });
 }
 
-// Column pass of derivative groups: forward column FFT of nin input spectra, then for
-// each output a linear combination sum_p m_op(kx, ky) X_p, inverse column FFT, store.
+// Column pass of derivative groups: forward column FFTs of the nin input spectra, then
+// each output the linear combination sum_p m_op(kx, ky) X_p, inverse column FFTs, store.
+//
+// LDS layout: the CW columns of up to kMultiSlots planes interleaved by row, column c of
+// plane slot p at element (y, p CW + c), i.e. lds[pad(y SI + p CW + c)] with SI =
+// kMultiSlots CW, so that the transforms of all nin inputs (and later of all nout
+// outputs) are one batched call: transform t = p CW + c, element y at t + y SI.  The
+// combination is done in place by the thread that owns (y, c) of every slot.  Group
+// shapes (nin, nout) are compile-time in the body; the kernel dispatches on them.
+constexpr int kMultiSlots = 4;
+
+__device__ __forceinline__ float2 mk_apply(int kd, float kx, float ky, float2 v) {
+  // m v for the multiplier kinds: i k_x, i k_y (imaginary), -k_x^2, -k_y^2, -k_x k_y,
+  // -(k_x^2 + k_y^2) (real)
+  const float ai = kd == MK_IKX ? kx : kd == MK_IKY ? ky : 0.0f;
+  const float ar = kd == MK_KXX   ? -kx * kx
+                 : kd == MK_KYY   ? -ky * ky
+                 : kd == MK_KXY   ? -kx * ky
+                 : kd == MK_LAP   ? -(kx * kx + ky * ky)
+                                  : 0.0f;
+  return make_float2(ar * v.x - ai * v.y, ar * v.y + ai * v.x);
+}
+
+template <int NY, int CW, int NT, int R, int NIN, int NOUT>
+__device__ __forceinline__ void col_multi_body(const ColInst& In, const ColGroup& G, float2* lds, const float2* twy,
+                                               unsigned ut, int tid, unsigned c0, long off) {
+  static_assert(NIN <= kMultiSlots && NOUT <= kMultiSlots, "group shape");
+  constexpr int SI = kMultiSlots * CW;
+  constexpr int BLK = NY * CW;  // elements (y, c) of one plane
+  // power-of-two spans and strides: compile-time butterfly offsets (see stockham_pass)
+  constexpr bool AL = is_pow2(NY);
+  const unsigned tw = In.tw;
+  const long hp = (long)(In.nx / 2) * NY;  // complex values per spectral plane
+  const float scale = In.scale;
+#pragma unroll
+  for (int p = 0; p < NIN; ++p) {
+    const float2* g = In.spec + G.in[p] * hp + off;
+    for_strided<BLK, NT>(ut, [&](unsigned e) {
+      const unsigned y = e / CW, c = e % CW;
+      lds[padu(y * SI + p * CW + c)] = elem(g, y * tw + c);
+    });
+  }
+  __syncthreads();
+  fft_lds<NY, -1, NT, NIN * CW, true, SI, AL, R>(lds, 0, 1, twy, tid);
+  // NT is a multiple of CW: the column, and k_x, are fixed per thread
+  const float kx = elem(In.kapx, c0 + ut % CW);
+  int kd[NOUT][NIN];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+    for (int p = 0; p < NIN; ++p) kd[o][p] = G.kind[o][p];
+  for_strided<BLK, NT>(ut, [&](unsigned e) {
+    const unsigned y = e / CW, c = e % CW;
+    const float ky = elem(In.kapy, y);
+    float2 x[NIN];
+#pragma unroll
+    for (int p = 0; p < NIN; ++p) x[p] = lds[padu(y * SI + p * CW + c)];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int p = 0; p < NIN; ++p) acc = cadd(acc, mk_apply(kd[o][p], kx, ky, x[p]));
+      lds[padu(y * SI + o * CW + c)] = make_float2(acc.x * scale, acc.y * scale);
+    }
+  });
+  __syncthreads();
+  fft_lds<NY, +1, NT, NOUT * CW, true, SI, AL, R>(lds, 0, 1, twy, tid);
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    float2* g = In.spec + G.out[o] * hp + off;
+    for_strided<BLK, NT>(ut, [&](unsigned e) {
+      const unsigned y = e / CW, c = e % CW;
+      elem(g, y * tw + c) = lds[padu(y * SI + o * CW + c)];
+    });
+  }
+}
+
+// Group shapes with a compiled body (every group the solver builds has one of them).
+__host__ __device__ constexpr bool multi_shape_ok(int nin, int nout) {
+  return (nin == 1 && (nout == 1 || nout == 2)) || (nin == 2 && (nout == 1 || nout == 3)) || (nin == 3 && nout == 2);
+}
+
 template <int NY, int CW, int NT, int R>
 __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
   const ColInst& In = A.c[blockIdx.z];
   if (retired(A.state, In.id)) return;
   extern __shared__ float2 lds[];
-  const float* __restrict__ kapx = In.kapx;
-  const float* __restrict__ kapy = In.kapy;
-  const unsigned tw = In.tw;
-  const float scale = In.scale;
-  const long hp = (long)(In.nx / 2) * NY;  // complex values per spectral plane
   const int tid = threadIdx.x;
   const unsigned ut = static_cast<unsigned>(tid);
   __builtin_assume(ut < static_cast<unsigned>(NT));
-  const float2* twy = col_twiddles<NY, R>(lds + lds_alloc(4 * NY * CW), In.twy, tid, NT);
+  const float2* twy = col_twiddles<NY, R>(lds + lds_alloc(kMultiSlots * NY * CW), In.twy, tid, NT);
   const ColGroup& G = L.g[blockIdx.y];
+  const unsigned tw = In.tw;
   const unsigned c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
   const long off = (long)(c0 / tw) * NY * tw + (c0 % tw);
-  constexpr int BLK = NY * CW;  // input p occupies elements [p BLK, (p + 1) BLK)
-  constexpr bool AL = is_pow2(NY) && (BLK % 32 == 0);
-  for (int p = 0; p < G.nin; ++p) {
-    const float2* g = In.spec + G.in[p] * hp + off;
-    for_strided<BLK, NT>(ut, [&](unsigned e) {
-      const unsigned y = e / CW, c = e % CW;
-      lds[padu(p * BLK + e)] = elem(g, y * tw + c);
-    });
-  }
-  __syncthreads();
-  for (int p = 0; p < G.nin; ++p) fft_lds<NY, -1, NT, CW, true, CW, AL, R>(lds, p * BLK, 1, twy, tid);
-  const int wb = 3 * BLK;  // work block (after the largest input set)
-  const float kx = elem(kapx, c0 + ut % CW);  // NT is a multiple of CW: the column is fixed per thread
-  for (int o = 0; o < G.nout; ++o) {
-    for (unsigned e = ut; e < BLK; e += NT) {
-      const unsigned y = e / CW;
-      const float ky = elem(kapy, y);
-      float re = 0.0f, im = 0.0f;
-      for (int p = 0; p < G.nin; ++p) {
-        const int kd = G.kind[o][p];
-        if (kd == MK_NONE) continue;
-        const float2 v = lds[padu(p * BLK + e)];
-        if (kd == MK_IKX || kd == MK_IKY) {
-          const float kk = kd == MK_IKX ? kx : ky;
-          re -= kk * v.y;
-          im += kk * v.x;
-        } else {
-          const float m = kd == MK_KXX ? -kx * kx
-                        : kd == MK_KYY ? -ky * ky
-                        : kd == MK_KXY ? -kx * ky
-                                       : -(kx * kx + ky * ky);
-          re += m * v.x;
-          im += m * v.y;
-        }
-      }
-      lds[padu(wb + e)] = make_float2(re * scale, im * scale);
-    }
-    __syncthreads();
-    fft_lds<NY, +1, NT, CW, true, CW, AL, R>(lds, wb, 1, twy, tid);
-    float2* g = In.spec + G.out[o] * hp + off;
-    for_strided<BLK, NT>(ut, [&](unsigned e) {
-      const unsigned y = e / CW, c = e % CW;
-      elem(g, y * tw + c) = lds[padu(wb + e)];
-    });
-    __syncthreads();
+  switch (G.nin * 4 + G.nout) {
+    case 1 * 4 + 1: col_multi_body<NY, CW, NT, R, 1, 1>(In, G, lds, twy, ut, tid, c0, off); break;
+    case 1 * 4 + 2: col_multi_body<NY, CW, NT, R, 1, 2>(In, G, lds, twy, ut, tid, c0, off); break;
+    case 2 * 4 + 1: col_multi_body<NY, CW, NT, R, 2, 1>(In, G, lds, twy, ut, tid, c0, off); break;
+    case 2 * 4 + 3: col_multi_body<NY, CW, NT, R, 2, 3>(In, G, lds, twy, ut, tid, c0, off); break;
+    case 3 * 4 + 2: col_multi_body<NY, CW, NT, R, 3, 2>(In, G, lds, twy, ut, tid, c0, off); break;
+    default: break;  // not built by the host (multi_shape_ok)
   }
 }
 

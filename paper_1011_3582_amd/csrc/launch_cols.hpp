@@ -35,15 +35,16 @@ int col_conv_plan(const StepLaunch& L, hipStream_t s) {
 
 template <int NY, int CW, int R>
 int col_multi_plan(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
-  if constexpr (4 * NY * CW > kColLdsElems) {
+  if constexpr (kMultiSlots * NY * CW > kColLdsElems) {
     return FFTLB_EINVAL;
   } else {
     constexpr int NT = col_threads(NY, CW, R);
     for (int first = 0; first < L.ninst; first += kColSlots) {
       const int count = cmin(kColSlots, L.ninst - first);
-      // three input blocks and one work block
+      // kMultiSlots interleaved planes of CW columns, then the twiddle tables
       hipLaunchKernelGGL((k_col_multi<NY, CW, NT, R>), dim3((L.nx / 2) / CW, ngroups, count), dim3(NT),
-                         (lds_alloc(4 * NY * CW) + NY) * sizeof(float2), s, col_args(L, first, count, false), groups);
+                         (lds_alloc(kMultiSlots * NY * CW) + NY) * sizeof(float2), s, col_args(L, first, count, false),
+                         groups);
     }
     return FFTLB_OK;
   }

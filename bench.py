@@ -283,7 +283,7 @@ def main():
                           "kernel_ms": dict(zip(STAGES, kern_ms)),
                           "event_ms_per_step": ev_s / args.steps * 1e3},
         "globals": {k: glob[k] for k in ("mass", "energy", "residual", "umax")},
-        "plan": {"conv_cols": plan[0], "multi_cols": plan[1], "col_radix": plan[2]},
+        "plan": {"conv_cols": plan[0], "multi_cols": plan[1], "conv_radix": plan[2], "multi_radix": plan[3]},
     }
     if batch is not None:
         out["batch"] = batch

@@ -124,13 +124,12 @@ int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream);
 /* Column-pass plan of a handle: spectral columns per block of the convection pass and of
  * the derivative passes (powers of two up to 16, at most the tile width min(16, the
  * largest power of two dividing nx/2), and within 64 KB of LDS: ny * conv_cols <= 8192,
- * 4 * ny * multi_cols <= 8192), and the largest radix of the column transforms (8 or 16).
- * fftlb_init picks the widest tiles and radix 16; a new plan takes effect at the next call
- * (the captured step graphs are rebuilt).  Plans change speed only: the results of any
- * two plans agree to FP32 rounding of the column transforms. */
+ * 3 * ny * multi_cols <= 8192), and the largest radix of the column transforms of each
+ * (8 or 16).  fftlb_init picks the widest tiles and radix 16; a new plan takes effect at
+ * the next call (the captured step graphs are rebuilt).  Plans change speed only: the
+ * results of any two plans agree to FP32 rounding of the column transforms. */
 typedef struct fftlb_plan {
-  int32_t conv_cols, multi_cols, col_radix;
-  int32_t reserved; /* must be 0 */
+  int32_t conv_cols, multi_cols, conv_radix, multi_radix;
 } fftlb_plan;
 int fftlb_get_plan(const fftlb_handle* h, fftlb_plan* plan);
 int fftlb_set_plan(fftlb_handle* h, const fftlb_plan* plan);

@@ -59,18 +59,19 @@ int row_rows_per_block(int nx) {
 int tile_width(int nx) { return std::min(16, (nx / 2) & -(nx / 2)); }
 
 // Largest column counts per block the LDS budget allows: one buffer of ny * cw float2 for the
-// convection pass, four for the derivative passes (three inputs and a work block).
+// convection pass, kMultiSlots for the derivative passes (their largest group).
 int conv_cols_max(int ny, int tw) { return std::min(tw, floor_pow2(std::max(1, std::min(16, kColLdsElems / ny)))); }
 int multi_cols_max(int ny, int tw) {
-  return std::min(tw, floor_pow2(std::max(1, std::min(16, kColLdsElems / (4 * ny)))));
+  return std::min(tw, floor_pow2(std::max(1, std::min(16, kColLdsElems / (kMultiSlots * ny)))));
 }
 
-ColPlan default_plan(int ny, int tw) { return ColPlan{conv_cols_max(ny, tw), multi_cols_max(ny, tw), 16}; }
+ColPlan default_plan(int ny, int tw) { return ColPlan{conv_cols_max(ny, tw), multi_cols_max(ny, tw), 16, 16}; }
 
 bool plan_ok(const ColPlan& p, int ny, int tw) {
   auto cw_ok = [&](int cw, int mx) { return cw >= 1 && is_pow2(cw) && cw <= mx; };
+  auto radix_ok = [](int r) { return r == 8 || r == 16; };
   return cw_ok(p.conv_cw, conv_cols_max(ny, tw)) && cw_ok(p.multi_cw, multi_cols_max(ny, tw)) &&
-         (p.radix == 8 || p.radix == 16);
+         radix_ok(p.conv_radix) && radix_ok(p.multi_radix);
 }
 
 bool config_ok(const fftlb_config* c) {
@@ -404,8 +405,8 @@ int refresh_from_f(fftlb_handle* h, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Plan cache: a text file with one line "arch nx ny conv_cols multi_cols col_radix" per
-// grid size and device architecture.
+// Plan cache: a text file with one line "arch nx ny conv_cols multi_cols conv_radix
+// multi_radix" per grid size and device architecture.
 // ---------------------------------------------------------------------------
 
 std::string device_arch(int dev) {
@@ -420,11 +421,11 @@ bool cache_lookup(const char* path, const std::string& arch, int nx, int ny, Col
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char a[64];
-  int x, y, c, m, r;
+  int x, y, c, m, rc, rm;
   bool found = false;
-  while (std::fscanf(f, "%63s %d %d %d %d %d", a, &x, &y, &c, &m, &r) == 6)
+  while (std::fscanf(f, "%63s %d %d %d %d %d %d", a, &x, &y, &c, &m, &rc, &rm) == 7)
     if (arch == a && x == nx && y == ny) {
-      *out = ColPlan{c, m, r};
+      *out = ColPlan{c, m, rc, rm};
       found = true;  // the last entry for a size wins
     }
   std::fclose(f);
@@ -434,7 +435,8 @@ bool cache_lookup(const char* path, const std::string& arch, int nx, int ny, Col
 void cache_store(const char* path, const std::string& arch, int nx, int ny, const ColPlan& p) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d\n", arch.c_str(), nx, ny, p.conv_cw, p.multi_cw, p.radix);
+  std::fprintf(f, "%s %d %d %d %d %d %d\n", arch.c_str(), nx, ny, p.conv_cw, p.multi_cw, p.conv_radix,
+               p.multi_radix);
   std::fclose(f);
 }
 
@@ -452,8 +454,9 @@ int time_stages(const StepLaunch& L, const int* stages, int ns, int reps, hipStr
   return FFTLB_OK;
 }
 
-// Time every column plan of the handle's size on its own state and keep the fastest:
-// for each radix, the best convection tile width plus the best derivative tile width.
+// Time every column plan of the handle's size on its own state and keep the fastest: the
+// convection pass (tile width x radix) and the derivative passes (tile width x radix) are
+// independent choices.
 int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
@@ -463,28 +466,24 @@ int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
     return FFTLB_EHIP;
   }
   const int conv_stage[1] = {0}, multi_stages[2] = {1, 3};
-  float best_ms = 1e30f;
+  float bc = 1e30f, bm = 1e30f;
+  ColPlan b = h->plan;
   int rc = FFTLB_OK;
   for (int radix : {16, 8}) {
-    float bc = 1e30f, bm = 1e30f;
-    int cc = 0, cm = 0;
     for (int cw = 1; cw <= conv_cols_max(h->ny, h->tw) && rc == FFTLB_OK; cw *= 2) {
       float ms;
-      const ColPlan p{cw, h->plan.multi_cw, radix};
+      const ColPlan p{cw, h->plan.multi_cw, radix, h->plan.multi_radix};
       rc = time_stages(single_launch(h, p), conv_stage, 1, reps, s, e0, e1, &ms);
-      if (rc == FFTLB_OK && ms < bc) bc = ms, cc = cw;
+      if (rc == FFTLB_OK && ms < bc) bc = ms, b.conv_cw = cw, b.conv_radix = radix;
     }
     for (int cw = 1; cw <= multi_cols_max(h->ny, h->tw) && rc == FFTLB_OK; cw *= 2) {
       float ms;
-      const ColPlan p{h->plan.conv_cw, cw, radix};
+      const ColPlan p{h->plan.conv_cw, cw, h->plan.conv_radix, radix};
       rc = time_stages(single_launch(h, p), multi_stages, 2, reps, s, e0, e1, &ms);
-      if (rc == FFTLB_OK && ms < bm) bm = ms, cm = cw;
-    }
-    if (rc == FFTLB_OK && bc + bm < best_ms) {
-      best_ms = bc + bm;
-      *best = ColPlan{cc, cm, radix};
+      if (rc == FFTLB_OK && ms < bm) bm = ms, b.multi_cw = cw, b.multi_radix = radix;
     }
   }
+  if (rc == FFTLB_OK) *best = b;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != FFTLB_OK) return rc;
@@ -494,7 +493,8 @@ int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
 
 int set_plan(fftlb_handle* h, const ColPlan& p) {
   if (!plan_ok(p, h->ny, h->tw)) return FFTLB_EINVAL;
-  if (p.conv_cw != h->plan.conv_cw || p.multi_cw != h->plan.multi_cw || p.radix != h->plan.radix) {
+  if (p.conv_cw != h->plan.conv_cw || p.multi_cw != h->plan.multi_cw || p.conv_radix != h->plan.conv_radix ||
+      p.multi_radix != h->plan.multi_radix) {
     h->plan = p;
     drop_graphs(h);
   }
@@ -841,13 +841,13 @@ int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, vo
 
 int fftlb_get_plan(const fftlb_handle* h, fftlb_plan* plan) {
   if (!h || !plan) return FFTLB_EINVAL;
-  *plan = fftlb_plan{h->plan.conv_cw, h->plan.multi_cw, h->plan.radix, 0};
+  *plan = fftlb_plan{h->plan.conv_cw, h->plan.multi_cw, h->plan.conv_radix, h->plan.multi_radix};
   return FFTLB_OK;
 }
 
 int fftlb_set_plan(fftlb_handle* h, const fftlb_plan* plan) {
-  if (!h || !plan || plan->reserved != 0) return FFTLB_EINVAL;
-  return set_plan(h, ColPlan{plan->conv_cols, plan->multi_cols, plan->col_radix});
+  if (!h || !plan) return FFTLB_EINVAL;
+  return set_plan(h, ColPlan{plan->conv_cols, plan->multi_cols, plan->conv_radix, plan->multi_radix});
 }
 
 int fftlb_autotune(fftlb_handle* h, int32_t reps, const char* cache_path, void* stream, fftlb_plan* best) {
@@ -855,7 +855,7 @@ int fftlb_autotune(fftlb_handle* h, int32_t reps, const char* cache_path, void* 
   DeviceGuard dg(h->device);
   ColPlan p;
   RC_TRY(autotune(h, reps, cache_path, reinterpret_cast<hipStream_t>(stream), &p));
-  if (best) *best = fftlb_plan{p.conv_cw, p.multi_cw, p.radix, 0};
+  if (best) *best = fftlb_plan{p.conv_cw, p.multi_cw, p.conv_radix, p.multi_radix};
   return FFTLB_OK;
 }
 

@@ -615,13 +615,13 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
 // Column pass of derivative groups: forward column FFTs of the nin input spectra, then
 // each output the linear combination sum_p m_op(kx, ky) X_p, inverse column FFTs, store.
 //
-// LDS layout: the CW columns of up to kMultiSlots planes interleaved by row, column c of
-// plane slot p at element (y, p CW + c), i.e. lds[pad(y SI + p CW + c)] with SI =
-// kMultiSlots CW, so that the transforms of all nin inputs (and later of all nout
-// outputs) are one batched call: transform t = p CW + c, element y at t + y SI.  The
-// combination is done in place by the thread that owns (y, c) of every slot.  Group
-// shapes (nin, nout) are compile-time in the body; the kernel dispatches on them.
-constexpr int kMultiSlots = 4;
+// LDS layout: transform-contiguous (as in the row kernels): column c of plane slot p is
+// transform t = p CW + c, its element y at lds[pad(t NY + y)], so that the transforms of
+// all nin inputs (and later of all nout outputs) are one batched call whose passes walk
+// consecutive butterflies of one transform.  The combination is done in place by the
+// thread that owns (y, c) of every slot.  Group shapes (nin, nout) are compile-time in the
+// body; the kernel dispatches on them.
+constexpr int kMultiSlots = 3;
 
 __device__ __forceinline__ float2 mk_apply(int kd, float kx, float ky, float2 v) {
   // m v for the multiplier kinds: i k_x, i k_y (imaginary), -k_x^2, -k_y^2, -k_x k_y,
@@ -639,52 +639,51 @@ template <int NY, int CW, int NT, int R, int NIN, int NOUT>
 __device__ __forceinline__ void col_multi_body(const ColInst& In, const ColGroup& G, float2* lds, const float2* twy,
                                                unsigned ut, int tid, unsigned c0, long off) {
   static_assert(NIN <= kMultiSlots && NOUT <= kMultiSlots, "group shape");
-  constexpr int SI = kMultiSlots * CW;
   constexpr int BLK = NY * CW;  // elements (y, c) of one plane
-  // power-of-two spans and strides: compile-time butterfly offsets (see stockham_pass)
-  constexpr bool AL = is_pow2(NY);
+  // transforms start at multiples of 32 (NY a power of two >= 32): compile-time offsets
+  constexpr bool AL = is_pow2(NY) && NY % 32 == 0;
   const unsigned tw = In.tw;
   const long hp = (long)(In.nx / 2) * NY;  // complex values per spectral plane
   const float scale = In.scale;
+  // global side: consecutive lanes take consecutive columns of a row (e = y CW + c)
 #pragma unroll
   for (int p = 0; p < NIN; ++p) {
     const float2* g = In.spec + G.in[p] * hp + off;
     for_strided<BLK, NT>(ut, [&](unsigned e) {
       const unsigned y = e / CW, c = e % CW;
-      lds[padu(y * SI + p * CW + c)] = elem(g, y * tw + c);
+      lds[padu((p * CW + c) * NY + y)] = elem(g, y * tw + c);
     });
   }
   __syncthreads();
-  fft_lds<NY, -1, NT, NIN * CW, true, SI, AL, R>(lds, 0, 1, twy, tid);
-  // NT is a multiple of CW: the column, and k_x, are fixed per thread
-  const float kx = elem(In.kapx, c0 + ut % CW);
+  fft_lds<NY, -1, NT, NIN * CW, false, 1, AL, R>(lds, 0, NY, twy, tid);
   int kd[NOUT][NIN];
 #pragma unroll
   for (int o = 0; o < NOUT; ++o)
 #pragma unroll
     for (int p = 0; p < NIN; ++p) kd[o][p] = G.kind[o][p];
+  // combination: consecutive lanes take consecutive rows of a column (e = c NY + y)
   for_strided<BLK, NT>(ut, [&](unsigned e) {
-    const unsigned y = e / CW, c = e % CW;
-    const float ky = elem(In.kapy, y);
+    const unsigned c = e / NY, y = e % NY;
+    const float kx = elem(In.kapx, c0 + c), ky = elem(In.kapy, y);
     float2 x[NIN];
 #pragma unroll
-    for (int p = 0; p < NIN; ++p) x[p] = lds[padu(y * SI + p * CW + c)];
+    for (int p = 0; p < NIN; ++p) x[p] = lds[padu((p * CW + c) * NY + y)];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
       float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int p = 0; p < NIN; ++p) acc = cadd(acc, mk_apply(kd[o][p], kx, ky, x[p]));
-      lds[padu(y * SI + o * CW + c)] = make_float2(acc.x * scale, acc.y * scale);
+      lds[padu((o * CW + c) * NY + y)] = make_float2(acc.x * scale, acc.y * scale);
     }
   });
   __syncthreads();
-  fft_lds<NY, +1, NT, NOUT * CW, true, SI, AL, R>(lds, 0, 1, twy, tid);
+  fft_lds<NY, +1, NT, NOUT * CW, false, 1, AL, R>(lds, 0, NY, twy, tid);
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     float2* g = In.spec + G.out[o] * hp + off;
     for_strided<BLK, NT>(ut, [&](unsigned e) {
       const unsigned y = e / CW, c = e % CW;
-      elem(g, y * tw + c) = lds[padu(y * SI + o * CW + c)];
+      elem(g, y * tw + c) = lds[padu((o * CW + c) * NY + y)];
     });
   }
 }

@@ -9,10 +9,10 @@
 
 namespace fftlb {
 
-// Column-pass plan of a grid size: spectral columns per block of the convection pass and
-// of the derivative passes, and the largest radix (8 or 16) of the column transforms.
+// Column-pass plan of a grid size: spectral columns per block and the largest radix (8 or
+// 16) of the column transforms, for the convection pass and for the derivative passes.
 struct ColPlan {
-  int conv_cw, multi_cw, radix;
+  int conv_cw, multi_cw, conv_radix, multi_radix;
 };
 
 // Host-side description of one solver instance (pointers into its workspace).

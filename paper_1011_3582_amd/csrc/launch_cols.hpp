@@ -41,7 +41,7 @@ int col_multi_plan(const StepLaunch& L, const ColLaunch& groups, int ngroups, hi
     constexpr int NT = col_threads(NY, CW, R);
     for (int first = 0; first < L.ninst; first += kColSlots) {
       const int count = cmin(kColSlots, L.ninst - first);
-      // kMultiSlots interleaved planes of CW columns, then the twiddle tables
+      // kMultiSlots planes of CW columns, then the twiddle tables
       hipLaunchKernelGGL((k_col_multi<NY, CW, NT, R>), dim3((L.nx / 2) / CW, ngroups, count), dim3(NT),
                          (lds_alloc(kMultiSlots * NY * CW) + NY) * sizeof(float2), s, col_args(L, first, count, false),
                          groups);
@@ -76,7 +76,7 @@ int col_multi_cw(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipS
 
 template <int NY>
 int launch_col_conv(const StepLaunch& L, hipStream_t s) {
-  switch (L.plan.radix) {
+  switch (L.plan.conv_radix) {
     case 8: return col_conv_cw<NY, 8>(L, s);
     case 16: return col_conv_cw<NY, 16>(L, s);
   }
@@ -85,7 +85,7 @@ int launch_col_conv(const StepLaunch& L, hipStream_t s) {
 
 template <int NY>
 int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
-  switch (L.plan.radix) {
+  switch (L.plan.multi_radix) {
     case 8: return col_multi_cw<NY, 8>(L, groups, ngroups, s);
     case 16: return col_multi_cw<NY, 16>(L, groups, ngroups, s);
   }

@@ -43,12 +43,12 @@ class Config(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    """Mirror of struct fftlb_plan: column-pass tile widths and radix."""
-    _fields_ = [("conv_cols", ctypes.c_int32), ("multi_cols", ctypes.c_int32), ("col_radix", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+    """Mirror of struct fftlb_plan: column-pass tile widths and radices."""
+    _fields_ = [("conv_cols", ctypes.c_int32), ("multi_cols", ctypes.c_int32), ("conv_radix", ctypes.c_int32),
+                ("multi_radix", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.conv_cols, self.multi_cols, self.col_radix)
+        return (self.conv_cols, self.multi_cols, self.conv_radix, self.multi_radix)
 
 
 @dataclasses.dataclass
@@ -254,8 +254,8 @@ class Solver:
         _check(_lib.fftlb_get_plan(self.handle, ctypes.byref(p)), "fftlb_get_plan")
         return p.as_tuple()
 
-    def set_plan(self, conv_cols: int, multi_cols: int, col_radix: int):
-        p = Plan(int(conv_cols), int(multi_cols), int(col_radix), 0)
+    def set_plan(self, conv_cols: int, multi_cols: int, conv_radix: int, multi_radix: int):
+        p = Plan(int(conv_cols), int(multi_cols), int(conv_radix), int(multi_radix))
         _check(_lib.fftlb_set_plan(self.handle, ctypes.byref(p)), "fftlb_set_plan")
 
     def autotune(self, reps: int = 10, cache_path: str | None = None):

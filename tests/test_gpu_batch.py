@@ -57,16 +57,17 @@ def plans_for(ny, nx):
     """Every valid column plan of a grid size."""
     tw = min(16, (nx // 2) & -(nx // 2))
     cmax = min(tw, 1 << int(math.log2(max(1, min(16, 8192 // ny)))))
-    mmax = min(tw, 1 << int(math.log2(max(1, min(16, 2048 // ny)))))
+    mmax = min(tw, 1 << int(math.log2(max(1, min(16, 8192 // (3 * ny))))))
     out = []
-    for r in (16, 8):
-        c = 1
-        while c <= cmax:
-            m = 1
-            while m <= mmax:
-                out.append((c, m, r))
-                m *= 2
-            c *= 2
+    for rc in (16, 8):
+        for rm in (16, 8):
+            c = 1
+            while c <= cmax:
+                m = 1
+                while m <= mmax:
+                    out.append((c, m, rc, rm))
+                    m *= 2
+                c *= 2
     return out
 
 
@@ -94,7 +95,8 @@ def test_every_plan_gives_the_same_step(ny, nx):
 def test_invalid_plans_rejected():
     fld = W.smooth_random(64, 64, seed=22)
     with solver(fld) as s:
-        for bad in [(3, 1, 16), (32, 1, 16), (1, 0, 16), (1, 1, 4), (1, 1, 32), (16, 32, 16)]:
+        for bad in [(3, 1, 16, 16), (32, 1, 16, 16), (1, 0, 16, 16), (1, 1, 4, 16), (1, 1, 32, 16), (16, 32, 16, 16),
+                    (1, 1, 16, 4), (1, 1, 8, 32)]:
             with pytest.raises(F.FFTLBError) as ei:
                 s.set_plan(*bad)
             assert ei.value.code == F.FFTLB_EINVAL
@@ -114,7 +116,7 @@ def test_autotune_leaves_the_trajectory_unchanged(tmp_path):
         assert torch.equal(a.get_state(), b.get_state())
         # the plan was stored and is found again without timing
         line = open(cache).read().split()
-        assert line[1:3] == ["128", "64"] and tuple(int(v) for v in line[3:6]) == best
+        assert line[1:3] == ["128", "64"] and tuple(int(v) for v in line[3:7]) == best
         with solver(fld) as c:
             assert c.autotune(reps=3, cache_path=cache) == best
 

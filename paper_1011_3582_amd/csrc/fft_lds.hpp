@@ -185,17 +185,8 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restri
 // T_P[(r - 1) P + k] = exp(-2 pi i r k / (P R)) for butterfly k = i mod P, so the lanes of
 // a wave (consecutive k) read consecutive entries and every power is a single LDS read (no
 // vector-memory issue, no products).  The tables of all passes of a length-N transform
-// hold fewer than N entries in total.
-template <int R, int DIR>
-__device__ __forceinline__ void apply_twiddles_lds(float2* v, const float2* tp, int P) {
-#pragma unroll
-  for (int r = 1; r < R; ++r) {
-    const float2 w = tp[(r - 1) * P];
-    v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
-  }
-}
-
-// The same with the powers already read (w[r - 1] = T_P[(r - 1) P + k]).
+// hold fewer than N entries in total.  stockham_pass reads them together with the data
+// (before its barrier); this applies them from registers (w[r - 1] = T_P[(r - 1) P + k]).
 template <int R, int DIR>
 __device__ __forceinline__ void apply_twiddle_regs(float2* v, const float2* w) {
 #pragma unroll

@@ -963,8 +963,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       const float r = mr[j], t = mt[j];
       site_init(st[j], r, mux[j], muy[j], t);
       const float irT = 1.0f / (r * t);
-      const float cc = mc[j] + 0.5f * gd * irT * st[j].iT;   // C + C_q, C_q = G / (2 rho T^2)
-      site_force(st[j], bxy.x * irT, bxy.y * irT, cc);
+      const float cc = mc[j] + 0.5f * gd * (irT * irT) * r;   // C + C_q, C_q = G / (2 rho T^2)
+      site_force(st[j], M, bxy.x * irT, bxy.y * irT, cc);
     }
     __syncthreads();
   } else if constexpr (MODE == MODE_INIT) {
@@ -982,7 +982,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     const unsigned s = rt.site(j);
     float fn;
     if constexpr (MODE == MODE_STEP) {
-      fn = relax_update(st[j], M, elem(P.f + rb, s), feq_rest(st[j]), 0.0f, 0.0f, 0.0f, 0.0f);
+      fn = relax_update(st[j], M, elem(P.f + rb, s), feq_rest(st[j]), 0.0f, 0.0f, 0.0f, force_k0(st[j], M, 0.0f));
     } else if constexpr (MODE == MODE_INIT) {
       fn = rounded(feq_rest(st[j]));
     } else {
@@ -1026,9 +1026,13 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       const int k = GPR * rd + g;
       const float v2 = c_vel.v2[1 + 8 * k];
       GroupEq ge[J];
+      float k0[J];
       if constexpr (MODE != MODE_SET) {
 #pragma unroll
-        for (int j = 0; j < J; ++j) ge[j] = group_eq(st[j], (float)group_weight((double)st[j].T, k));
+        for (int j = 0; j < J; ++j) {
+          ge[j] = group_eq(st[j], (float)group_weight((double)st[j].T, k));
+          k0[j] = force_k0(st[j], M, v2);
+        }
       }
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
@@ -1053,8 +1057,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
               const float2 c = lds[li];
               const float f0a = PREF ? fpre[2 * slot][j] : elem(fA, x);
               const float f0b = PREF ? fpre[2 * slot + 1][j] : elem(fB, x);
-              fa = relax_update(st[j], M, f0a, ea, c.x, vxa, vya, v2);
-              fb = relax_update(st[j], M, f0b, eb, c.y, vxb, vyb, v2);
+              fa = relax_update(st[j], M, f0a, ea, c.x, vxa, vya, k0[j]);
+              fb = relax_update(st[j], M, f0b, eb, c.y, vxb, vyb, k0[j]);
             } else {
               fa = rounded(ea);
               fb = rounded(eb);

@@ -83,19 +83,20 @@ __device__ __forceinline__ float rest_weight(float T) {
 }
 
 // What the 33-velocity loop keeps per site: the moments and the force polynomial
-// A + B.(v-u) + (C+Cq)|v-u|^2 = s0 + sx vx + sy vy + cc |v|^2 (Eqs. (11), (20)).
+// A + B.(v-u) + (C+Cq)|v-u|^2 = s0 + sx vx + sy vy + cc |v|^2 (Eqs. (11), (20)), the
+// latter with -dt folded in for the update.
 struct Site {
   float rho, ux, uy, T;
-  float iT;  // 1/T, formed once per site
-  float s0, sx, sy, cc;
+  float uxT, uyT;   // u / T
+  float s0, cc;     // velocity-independent part and |v|^2 coefficient of the force polynomial
+  float dsx, dsy;   // -dt sx, -dt sy
 };
 
-// Per-site factors of Eq. (3) for one speed group.
+// Per-site factors of Eq. (3) for one speed group: with w = v.u/T, f^eq = rho F_k (base +
+// g w + (g/2) w^2 + w^3/6 + w^4/24), g = 1 - u^2/2T, base = g + u^4/8T^2; the rho F_k
+// factor is folded into the five coefficients (Horner form).
 struct GroupEq {
-  float rF;    // rho F_k
-  float invT;  // 1/T
-  float g;     // 1 - u^2/2T
-  float base;  // 1 - u^2/2T + u^4/8T^2
+  float c0, c1, c2, c3, c4;
 };
 
 __device__ __forceinline__ void site_init(Site& s, float rho, float ux, float uy, float T) {
@@ -103,51 +104,57 @@ __device__ __forceinline__ void site_init(Site& s, float rho, float ux, float uy
   s.ux = ux;
   s.uy = uy;
   s.T = T;
-  s.iT = 1.0f / T;
-  s.s0 = s.sx = s.sy = s.cc = 0.0f;
+  const float iT = 1.0f / T;
+  s.uxT = ux * iT;
+  s.uyT = uy * iT;
+  s.s0 = s.cc = s.dsx = s.dsy = 0.0f;
 }
 
 // Force coefficients A, B, C + C_q (Eqs. (20)-(23)) folded into the polynomial in v.
-__device__ __forceinline__ void site_force(Site& s, float Bx, float By, float cc) {
+__device__ __forceinline__ void site_force(Site& s, const Model& M, float Bx, float By, float cc) {
   const float A = -2.0f * cc * s.T;
   const float u2 = s.ux * s.ux + s.uy * s.uy;
   s.s0 = A - (Bx * s.ux + By * s.uy) + cc * u2;
-  s.sx = Bx - 2.0f * cc * s.ux;
-  s.sy = By - 2.0f * cc * s.uy;
+  s.dsx = -M.dt * (Bx - 2.0f * cc * s.ux);
+  s.dsy = -M.dt * (By - 2.0f * cc * s.uy);
   s.cc = cc;
 }
 
 __device__ __forceinline__ GroupEq group_eq(const Site& s, float Fk) {
+  const float u2T = s.ux * s.uxT + s.uy * s.uyT;  // u^2 / T
+  const float g = 1.0f - 0.5f * u2T;
+  const float base = g + 0.125f * u2T * u2T;
+  const float rF = s.rho * Fk;
   GroupEq e;
-  e.invT = s.iT;
-  const float u2 = s.ux * s.ux + s.uy * s.uy;
-  e.g = 1.0f - 0.5f * u2 * e.invT;
-  e.base = e.g + 0.125f * u2 * u2 * e.invT * e.invT;
-  e.rF = s.rho * Fk;
+  e.c0 = rF * base;
+  e.c1 = rF * g;
+  e.c2 = 0.5f * e.c1;
+  e.c3 = rF * (1.0f / 6.0f);
+  e.c4 = rF * (1.0f / 24.0f);
   return e;
 }
 
 // Eq. (3) for a moving population with velocity (vx, vy).
 __device__ __forceinline__ float feq_moving(const Site& s, const GroupEq& e, float vx, float vy) {
-  const float w = (vx * s.ux + vy * s.uy) * e.invT;
-  const float poly = e.base + e.g * (w + 0.5f * w * w) + w * w * w * (1.0f / 6.0f) +
-                     w * w * w * w * (1.0f / 24.0f);
-  return e.rF * poly;
+  const float w = fmaf(vx, s.uxT, vy * s.uyT);
+  return fmaf(w, fmaf(w, fmaf(w, fmaf(w, e.c4, e.c3), e.c2), e.c1), e.c0);
 }
 
 // Eq. (3) for the rest particle (v = 0).
-__device__ __forceinline__ float feq_rest(const Site& s) {
-  const GroupEq e = group_eq(s, rest_weight(s.T));
-  return e.rF * e.base;
+__device__ __forceinline__ float feq_rest(const Site& s) { return group_eq(s, rest_weight(s.T)).c0; }
+
+// -dt times the velocity-independent part of the force polynomial for speed v^2.
+__device__ __forceinline__ float force_k0(const Site& s, const Model& M, float v2) {
+  return -M.dt * fmaf(s.cc, v2, s.s0);
 }
 
-// f^{n+1} = f - dt C - omega (f - feq) + dt I with I = -(s0 + sx vx + sy vy + cc |v|^2) feq.
-// The increment is formed first and added once: f is rounded to FP32 a single time and
-// no O(eps) multiple of f (e.g. from rounding 1 - omega) biases the mass.
+// f^{n+1} = f - dt C - omega (f - feq) + dt I with I = -(s0 + sx vx + sy vy + cc |v|^2) feq,
+// k0 = force_k0(v^2).  The increment is formed first and added once: f is rounded to FP32
+// a single time and no O(eps) multiple of f (e.g. from rounding 1 - omega) biases the mass.
 __device__ __forceinline__ float relax_update(const Site& s, const Model& M, float f, float feq, float conv,
-                                              float vx, float vy, float v2) {
-  const float fac = s.s0 + s.sx * vx + s.sy * vy + s.cc * v2;
-  const float inc = M.omega * (feq - f) - M.dt * (fac * feq + conv);
+                                              float vx, float vy, float k0) {
+  const float kf = fmaf(s.dsx, vx, fmaf(s.dsy, vy, k0));  // -dt (s0 + sx vx + sy vy + cc v^2)
+  const float inc = fmaf(M.omega, feq - f, fmaf(kf, feq, -M.dt * conv));
   return f + inc;
 }
 

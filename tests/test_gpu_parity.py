@@ -172,6 +172,21 @@ def _c15(gpu_state, ora_state):
                 ux=float(np.abs(gu - ou).max() / vt), uy=float(np.abs(gv - ov).max() / vt))
 
 
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+def test_one_step_other_window_orders(m):
+    """The whole step with the exact wavenumber (m = 0) and the k1..k3 windows (Eqs. (44)-(46))."""
+    fld = W.smooth_random(64, 64, seed=11, T0=1.2)
+    p = F.Params(m=m)
+    with solver(fld, p) as s:
+        s.step(2)
+        f0 = state64(s)
+        s.step(1)
+        f1 = state64(s)
+    ref = O.step(f0, oparams(p))
+    scale = np.abs(ref).max()
+    assert np.abs(f1 - ref).max() < 3e-7 * scale, np.abs(f1 - ref).max() / scale
+
+
 def test_slab64_100_steps_within_target():
     """The 64 x 64 slab at 0.9 T_c (a = 2, b = 0.4), 100 steps: every field within 1e-5."""
     fld = W.slab_64()

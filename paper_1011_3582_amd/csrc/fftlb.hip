@@ -379,13 +379,17 @@ int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
       h->cap,
       [&]() {
         // per step: the convection column pass (stage 0) on a branch of its own, beside the
-        // force pipeline (stages 1-3); both read only what the previous collide wrote
+        // force pipeline (stages 1-3); both read only what the previous collide wrote.  The
+        // stage-1 column pass is enqueued first: dispatched first, its latency-bound blocks
+        // take part of each CU and the convection pass fills the rest (measured 9 us per
+        // step faster than the other order)
         for (int i = 0; i < nsteps; ++i) {
           HIP_TRY(hipEventRecord(h->fork, h->cap));
           HIP_TRY(hipStreamWaitEvent(h->side, h->fork, 0));
+          RC_TRY(enqueue_stage(L, 1, h->cap));
           RC_TRY(enqueue_stage(L, 0, h->side));
           HIP_TRY(hipEventRecord(h->join, h->side));
-          for (int k = 1; k < kNumStages - 1; ++k) RC_TRY(enqueue_stage(L, k, h->cap));
+          for (int k = 2; k < kNumStages - 1; ++k) RC_TRY(enqueue_stage(L, k, h->cap));
           HIP_TRY(hipStreamWaitEvent(h->cap, h->join, 0));
           RC_TRY(enqueue_stage(L, kNumStages - 1, h->cap));
         }

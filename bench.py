@@ -44,11 +44,12 @@ CSRC = os.path.join(ROOT, "paper_1011_3582_amd", "csrc")
 
 
 def kernel_source_hash() -> str:
-    """Hash of every source the solver's kernels are built from (the warm-start network's
-    files excluded)."""
+    """Hash of every source the solver's kernels are built from: the device headers and the
+    translation units that instantiate the kernels (the host API, fftlb.hip, and the
+    warm-start network's files excluded)."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hpp", ".hip")) and not name.startswith("cnn."):
+        if (name.endswith(".hpp") or name.startswith(("rows_", "cols_"))) and not name.startswith("cnn."):
             with open(os.path.join(CSRC, name), "rb") as fh:
                 h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]

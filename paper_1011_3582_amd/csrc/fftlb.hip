@@ -211,8 +211,6 @@ struct fftlb_handle {
   ColPlan plan;
   int64_t steps;
   hipStream_t cap;         // capture stream
-  hipStream_t side;        // second branch of the captured step (convection column pass)
-  hipEvent_t fork, join;
   hipGraphExec_t g1, gN;
 };
 
@@ -371,28 +369,11 @@ int capture_graph(hipStream_t cap, Body body, hipGraphExec_t* out) {
 
 int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
   RC_TRY(make_stream(&h->cap));
-  RC_TRY(make_stream(&h->side));
-  if (!h->fork) HIP_TRY(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
-  if (!h->join) HIP_TRY(hipEventCreateWithFlags(&h->join, hipEventDisableTiming));
   const StepLaunch L = single_launch(h, h->plan);
   return capture_graph(
       h->cap,
       [&]() {
-        // per step: the convection column pass (stage 0) on a branch of its own, beside the
-        // force pipeline (stages 1-3); both read only what the previous collide wrote.  The
-        // stage-1 column pass is enqueued first: dispatched first, its latency-bound blocks
-        // take part of each CU and the convection pass fills the rest (measured 9 us per
-        // step faster than the other order)
-        for (int i = 0; i < nsteps; ++i) {
-          HIP_TRY(hipEventRecord(h->fork, h->cap));
-          HIP_TRY(hipStreamWaitEvent(h->side, h->fork, 0));
-          RC_TRY(enqueue_stage(L, 1, h->cap));
-          RC_TRY(enqueue_stage(L, 0, h->side));
-          HIP_TRY(hipEventRecord(h->join, h->side));
-          for (int k = 2; k < kNumStages - 1; ++k) RC_TRY(enqueue_stage(L, k, h->cap));
-          HIP_TRY(hipStreamWaitEvent(h->cap, h->join, 0));
-          RC_TRY(enqueue_stage(L, kNumStages - 1, h->cap));
-        }
+        for (int i = 0; i < nsteps; ++i) RC_TRY(enqueue_step_all(&L, 1, h->cap));
         return FFTLB_OK;
       },
       out);
@@ -694,8 +675,7 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   h->steps = 0;
   h->plan = default_plan(h->ny, h->tw);
   h->g1 = h->gN = nullptr;
-  h->cap = h->side = nullptr;
-  h->fork = h->join = nullptr;
+  h->cap = nullptr;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return FFTLB_EHIP;
@@ -892,9 +872,6 @@ int fftlb_destroy(fftlb_handle* h) {
     (void)hipDeviceSynchronize();
     drop_graphs(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
-    if (h->side) (void)hipStreamDestroy(h->side);
-    if (h->fork) (void)hipEventDestroy(h->fork);
-    if (h->join) (void)hipEventDestroy(h->join);
   }
   delete h;
   return FFTLB_OK;

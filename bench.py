@@ -28,16 +28,17 @@ METRIC = "site·velocity updates/s per FFT-LB step; % HBM roofline; time-to-equi
 
 # Algorithmic bytes per site of each kernel of the step (FP32 values; a packed half
 # spectrum of a real plane is nx*ny/2 complex = one float per site):
-#   0 convection columns: read 24 spectra, write 24 (v_y != 0 only)       ->  48 floats
-#   1 stage-1 columns:    read 4 moment spectra, write 6 y-derivatives    ->  10
-#   2 stage-2 rows:       read 4 + 6 spectra + 4 fields, write 5 spectra + C -> 20
-#   3 stage-2 columns:    read 5 spectra, write 3                         ->   8
-#   4 collide rows:       read f (33) + 32 spectra + 3 + C + 4 fields,
+#   0 convection + stage-1 columns (one launch):
+#                         read 24 spectra, write 24 (v_y != 0 only),
+#                         read 4 moment spectra, write 6 y-derivatives     ->  58 floats
+#   1 stage-2 rows:       read 4 + 6 spectra + 4 fields, write 5 spectra + C -> 20
+#   2 stage-2 columns:    read 5 spectra, write 3                         ->   8
+#   3 collide rows:       read f (33) + 32 spectra + 3 + C + 4 fields,
 #                         write f (33) + 32 spectra + 4 spectra + 4 fields -> 146
-STAGES = ("conv_columns", "stage1_columns", "stage2_rows", "stage2_columns", "collide_rows")
-STAGE_KERNELS = ("k_col_conv", "k_col_multi", "k_rows_stage2", "k_col_multi", "k_rows_collide")
-STAGE_FLOATS_PER_SITE = (48, 10, 20, 8, 146)
-DOMINANT = 4
+STAGES = ("conv_stage1_columns", "stage2_rows", "stage2_columns", "collide_rows")
+STAGE_KERNELS = ("k_col_conv_multi", "k_rows_stage2", "k_col_multi", "k_rows_collide")
+STAGE_FLOATS_PER_SITE = (58, 20, 8, 146)
+DOMINANT = 3
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_spinodal1024.json")
 CSRC = os.path.join(ROOT, "paper_1011_3582_amd", "csrc")

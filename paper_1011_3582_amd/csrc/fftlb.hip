@@ -249,20 +249,20 @@ int rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s) {
   return FFTLB_EINVAL;
 }
 
-int col_conv(const StepLaunch& L, hipStream_t s) {
+int col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
   switch (L.ny) {
 #define X(n) \
-  case n: return launch_col_conv<n>(L, s);
+  case n: return launch_col_multi<n>(L, groups, ngroups, s);
     FFTLB_FOR_COL_SIZES(X)
 #undef X
   }
   return FFTLB_EINVAL;
 }
 
-int col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+int col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
   switch (L.ny) {
 #define X(n) \
-  case n: return launch_col_multi<n>(L, groups, ngroups, s);
+  case n: return launch_col_conv_multi<n>(L, groups, ngroups, s);
     FFTLB_FOR_COL_SIZES(X)
 #undef X
   }
@@ -299,17 +299,18 @@ StepLaunch single_launch(const fftlb_handle* h, const ColPlan& plan) {
 // The step
 // ---------------------------------------------------------------------------
 
-constexpr int kNumStages = 5;
+constexpr int kNumStages = 4;
+// Kernels of the step, in order, and the stage-1 derivative column pass by itself (the
+// diagnostics reuse it; in the step it runs inside the convection launch).
+enum : int { ST_CONV_S1 = 0, ST_S2_ROWS = 1, ST_S2_COLS = 2, ST_COLLIDE = 3, ST_S1_COLS = 4 };
 
-// One kernel of the step: 0 convection columns, 1 stage-1 columns, 2 stage-2 rows,
-// 3 stage-2 columns, 4 collide rows.
 int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
   switch (stage) {
-    case 0: return col_conv(L, s);
-    case 1: return col_multi(L, kStage1, 3, s);
-    case 2: return rows(L, RK_STAGE2, Inputs{}, s);
-    case 3: return col_multi(L, kStage2, 2, s);
-    case 4: return rows(L, RK_COLLIDE, Inputs{}, s);
+    case ST_CONV_S1: return col_conv_multi(L, kStage1, 3, s);
+    case ST_S2_ROWS: return rows(L, RK_STAGE2, Inputs{}, s);
+    case ST_S2_COLS: return col_multi(L, kStage2, 2, s);
+    case ST_COLLIDE: return rows(L, RK_COLLIDE, Inputs{}, s);
+    case ST_S1_COLS: return col_multi(L, kStage1, 3, s);
   }
   return FFTLB_EINVAL;
 }
@@ -322,9 +323,9 @@ int enqueue_residual(const StepLaunch& L, hipStream_t s) {
   return rows(L, RK_RESIDUAL, Inputs{}, s);
 }
 
-// One step of every launch group in `Ls`, kernel after kernel.  (A graph whose convection
-// column pass ran on a concurrent branch was measured slower: the convection pass fills
-// the GPU by itself, so the branch only added dependency overhead.)
+// One step of every launch group in `Ls`, kernel after kernel.  (The convection and
+// stage-1 column passes are independent; they overlap inside one joint launch, not on
+// concurrent graph branches.)
 int enqueue_step_all(const StepLaunch* Ls, int nl, hipStream_t s) {
   for (int k = 0; k < kNumStages; ++k)
     for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], k, s));
@@ -460,8 +461,8 @@ int time_stages(const StepLaunch& L, const int* stages, int ns, int reps, hipStr
 }
 
 // Time every column plan of the handle's size on its own state and keep the fastest: the
-// convection pass (tile width x radix) and the derivative passes (tile width x radix) are
-// independent choices.
+// joint convection and stage-1 launch (tile width x radix; the stage-1 tiles follow from
+// them) and the stage-2 derivative pass (tile width x radix) are independent choices.
 int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
@@ -470,7 +471,7 @@ int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
     set_error("hipEventCreate", hipErrorUnknown);
     return FFTLB_EHIP;
   }
-  const int conv_stage[1] = {0}, multi_stages[2] = {1, 3};
+  const int conv_stage[1] = {ST_CONV_S1}, multi_stages[1] = {ST_S2_COLS};
   float bc = 1e30f, bm = 1e30f;
   ColPlan b = h->plan;
   int rc = FFTLB_OK;
@@ -484,7 +485,7 @@ int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
     for (int cw = 1; cw <= multi_cols_max(h->ny, h->tw) && rc == FFTLB_OK; cw *= 2) {
       float ms;
       const ColPlan p{h->plan.conv_cw, cw, h->plan.conv_radix, radix};
-      rc = time_stages(single_launch(h, p), multi_stages, 2, reps, s, e0, e1, &ms);
+      rc = time_stages(single_launch(h, p), multi_stages, 1, reps, s, e0, e1, &ms);
       if (rc == FFTLB_OK && ms < bm) bm = ms, b.multi_cw = cw, b.multi_radix = radix;
     }
   }
@@ -789,7 +790,7 @@ int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream) 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const StepLaunch L = single_launch(h, h->plan);
   for (int i = 0; i < reps; ++i) RC_TRY(enqueue_stage(L, stage, s));
-  if (stage == kNumStages - 1) h->steps += reps;
+  if (stage == ST_COLLIDE) h->steps += reps;
   return check_launch("run_stage");
 }
 
@@ -804,8 +805,8 @@ int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, d
       HIP_TRY(hipMemcpyAsync(outs[i], h->I.P.macro + (size_t)i * h->nx * h->ny, pb, hipMemcpyDeviceToDevice, s));
   if (globals) {
     const StepLaunch L = single_launch(h, h->plan);
-    RC_TRY(enqueue_stage(L, 1, s));
-    RC_TRY(enqueue_stage(L, 2, s));
+    RC_TRY(enqueue_stage(L, ST_S1_COLS, s));
+    RC_TRY(enqueue_stage(L, ST_S2_ROWS, s));
     RC_TRY(enqueue_residual(L, s));
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->I.P.part_d, h->I.nblk, h->I.P.part_f, h->I.nblk,
                        h->cfg.dx * h->cfg.dy, h->cfg.dt, (double)h->steps, globals);

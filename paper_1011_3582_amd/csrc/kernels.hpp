@@ -9,10 +9,12 @@
 //     (kx / TW) * ny * TW + y * TW + (kx % TW).
 //
 // Per time step (all derivatives by windowed FFT, Sec. 3.6):
-//   k_col_conv      column FFT of the 32 moving populations' row spectra, multiply by
+//   k_col_conv_multi  one launch of two independent column passes: column FFT of the
+//                   row spectra of the 24 populations with v_y != 0, multiply by
 //                   i (v_x k_m(kx) + v_y k_m(ky)) / (nx ny), inverse column FFT (in place);
-//   k_col_multi     column pass of the macroscopic fields: 4 spectra -> 11 derivative
-//                   spectra (stage 1), and later 5 -> 3 divergence spectra (stage 2);
+//                   and the stage-1 pass of the macroscopic fields, 4 moment spectra -> 6
+//                   y-derivative spectra;
+//   k_col_multi     column pass of derivative groups: 5 -> 3 divergence spectra (stage 2);
 //   k_rows_stage2   inverse row FFTs of the 11 derivatives, the pointwise closure of
 //                   Eqs. (18)-(23), forward row FFTs of the 5 fields whose divergences the
 //                   force needs, FP64 partial sums for the global diagnostics;
@@ -112,7 +114,7 @@ __device__ __forceinline__ const T& elem(const T* base, unsigned i) {
 // Pointers into the workspace (and the caller's buffers for the init/set modes).
 struct Planes {
   float* f;          // [33][ny][nx]
-  float2* sf;        // [32] row spectra of f_1..f_32 (in place: convection spectra after k_col_conv)
+  float2* sf;        // [32] row spectra of f_1..f_32 (in place: convection spectra after the column pass)
   float2* sm;        // [4]  row spectra of rho, ux, uy, T
   float2* s1;        // [6]  stage-1 y-derivative spectra
   float2* s2i;       // [5]  stage-2 input spectra
@@ -567,11 +569,9 @@ __device__ __forceinline__ int conv_column_plane(int j) {
   return 8 * k + (r < 3 ? r + 1 : r + 2);
 }
 
+// Tile b of nblocks (24 planes times (nx/2)/CW column tiles) of one instance.
 template <int NY, int CW, int NT, int R>
-__global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
-  const ColInst& In = A.c[blockIdx.y];
-  if (retired(A.state, In.id)) return;
-  extern __shared__ float2 lds[];
+__device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, int b, int nblocks) {
   float2* __restrict__ spec = In.spec;
   const float2* twy = In.twy;
   const float* __restrict__ kapx = In.kapx;
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
   __builtin_assume(ut < static_cast<unsigned>(NT));
   twy = col_twiddles<NY, R>(lds + lds_alloc(NY * CW), twy, tid, NT);
   const int nsub = (nx / 2) / CW;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  b = xcd_remap(b, nblocks);
   const int p = conv_column_plane(b / nsub), sub = b % nsub;
   const unsigned c0 = sub * CW;
   float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
@@ -611,6 +611,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv(ColArgs A) {
     elem(g, y * tw + c) = lds[padu(e)];
   });
 }
+
 
 // Column pass of derivative groups: forward column FFTs of the nin input spectra, then
 // each output the linear combination sum_p m_op(kx, ky) X_p, inverse column FFTs, store.
@@ -693,18 +694,15 @@ __host__ __device__ constexpr bool multi_shape_ok(int nin, int nout) {
   return (nin == 1 && (nout == 1 || nout == 2)) || (nin == 2 && (nout == 1 || nout == 3)) || (nin == 3 && nout == 2);
 }
 
+// Column tile b of ntiles ((nx/2)/CW) of group G of one instance.
 template <int NY, int CW, int NT, int R>
-__global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
-  const ColInst& In = A.c[blockIdx.z];
-  if (retired(A.state, In.id)) return;
-  extern __shared__ float2 lds[];
+__device__ __forceinline__ void col_multi_tile(const ColInst& In, const ColGroup& G, float2* lds, int b, int ntiles) {
   const int tid = threadIdx.x;
   const unsigned ut = static_cast<unsigned>(tid);
   __builtin_assume(ut < static_cast<unsigned>(NT));
   const float2* twy = col_twiddles<NY, R>(lds + lds_alloc(kMultiSlots * NY * CW), In.twy, tid, NT);
-  const ColGroup& G = L.g[blockIdx.y];
   const unsigned tw = In.tw;
-  const unsigned c0 = xcd_remap(blockIdx.x, gridDim.x) * CW;
+  const unsigned c0 = xcd_remap(b, ntiles) * CW;
   const long off = (long)(c0 / tw) * NY * tw + (c0 % tw);
   switch (G.nin * 4 + G.nout) {
     case 1 * 4 + 1: col_multi_body<NY, CW, NT, R, 1, 1>(In, G, lds, twy, ut, tid, c0, off); break;
@@ -713,6 +711,42 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
     case 2 * 4 + 3: col_multi_body<NY, CW, NT, R, 2, 3>(In, G, lds, twy, ut, tid, c0, off); break;
     case 3 * 4 + 2: col_multi_body<NY, CW, NT, R, 3, 2>(In, G, lds, twy, ut, tid, c0, off); break;
     default: break;  // not built by the host (multi_shape_ok)
+  }
+}
+
+template <int NY, int CW, int NT, int R>
+__global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
+  const ColInst& In = A.c[blockIdx.z];
+  if (retired(A.state, In.id)) return;
+  extern __shared__ float2 lds[];
+  col_multi_tile<NY, CW, NT, R>(In, L.g[blockIdx.y], lds, blockIdx.x, gridDim.x);
+}
+
+// The convection pass and a derivative pass (of ngroups groups) in one launch: the first
+// nc blocks of a slot run the convection tiles, the ngroups nt blocks after them the
+// derivative tiles (CWM columns each, nt = (nx/2)/CWM tiles per group) with the
+// convection pass's block size and radix.  The two passes are independent: the
+// latency-bound derivative tiles, dispatched last, run in the slots that the convection
+// tiles free as that pass drains (measured faster than dispatching them first).
+struct ConvMultiArgs {
+  ColArgs a;                 // the convection pass's instances (population spectra)
+  float2* mspec[kColSlots];  // the spectral block of each instance
+};
+
+template <int NY, int CW, int NT, int R, int CWM>
+__global__ __launch_bounds__(NT, 4) void k_col_conv_multi(ConvMultiArgs A, ColLaunch L, int ngroups) {
+  const ColInst& In = A.a.c[blockIdx.y];
+  if (retired(A.a.state, In.id)) return;
+  extern __shared__ float2 lds[];
+  const int nt = (In.nx / 2) / CWM;
+  const int nm = ngroups * nt, nc = gridDim.x - nm;
+  const int b = blockIdx.x;
+  if (b >= nc) {
+    ColInst Im = In;
+    Im.spec = A.mspec[blockIdx.y];
+    col_multi_tile<NY, CWM, NT, R>(Im, L.g[(b - nc) / nt], lds, (b - nc) % nt, nt);
+  } else {
+    col_conv_body<NY, CW, NT, R>(In, lds, b, nc);
   }
 }
 

@@ -113,9 +113,10 @@ int fftlb_set_state(fftlb_handle* h, const float* f, void* stream);
 int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, void* stream);
 
 /* Enqueue `reps` launches of one kernel of the time step, without graph capture:
- * stage 0 = convection column pass together with the stage-1 derivative column pass (one
- * launch), 1 = stage-2 row kernel (closure of Eqs. (18)-(23)), 2 = stage-2 divergence
- * column pass, 3 = collide row kernel (Eqs. (3), (11) and the update).  Running stages
+ * stage 0 = stage-1 derivative column pass together with the convection column pass of
+ * 16 of the 24 populations with v_y != 0 (one launch), 1 = stage-2 row kernel (closure of
+ * Eqs. (18)-(23)), 2 = stage-2 divergence column pass together with the convection column
+ * pass of the other 8, 3 = collide row kernel (Eqs. (3), (11) and the update).  Running stages
  * 0..3 once, in order, is exactly one fftlb_step; repeating a stage is for timing and
  * leaves the state meaningless until the next fftlb_set_state or fftlb_init (each
  * stage-3 launch counts as a step).  Other stage numbers: FFTLB_EINVAL. */
@@ -125,9 +126,10 @@ int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream);
  * the derivative passes (powers of two up to 16, at most the tile width min(16, the
  * largest power of two dividing nx/2), and within 64 KB of LDS: ny * conv_cols <= 8192,
  * 3 * ny * multi_cols <= 8192), and the largest radix of the column transforms of each
- * (8 or 16).  The stage-1 derivative pass runs inside the convection launch with that
- * launch's radix and block size and conv_cols / 3 columns per block (rounded down to a
- * power of two, at least 1); multi_cols and multi_radix set the other derivative passes.  fftlb_init picks the widest tiles and radix 16; a new plan takes effect at
+ * (8 or 16).  In the step both derivative passes run inside convection launches, with
+ * their radix and block size and conv_cols / 3 columns per block (rounded down to a
+ * power of two, at least 1); multi_cols and multi_radix set the derivative passes of the
+ * diagnostics (fftlb_moments, the batch residual) and of fftlb_derivative.  fftlb_init picks the widest tiles and radix 16; a new plan takes effect at
  * the next call (the captured step graphs are rebuilt).  Plans change speed only: the
  * results of any two plans agree to FP32 rounding of the column transforms. */
 typedef struct fftlb_plan {

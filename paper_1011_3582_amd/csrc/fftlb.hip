@@ -259,10 +259,10 @@ int col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStre
   return FFTLB_EINVAL;
 }
 
-int col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+int col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, int pfirst, int nplanes, hipStream_t s) {
   switch (L.ny) {
 #define X(n) \
-  case n: return launch_col_conv_multi<n>(L, groups, ngroups, s);
+  case n: return launch_col_conv_multi<n>(L, groups, ngroups, pfirst, nplanes, s);
     FFTLB_FOR_COL_SIZES(X)
 #undef X
   }
@@ -301,14 +301,21 @@ StepLaunch single_launch(const fftlb_handle* h, const ColPlan& plan) {
 
 constexpr int kNumStages = 4;
 // Kernels of the step, in order, and the stage-1 derivative column pass by itself (the
-// diagnostics reuse it; in the step it runs inside the convection launch).
+// diagnostics reuse it; in the step it runs inside a convection launch).
 enum : int { ST_CONV_S1 = 0, ST_S2_ROWS = 1, ST_S2_COLS = 2, ST_COLLIDE = 3, ST_S1_COLS = 4 };
+
+// The convection columns of the 24 populations with v_y != 0 are split over the two
+// derivative column passes of the step, which are latency-bound and leave most of the GPU
+// idle: the first kConvSplit of them run in the stage-1 launch, the rest in the stage-2
+// launch.  Measured at 1024^2 (step time against the split 8, 12, 16, 18, 20, 24): 16 is
+// best, and 16..20 are within 1 us of each other.
+constexpr int kConvSplit = 16;
 
 int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
   switch (stage) {
-    case ST_CONV_S1: return col_conv_multi(L, kStage1, 3, s);
+    case ST_CONV_S1: return col_conv_multi(L, kStage1, 3, 0, kConvSplit, s);
     case ST_S2_ROWS: return rows(L, RK_STAGE2, Inputs{}, s);
-    case ST_S2_COLS: return col_multi(L, kStage2, 2, s);
+    case ST_S2_COLS: return col_conv_multi(L, kStage2, 2, kConvSplit, 24 - kConvSplit, s);
     case ST_COLLIDE: return rows(L, RK_COLLIDE, Inputs{}, s);
     case ST_S1_COLS: return col_multi(L, kStage1, 3, s);
   }
@@ -323,9 +330,9 @@ int enqueue_residual(const StepLaunch& L, hipStream_t s) {
   return rows(L, RK_RESIDUAL, Inputs{}, s);
 }
 
-// One step of every launch group in `Ls`, kernel after kernel.  (The convection and
-// stage-1 column passes are independent; they overlap inside one joint launch, not on
-// concurrent graph branches.)
+// One step of every launch group in `Ls`, kernel after kernel.  (The convection column
+// pass is independent of the derivative column passes; it overlaps them inside joint
+// launches, not on concurrent graph branches.)
 int enqueue_step_all(const StepLaunch* Ls, int nl, hipStream_t s) {
   for (int k = 0; k < kNumStages; ++k)
     for (int i = 0; i < nl; ++i) RC_TRY(enqueue_stage(Ls[i], k, s));
@@ -461,8 +468,9 @@ int time_stages(const StepLaunch& L, const int* stages, int ns, int reps, hipStr
 }
 
 // Time every column plan of the handle's size on its own state and keep the fastest: the
-// joint convection and stage-1 launch (tile width x radix; the stage-1 tiles follow from
-// them) and the stage-2 derivative pass (tile width x radix) are independent choices.
+// two joint convection and derivative launches of the step (tile width x radix; their
+// derivative tiles follow from them) and the stand-alone derivative passes of the
+// diagnostics (tile width x radix, timed on the stage-1 pass) are independent choices.
 int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
@@ -471,7 +479,7 @@ int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
     set_error("hipEventCreate", hipErrorUnknown);
     return FFTLB_EHIP;
   }
-  const int conv_stage[1] = {ST_CONV_S1}, multi_stages[1] = {ST_S2_COLS};
+  const int conv_stages[2] = {ST_CONV_S1, ST_S2_COLS}, multi_stages[1] = {ST_S1_COLS};
   float bc = 1e30f, bm = 1e30f;
   ColPlan b = h->plan;
   int rc = FFTLB_OK;
@@ -479,7 +487,7 @@ int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
     for (int cw = 1; cw <= conv_cols_max(h->ny, h->tw) && rc == FFTLB_OK; cw *= 2) {
       float ms;
       const ColPlan p{cw, h->plan.multi_cw, radix, h->plan.multi_radix};
-      rc = time_stages(single_launch(h, p), conv_stage, 1, reps, s, e0, e1, &ms);
+      rc = time_stages(single_launch(h, p), conv_stages, 2, reps, s, e0, e1, &ms);
       if (rc == FFTLB_OK && ms < bc) bc = ms, b.conv_cw = cw, b.conv_radix = radix;
     }
     for (int cw = 1; cw <= multi_cols_max(h->ny, h->tw) && rc == FFTLB_OK; cw *= 2) {

@@ -10,11 +10,12 @@
 //
 // Per time step (all derivatives by windowed FFT, Sec. 3.6):
 //   k_col_conv_multi  one launch of two independent column passes: column FFT of the
-//                   row spectra of the 24 populations with v_y != 0, multiply by
+//                   row spectra of some of the 24 populations with v_y != 0, multiply by
 //                   i (v_x k_m(kx) + v_y k_m(ky)) / (nx ny), inverse column FFT (in place);
-//                   and the stage-1 pass of the macroscopic fields, 4 moment spectra -> 6
-//                   y-derivative spectra;
-//   k_col_multi     column pass of derivative groups: 5 -> 3 divergence spectra (stage 2);
+//                   and a derivative pass of the macroscopic fields: 4 moment spectra -> 6
+//                   y-derivative spectra (stage 1; launched with 16 of the populations),
+//                   5 -> 3 divergence spectra (stage 2; with the other 8);
+//   k_col_multi     the derivative passes by themselves (diagnostics);
 //   k_rows_stage2   inverse row FFTs of the 11 derivatives, the pointwise closure of
 //                   Eqs. (18)-(23), forward row FFTs of the 5 fields whose divergences the
 //                   force needs, FP64 partial sums for the global diagnostics;
@@ -569,9 +570,10 @@ __device__ __forceinline__ int conv_column_plane(int j) {
   return 8 * k + (r < 3 ? r + 1 : r + 2);
 }
 
-// Tile b of nblocks (24 planes times (nx/2)/CW column tiles) of one instance.
+// Tile b of nblocks (planes pfirst.. of the 24, (nx/2)/CW column tiles each) of one
+// instance.
 template <int NY, int CW, int NT, int R>
-__device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, int b, int nblocks) {
+__device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, int b, int nblocks, int pfirst) {
   float2* __restrict__ spec = In.spec;
   const float2* twy = In.twy;
   const float* __restrict__ kapx = In.kapx;
@@ -585,7 +587,7 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
   twy = col_twiddles<NY, R>(lds + lds_alloc(NY * CW), twy, tid, NT);
   const int nsub = (nx / 2) / CW;
   b = xcd_remap(b, nblocks);
-  const int p = conv_column_plane(b / nsub), sub = b % nsub;
+  const int p = conv_column_plane(pfirst + b / nsub), sub = b % nsub;
   const unsigned c0 = sub * CW;
   float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
   // element e of the block is (y, c) = (e / CW, e % CW); NT is a multiple of CW, so c and
@@ -722,9 +724,9 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
   col_multi_tile<NY, CW, NT, R>(In, L.g[blockIdx.y], lds, blockIdx.x, gridDim.x);
 }
 
-// The convection pass and a derivative pass (of ngroups groups) in one launch: the first
-// nc blocks of a slot run the convection tiles, the ngroups nt blocks after them the
-// derivative tiles (CWM columns each, nt = (nx/2)/CWM tiles per group) with the
+// Convection tiles of planes pfirst.. and a derivative pass (of ngroups groups) in one
+// launch: the first nc blocks of a slot run the convection tiles, the ngroups nt blocks
+// after them the derivative tiles (CWM columns each, nt = (nx/2)/CWM tiles per group) with the
 // convection pass's block size and radix.  The two passes are independent: the
 // latency-bound derivative tiles, dispatched last, run in the slots that the convection
 // tiles free as that pass drains (measured faster than dispatching them first).
@@ -734,7 +736,7 @@ struct ConvMultiArgs {
 };
 
 template <int NY, int CW, int NT, int R, int CWM>
-__global__ __launch_bounds__(NT, 4) void k_col_conv_multi(ConvMultiArgs A, ColLaunch L, int ngroups) {
+__global__ __launch_bounds__(NT, 4) void k_col_conv_multi(ConvMultiArgs A, ColLaunch L, int ngroups, int pfirst) {
   const ColInst& In = A.a.c[blockIdx.y];
   if (retired(A.a.state, In.id)) return;
   extern __shared__ float2 lds[];
@@ -746,7 +748,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv_multi(ConvMultiArgs A, ColLa
     Im.spec = A.mspec[blockIdx.y];
     col_multi_tile<NY, CWM, NT, R>(Im, L.g[(b - nc) / nt], lds, (b - nc) % nt, nt);
   } else {
-    col_conv_body<NY, CW, NT, R>(In, lds, b, nc);
+    col_conv_body<NY, CW, NT, R>(In, lds, b, nc, pfirst);
   }
 }
 

@@ -48,7 +48,8 @@ constexpr int col_threads(int ny, int cw, int radix) { return cmin(1024, cmax(64
 template <int NY>
 int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s);
 template <int NY>
-int launch_col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s);
+int launch_col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, int pfirst, int nplanes,
+                          hipStream_t s);
 
 enum : int { RK_STAGE2 = 0, RK_COLLIDE = 1, RK_INIT = 2, RK_SET = 3, RK_MOMENTUM = 4, RK_RESIDUAL = 5 };
 template <int NX>

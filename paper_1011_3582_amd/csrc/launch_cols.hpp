@@ -21,20 +21,21 @@ inline ColArgs col_args(const StepLaunch& L, int first, int count, bool conv) {
 constexpr int joint_multi_cw(int cw) { return cw >= 12 ? 4 : cw >= 6 ? 2 : 1; }
 
 template <int NY, int CW, int R>
-int col_conv_multi_plan(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+int col_conv_multi_plan(const StepLaunch& L, const ColLaunch& groups, int ngroups, int pfirst, int nplanes,
+                        hipStream_t s) {
   constexpr int CWM = joint_multi_cw(CW);
   if constexpr (NY * CW > kColLdsElems || kMultiSlots * NY * CWM > kColLdsElems) {
     return FFTLB_EINVAL;
   } else {
     constexpr int NT = col_threads(NY, CW, R);
-    const int nblocks = ngroups * ((L.nx / 2) / CWM) + 24 * ((L.nx / 2) / CW);
+    const int nblocks = ngroups * ((L.nx / 2) / CWM) + nplanes * ((L.nx / 2) / CW);
     const size_t lds = (cmax(lds_alloc(NY * CW), lds_alloc(kMultiSlots * NY * CWM)) + NY) * sizeof(float2);
     for (int first = 0; first < L.ninst; first += kColSlots) {
       const int count = cmin(kColSlots, L.ninst - first);
       ConvMultiArgs a{col_args(L, first, count, true), {}};
       for (int k = 0; k < count; ++k) a.mspec[k] = L.inst[first + k]->spec;
       hipLaunchKernelGGL((k_col_conv_multi<NY, CW, NT, R, CWM>), dim3(nblocks, count), dim3(NT), lds, s, a, groups,
-                         ngroups);
+                         ngroups, pfirst);
     }
     return FFTLB_OK;
   }
@@ -58,13 +59,14 @@ int col_multi_plan(const StepLaunch& L, const ColLaunch& groups, int ngroups, hi
 }
 
 template <int NY, int R>
-int col_conv_multi_cw(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+int col_conv_multi_cw(const StepLaunch& L, const ColLaunch& groups, int ngroups, int pfirst, int nplanes,
+                      hipStream_t s) {
   switch (L.plan.conv_cw) {
-    case 1: return col_conv_multi_plan<NY, 1, R>(L, groups, ngroups, s);
-    case 2: return col_conv_multi_plan<NY, 2, R>(L, groups, ngroups, s);
-    case 4: return col_conv_multi_plan<NY, 4, R>(L, groups, ngroups, s);
-    case 8: return col_conv_multi_plan<NY, 8, R>(L, groups, ngroups, s);
-    case 16: return col_conv_multi_plan<NY, 16, R>(L, groups, ngroups, s);
+    case 1: return col_conv_multi_plan<NY, 1, R>(L, groups, ngroups, pfirst, nplanes, s);
+    case 2: return col_conv_multi_plan<NY, 2, R>(L, groups, ngroups, pfirst, nplanes, s);
+    case 4: return col_conv_multi_plan<NY, 4, R>(L, groups, ngroups, pfirst, nplanes, s);
+    case 8: return col_conv_multi_plan<NY, 8, R>(L, groups, ngroups, pfirst, nplanes, s);
+    case 16: return col_conv_multi_plan<NY, 16, R>(L, groups, ngroups, pfirst, nplanes, s);
   }
   return FFTLB_EINVAL;
 }
@@ -82,10 +84,11 @@ int col_multi_cw(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipS
 }
 
 template <int NY>
-int launch_col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+int launch_col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, int pfirst, int nplanes,
+                          hipStream_t s) {
   switch (L.plan.conv_radix) {
-    case 8: return col_conv_multi_cw<NY, 8>(L, groups, ngroups, s);
-    case 16: return col_conv_multi_cw<NY, 16>(L, groups, ngroups, s);
+    case 8: return col_conv_multi_cw<NY, 8>(L, groups, ngroups, pfirst, nplanes, s);
+    case 16: return col_conv_multi_cw<NY, 16>(L, groups, ngroups, pfirst, nplanes, s);
   }
   return FFTLB_EINVAL;
 }
@@ -101,6 +104,6 @@ int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, 
 
 #define FFTLB_INSTANTIATE_COLS(NY)                                    \
   template int launch_col_multi<NY>(const StepLaunch&, const ColLaunch&, int, hipStream_t); \
-  template int launch_col_conv_multi<NY>(const StepLaunch&, const ColLaunch&, int, hipStream_t);
+  template int launch_col_conv_multi<NY>(const StepLaunch&, const ColLaunch&, int, int, int, hipStream_t);
 
 }  // namespace fftlb

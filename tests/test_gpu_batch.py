@@ -92,6 +92,26 @@ def test_every_plan_gives_the_same_step(ny, nx):
                 assert float((got - ref).abs().max()) < 3e-7 * scale, plan  # a few FP32 ulps of f
 
 
+@pytest.mark.parametrize("ny,nx", [(64, 64), (96, 48)])
+def test_every_plan_gives_the_same_diagnostics(ny, nx):
+    # In the step the derivative tiles follow the convection plan; the stand-alone
+    # derivative passes of the diagnostics (stage 1 again, and the residual's divergence)
+    # follow multi_cols and multi_radix.  Every plan must give the same FP64 globals.
+    fld = W.smooth_random(nx, ny, seed=23, T0=1.25)
+    with solver(fld) as s:
+        s.step(3)
+        _, ref = s.moments()
+        for plan in plans_for(ny, nx):
+            s.set_plan(*plan)
+            _, got = s.moments()
+            for k in ("mass", "px", "py", "umax"):  # from the macroscopic planes: plan-independent
+                assert got[k] == ref[k], (plan, k)
+            # the energy's gradient term and the residual come from column transforms
+            assert got["energy"] == pytest.approx(ref["energy"], rel=1e-6), plan
+            assert got["residual"] == pytest.approx(ref["residual"], rel=1e-3, abs=1e-12), plan
+            assert got["steps"] == ref["steps"]
+
+
 def test_invalid_plans_rejected():
     fld = W.smooth_random(64, 64, seed=22)
     with solver(fld) as s:

@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -46,15 +47,22 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_spinodal1024.json
 CSRC = os.path.join(ROOT, "paper_1011_3582_amd", "csrc")
 
 
+def _code_only(text: bytes) -> bytes:
+    """Source text without its comments and with whitespace collapsed."""
+    text = re.sub(rb"/\*.*?\*/", b" ", text, flags=re.S)
+    text = re.sub(rb"//[^\n]*", b" ", text)
+    return b" ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of every source the solver's kernels are built from: the device headers and the
-    translation units that instantiate the kernels (the host API, fftlb.hip, and the
-    warm-start network's files excluded)."""
+    """Hash of the code of every source the solver's kernels are built from: the device
+    headers and the translation units that instantiate the kernels (the host API, fftlb.hip,
+    and the warm-start network's files excluded).  Comments and layout do not count."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
         if (name.endswith(".hpp") or name.startswith(("rows_", "cols_"))) and not name.startswith("cnn."):
             with open(os.path.join(CSRC, name), "rb") as fh:
-                h.update(name.encode() + fh.read())
+                h.update(name.encode() + _code_only(fh.read()))
     return h.hexdigest()[:16]
 
 

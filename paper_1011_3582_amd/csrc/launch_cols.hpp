@@ -17,7 +17,9 @@ inline ColArgs col_args(const StepLaunch& L, int first, int count, bool conv) {
   return a;
 }
 
-// Columns per derivative tile in the joint launch: as many as fit the convection tile's LDS.
+// Columns per derivative tile in the joint launch: the largest power of two not above
+// CW / 3 (at least 1), so that from CW = 4 on the three derivative planes fit in the
+// convection tile's LDS (the launch allocates the larger of the two).
 constexpr int joint_multi_cw(int cw) { return cw >= 12 ? 4 : cw >= 6 ? 2 : 1; }
 
 template <int NY, int CW, int R>

@@ -262,6 +262,20 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    # context for the roofline fraction: what a plain device copy (torch) reaches on this GPU
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * (1 << 30) * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+
     sites = nx * ny
     step_s = wall / args.steps
     value = 33.0 * sites * args.steps / wall
@@ -294,6 +308,8 @@ def main():
                           "frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS,
                           "kernel_ms": dict(zip(STAGES, kern_ms)),
                           "event_ms_per_step": ev_s / args.steps * 1e3},
+        "device_copy": {"GBs": copy_gbs, "bytes": 2 * (1 << 30),
+                        "note": "torch device-to-device copy of 1 GiB (read + write), for context"},
         "globals": {k: glob[k] for k in ("mass", "energy", "residual", "umax")},
         "plan": {"conv_cols": plan[0], "multi_cols": plan[1], "conv_radix": plan[2], "multi_radix": plan[3]},
     }

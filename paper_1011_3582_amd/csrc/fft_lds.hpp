@@ -158,15 +158,18 @@ __device__ __forceinline__ void dft(float2* v) {
   }
 }
 
-// Twiddles w^r (r = 1..R-1) applied to v[r], from the table in global memory: only w,
-// w^2, w^4, w^8 are read (exact up to their FP32 rounding) and the other powers are
-// products of at most four of them.
-template <int R, int DIR>
-__device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restrict__ tw, int stride) {
-  float2 p[4];
+// Twiddles w^r (r = 1..R-1) from the table in global memory: only the bases w, w^2, w^4,
+// w^8 are read (exact up to their FP32 rounding); applying them to v[r] forms the other
+// powers as products of at most four of them.
+template <int R>
+__device__ __forceinline__ void read_twiddle_bases(float2* p, const float2* __restrict__ tw, int stride) {
 #pragma unroll
   for (int b = 0; b < 4; ++b)
     if ((1 << b) < R) p[b] = tw[(1 << b) * stride];
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void apply_twiddle_bases(float2* v, const float2* p) {
 #pragma unroll
   for (int r = 1; r < R; ++r) {
     float2 w = make_float2(1.0f, 0.0f);
@@ -181,6 +184,7 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restri
   }
 }
 
+
 // Per-pass twiddle tables in LDS (TWL): the pass with span P and radix R reads
 // T_P[(r - 1) P + k] = exp(-2 pi i r k / (P R)) for butterfly k = i mod P, so the lanes of
 // a wave (consecutive k) read consecutive entries and every power is a single LDS read (no
@@ -194,9 +198,9 @@ __device__ __forceinline__ void apply_twiddle_regs(float2* v, const float2* w) {
 }
 
 // One Stockham pass of radix R over NB transforms of length N, span P (product of the
-// radices of the passes before it), executed by NTH threads.  The LDS twiddles (read-only)
-// are read before the pass's barrier together with the data, so that their latency is
-// not added after it.
+// radices of the passes before it), executed by NTH threads.  The twiddles (read-only:
+// the LDS tables, or the bases w, w^2, w^4, w^8 from the global table) are read before
+// the pass's barrier together with the data, so that their latency is not added after it.
 //
 // Offsets.  With the base index B = off + t st + (i or j0) SI a multiple-of-32 apart from
 // a value below the butterfly's span, pad(B + o_r) = pad(B) + pad(o_r) for the load
@@ -210,8 +214,10 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
   constexpr int BPT = (TOT + NTH - 1) / NTH;
   constexpr bool EXACT = (TOT % NTH) == 0;
   constexpr bool TWR = TWL && P > 1;  // twiddles read with the data
+  constexpr bool TWG = !TWL && P > 1;  // global-table twiddle bases read with the data
   float2 v[BPT][R];
   float2 w[BPT][TWR ? R - 1 : 1];
+  float2 wg[BPT][TWG ? 4 : 1];
   unsigned base[BPT], idx[BPT];
   const unsigned ut = opaque_tid<NTH>(tid);
   const unsigned uoff = static_cast<unsigned>(off), ust = static_cast<unsigned>(st);
@@ -242,6 +248,7 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
 #pragma unroll
         for (int r = 1; r < R; ++r) w[s][r - 1] = tp[(r - 1) * P];
       }
+      if constexpr (TWG) read_twiddle_bases<R>(wg[s], tw, (i % P) * (N / (P * R)));
     }
   }
   __syncthreads();
@@ -253,8 +260,8 @@ __device__ __forceinline__ void stockham_pass(float2* __restrict__ lds, int off,
       const unsigned k = i % P;  // P is a compile-time constant (a shift and mask when a power of two)
       if constexpr (TWR)
         apply_twiddle_regs<R, DIR>(v[s], w[s]);
-      else if constexpr (P > 1)
-        apply_twiddles<R, DIR>(v[s], tw, k * (N / (P * R)));
+      else if constexpr (TWG)
+        apply_twiddle_bases<R, DIR>(v[s], wg[s]);
       dft<R, DIR>(v[s]);
       const unsigned j0 = (i - k) * R + k;
       if constexpr (ALIGNED) {

@@ -591,21 +591,34 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
   const unsigned c0 = sub * CW;
   float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
   // element e of the block is (y, c) = (e / CW, e % CW); NT is a multiple of CW, so c and
-  // the k_x multiplier are fixed per thread
+  // the k_x multiplier are fixed per thread.  The k_y of the thread's elements are read
+  // with the data, so that their latency is not added after the forward transform.
+  constexpr int IT = (NY * CW + NT - 1) / NT;
+  constexpr bool FULL = (NY * CW) % NT == 0;
+  float kyv[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned e = ut + i * NT;
+    kyv[i] = (FULL || e < static_cast<unsigned>(NY * CW)) ? elem(kapy, e / CW) : 0.0f;
+  }
+  const float kxv = elem(kapx, c0 + ut % CW);
+  const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
   for_strided<NY * CW, NT>(ut, [&](unsigned e) {
     const unsigned y = e / CW, c = e % CW;
     lds[padu(e)] = elem(g, y * tw + c);
   });
   __syncthreads();
   fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
-  const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
-  const float mx = vx * elem(kapx, c0 + ut % CW);
-  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
-    const unsigned y = e / CW;
-    const float m = (mx + vy * elem(kapy, y)) * scale;
-    const float2 v = lds[padu(e)];
-    lds[padu(e)] = make_float2(-m * v.y, m * v.x);
-  });
+  const float mx = vx * kxv;
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned e = ut + i * NT;
+    if (FULL || e < static_cast<unsigned>(NY * CW)) {
+      const float m = (mx + vy * kyv[i]) * scale;
+      const float2 v = lds[padu(e)];
+      lds[padu(e)] = make_float2(-m * v.y, m * v.x);
+    }
+  }
   __syncthreads();
   fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
   for_strided<NY * CW, NT>(ut, [&](unsigned e) {
@@ -648,6 +661,18 @@ __device__ __forceinline__ void col_multi_body(const ColInst& In, const ColGroup
   const unsigned tw = In.tw;
   const long hp = (long)(In.nx / 2) * NY;  // complex values per spectral plane
   const float scale = In.scale;
+  // the wavenumbers of the thread's elements in the combination (e = c NY + y), read with
+  // the data so that their latency is not added after the forward transforms
+  constexpr int IT = (BLK + NT - 1) / NT;
+  constexpr bool FULL = BLK % NT == 0;
+  float kxv[IT], kyv[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned e = ut + i * NT;
+    const bool in = FULL || e < static_cast<unsigned>(BLK);
+    kxv[i] = in ? elem(In.kapx, c0 + e / NY) : 0.0f;
+    kyv[i] = in ? elem(In.kapy, e % NY) : 0.0f;
+  }
   // global side: consecutive lanes take consecutive columns of a row (e = y CW + c)
 #pragma unroll
   for (int p = 0; p < NIN; ++p) {
@@ -665,9 +690,12 @@ __device__ __forceinline__ void col_multi_body(const ColInst& In, const ColGroup
 #pragma unroll
     for (int p = 0; p < NIN; ++p) kd[o][p] = G.kind[o][p];
   // combination: consecutive lanes take consecutive rows of a column (e = c NY + y)
-  for_strided<BLK, NT>(ut, [&](unsigned e) {
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned e = ut + i * NT;
+    if (!(FULL || e < static_cast<unsigned>(BLK))) continue;
     const unsigned c = e / NY, y = e % NY;
-    const float kx = elem(In.kapx, c0 + c), ky = elem(In.kapy, y);
+    const float kx = kxv[i], ky = kyv[i];
     float2 x[NIN];
 #pragma unroll
     for (int p = 0; p < NIN; ++p) x[p] = lds[padu((p * CW + c) * NY + y)];
@@ -678,7 +706,7 @@ __device__ __forceinline__ void col_multi_body(const ColInst& In, const ColGroup
       for (int p = 0; p < NIN; ++p) acc = cadd(acc, mk_apply(kd[o][p], kx, ky, x[p]));
       lds[padu((o * CW + c) * NY + y)] = make_float2(acc.x * scale, acc.y * scale);
     }
-  });
+  }
   __syncthreads();
   fft_lds<NY, +1, NT, NOUT * CW, false, 1, AL, R>(lds, 0, NY, twy, tid);
 #pragma unroll

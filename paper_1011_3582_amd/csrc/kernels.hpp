@@ -1070,10 +1070,14 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     }
     float fpre[PREF ? 2 * G::NPB : 1][J];
     if constexpr (PREF) {
+      // the prefetches of a round are issued at a raised wave priority (measured faster:
+      // their loads are not held up behind the transform work of the CU's other waves)
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int i = 0; i < 2 * G::NPB; ++i)
 #pragma unroll
         for (int j = 0; j < J; ++j) fpre[i][j] = elem(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
+      __builtin_amdgcn_s_setprio(0);
     }
     if constexpr (MODE == MODE_STEP) {
       const PairBatch<G::NPB> in = conv_batch(rd);
@@ -1142,7 +1146,9 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       }
     }
     if constexpr (PREF) {
+      __builtin_amdgcn_s_setprio(1);
       if (rd + 1 < 4 / GPR) cf = rows_fetch_batch<NX, G::NPB>(conv_batch(rd + 1), P.sg, P.kapx, row0, tid);
+      __builtin_amdgcn_s_setprio(0);
     }
     rows_forward_batch<NX, G::NPB>(lds, io, P.sg, twx, row0, tid);
   }

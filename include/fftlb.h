@@ -22,8 +22,9 @@
  *    device current at the call.  The caller owns all device memory: the workspace,
  *    inputs and outputs.  The library never allocates or frees device memory.
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All work is
- *    enqueued on it asynchronously; no call synchronises, except fftlb_init (it
- *    uploads small tables from host memory and waits for them) and fftlb_destroy.
+ *    enqueued on it asynchronously.  Calls that wait are said so below: fftlb_init (it
+ *    uploads small tables and captures the step graphs), fftlb_poll, fftlb_set_plan (for
+ *    the handle's last graph replay), fftlb_autotune, fftlb_destroy and the batch calls.
  *  - Return value: FFTLB_OK (0) or a negative error code; calls never abort.
  *    Argument errors are detected on the host before any device work is enqueued.
  *  - A handle is used from one host thread at a time.
@@ -42,7 +43,7 @@ extern "C" {
 #define FFTLB_EINVAL (-1)    /* bad configuration, size or pointer                        */
 #define FFTLB_ENOSPC (-2)    /* workspace smaller than fftlb_workspace_bytes() or misaligned */
 #define FFTLB_EHIP (-3)      /* HIP runtime error; fftlb_last_error() has the message      */
-#define FFTLB_EUNSTABLE (-4) /* non-finite values detected (reported by fftlb_moments)     */
+#define FFTLB_EUNSTABLE (-4) /* non-finite values in the state (fftlb_poll, fftlb_batch_run) */
 
 #define FFTLB_Q 33
 #define FFTLB_NGLOBALS 8
@@ -87,7 +88,9 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes,
                void* stream, fftlb_handle** out);
 
 /* Enqueue `nsteps` >= 0 explicit time steps (Sec. 3, Eq. (24) form, all derivatives by
- * windowed FFT).  The step sequence is captured once into HIP graphs and replayed. */
+ * windowed FFT).  The step sequence is captured into HIP graphs of 1, 2, 4, 8 and 16
+ * steps by fftlb_init (and again after a plan change) and replayed: floor(nsteps / 16)
+ * replays of the 16-step graph and one of each graph in the binary digits of the rest. */
 int fftlb_step(fftlb_handle* h, int64_t nsteps, void* stream);
 
 /* Macroscopic fields of the current state (Eqs. (7)-(9) evaluated on f) and FP64 globals.
@@ -101,6 +104,13 @@ int fftlb_step(fftlb_handle* h, int64_t nsteps, void* stream);
  *   [5] max |u|   [6] 1 if any non-finite value was seen in the state, else 0   [7] steps taken. */
 int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, double* globals,
                   void* stream);
+
+/* Synchronising check of the current state: the FP64 globals of fftlb_moments, computed on
+ * `stream` into the workspace and copied to `globals` (HOST double[FFTLB_NGLOBALS], or
+ * NULL); waits for `stream`.  Returns FFTLB_EUNSTABLE when the non-finite flag (global [6])
+ * is set, i.e. some rho, u, T or force coefficient of the state is NaN or infinite
+ * (a blown-up run), else FFTLB_OK; the globals are written in both cases. */
+int fftlb_poll(fftlb_handle* h, double* globals, void* stream);
 
 /* Copy the distribution out to / in from a device [33][ny][nx] float32 buffer. */
 int fftlb_get_state(fftlb_handle* h, float* f, void* stream);
@@ -129,9 +139,12 @@ int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream);
  * (8 or 16).  In the step both derivative passes run inside convection launches, with
  * their radix and block size and conv_cols / 3 columns per block (rounded down to a
  * power of two, at least 1); multi_cols and multi_radix set the derivative passes of the
- * diagnostics (fftlb_moments, the batch residual) and of fftlb_derivative.  fftlb_init picks the widest tiles and radix 16; a new plan takes effect at
- * the next call (the captured step graphs are rebuilt).  Plans change speed only: the
- * results of any two plans agree to FP32 rounding of the column transforms. */
+ * diagnostics (fftlb_moments, the batch residual) and of fftlb_derivative.  fftlb_init picks
+ * the widest tiles and radix 16.  fftlb_set_plan waits for the last replay of the handle's
+ * step graphs (they may still be queued on the caller's stream), destroys them and captures
+ * the new plan's graphs; the new plan applies to everything enqueued after the call.
+ * Plans change speed only: the results of any two plans agree to FP32 rounding of the
+ * column transforms. */
 typedef struct fftlb_plan {
   int32_t conv_cols, multi_cols, conv_radix, multi_radix;
 } fftlb_plan;
@@ -183,7 +196,9 @@ int fftlb_batch_autotune(fftlb_batch* b, int32_t reps, const char* cache_path, v
 /* Advance every running instance until all have retired or at least `max_steps` more
  * steps were taken (a multiple of poll_every, 1..1000).  An instance retires as
  * converged (state 1) when its residual is below `tol` at `consecutive` successive polls,
- * or as unstable (state 2) at a non-finite value.  Synchronises `stream`. */
+ * or as unstable (state 2) at a non-finite value.  Synchronises `stream`.  Returns
+ * FFTLB_EUNSTABLE when some instance is in state 2 at the end of the call (the others were
+ * advanced as usual; fftlb_batch_status tells which), else FFTLB_OK. */
 int fftlb_batch_run(fftlb_batch* b, double tol, int32_t consecutive, int32_t poll_every, int64_t max_steps,
                     void* stream);
 

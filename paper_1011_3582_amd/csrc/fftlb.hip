@@ -42,7 +42,11 @@ void set_error(const char* what, hipError_t e) {
   } while (0)
 
 constexpr int kMaxN = 2048;
-constexpr int kStepsPerGraph = 16;
+// Step graphs of 1, 2, 4, ..., 2^(kGraphLevels - 1) steps: a call of n steps replays the
+// largest one floor(n / 16) times and the rest as its binary digits (at most four more
+// launches), so no count of steps falls back to one replay per step.
+constexpr int kGraphLevels = 5;
+constexpr int kStepsPerGraph = 1 << (kGraphLevels - 1);
 constexpr int kMaxPollEvery = 1000;
 
 // Grid sizes with compiled kernels: powers of two, and 3 * 2^p from 48 to 768.
@@ -91,7 +95,7 @@ bool config_ok(const fftlb_config* c) {
 }
 
 struct Layout {
-  size_t f, sf, spec, macro, cpl, twx, twy, kx, ky, pd, pf, total;
+  size_t f, sf, spec, macro, cpl, twx, twy, kx, ky, pd, pf, gl, total;
 };
 
 // Planes of the spectral block (contiguous, so that a column pass addresses them by index).
@@ -120,6 +124,7 @@ Layout make_layout(int nx, int ny) {
   L.ky = take((size_t)ny * sizeof(float));
   L.pd = take(nblk * 6 * sizeof(double));
   L.pf = take(nblk * 2 * sizeof(float));
+  L.gl = take(FFTLB_NGLOBALS * sizeof(double));
   L.total = o;
   return L;
 }
@@ -211,7 +216,13 @@ struct fftlb_handle {
   ColPlan plan;
   int64_t steps;
   hipStream_t cap;         // capture stream
-  hipGraphExec_t g1, gN;
+  hipGraphExec_t g[kGraphLevels];  // step graphs of 2^i steps
+  // Recorded on the caller's stream after every replay of a step graph: a captured graph is
+  // destroyed only after its last replay has finished (set_plan, destroy).
+  hipEvent_t replayed;
+  bool pending;            // `replayed` was recorded since the last wait on it
+  bool graphs_at_init;     // capture the step graphs in fftlb_init and after a plan change
+  double* gdev;            // FFTLB_NGLOBALS doubles in the workspace for fftlb_poll
 };
 
 namespace {
@@ -387,10 +398,33 @@ int capture(fftlb_handle* h, int nsteps, hipGraphExec_t* out) {
       out);
 }
 
-void drop_graphs(fftlb_handle* h) {
-  if (h->g1) (void)hipGraphExecDestroy(h->g1);
-  if (h->gN) (void)hipGraphExecDestroy(h->gN);
-  h->g1 = h->gN = nullptr;
+// Wait until the last replay of the handle's step graphs has finished.  Destroying an
+// executable graph whose launches are still queued or running is not allowed (the runtime
+// still reads its nodes and kernel arguments); the plan change of a running solver did
+// exactly that before this wait existed.
+int wait_replays(fftlb_handle* h) {
+  if (h->pending) {
+    HIP_TRY(hipEventSynchronize(h->replayed));
+    h->pending = false;
+  }
+  return FFTLB_OK;
+}
+
+int drop_graphs(fftlb_handle* h) {
+  RC_TRY(wait_replays(h));
+  for (hipGraphExec_t& g : h->g)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  return FFTLB_OK;
+}
+
+// Capture every step graph that is missing.
+int ensure_graphs(fftlb_handle* h) {
+  for (int i = 0; i < kGraphLevels; ++i)
+    if (!h->g[i]) RC_TRY(capture(h, 1 << i, &h->g[i]));
+  return FFTLB_OK;
 }
 
 int check_launch(const char* what) {
@@ -410,6 +444,19 @@ int refresh_from_f(fftlb_handle* h, hipStream_t s) {
   in.a[0] = h->I.P.f;
   RC_TRY(rows(single_launch(h, h->plan), RK_SET, in, s));
   return check_launch("refresh");
+}
+
+// The FP64 globals of the current state into `out` (device, FFTLB_NGLOBALS doubles): the
+// stage-1 column pass and the stage-2 row kernel (mass, momentum, energy, max |u|,
+// non-finite flag), the residual pass, and the fixed-order final sum.
+int enqueue_globals(fftlb_handle* h, double* out, hipStream_t s) {
+  const StepLaunch L = single_launch(h, h->plan);
+  RC_TRY(enqueue_stage(L, ST_S1_COLS, s));
+  RC_TRY(enqueue_stage(L, ST_S2_ROWS, s));
+  RC_TRY(enqueue_residual(L, s));
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->I.P.part_d, h->I.nblk, h->I.P.part_f, h->I.nblk,
+                     h->cfg.dx * h->cfg.dy, h->cfg.dt, (double)h->steps, out);
+  return check_launch("globals");
 }
 
 // ---------------------------------------------------------------------------
@@ -505,12 +552,16 @@ int tune(fftlb_handle* h, int reps, hipStream_t s, ColPlan* best) {
   return refresh_from_f(h, s);
 }
 
+// A new plan: the step graphs of the old one are destroyed once their last replay has
+// finished, and captured again (now, for a solver that captures at init; else at the next
+// step call).
 int set_plan(fftlb_handle* h, const ColPlan& p) {
   if (!plan_ok(p, h->ny, h->tw)) return FFTLB_EINVAL;
   if (p.conv_cw != h->plan.conv_cw || p.multi_cw != h->plan.multi_cw || p.conv_radix != h->plan.conv_radix ||
       p.multi_radix != h->plan.multi_radix) {
+    RC_TRY(drop_graphs(h));
     h->plan = p;
-    drop_graphs(h);
+    if (h->graphs_at_init) RC_TRY(ensure_graphs(h));
   }
   return FFTLB_OK;
 }
@@ -654,18 +705,20 @@ int read_state(fftlb_batch* b, hipStream_t s, int* running) {
   return FFTLB_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int fftlb_workspace_bytes(const fftlb_config* cfg, size_t* bytes) {
-  if (!config_ok(cfg) || !bytes) return FFTLB_EINVAL;
-  *bytes = make_layout(cfg->nx, cfg->ny).total;
-  return FFTLB_OK;
+// Free what a handle owns (graphs, capture stream, event) and the handle; waits for the
+// handle's last graph replay.
+void release_handle(fftlb_handle* h) {
+  DeviceGuard dg(h->device);
+  (void)drop_graphs(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->replayed) (void)hipEventDestroy(h->replayed);
+  delete h;
 }
 
-int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const float* rho0, const float* ux0,
-               const float* uy0, const float* T0, void* stream, fftlb_handle** out) {
+// fftlb_init; `graphs`: capture the step graphs now (batch instances, which are advanced by
+// the batch's own graph, capture theirs only if they are ever stepped alone).
+int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const float* rho0, const float* ux0,
+                const float* uy0, const float* T0, void* stream, bool graphs, fftlb_handle** out) {
   if (!out) return FFTLB_EINVAL;
   *out = nullptr;
   if (!config_ok(cfg) || !rho0 || !ux0 || !uy0 || !T0) return FFTLB_EINVAL;
@@ -683,8 +736,11 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   h->L = L;
   h->steps = 0;
   h->plan = default_plan(h->ny, h->tw);
-  h->g1 = h->gN = nullptr;
+  for (hipGraphExec_t& g : h->g) g = nullptr;
   h->cap = nullptr;
+  h->replayed = nullptr;
+  h->pending = false;
+  h->graphs_at_init = graphs;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return FFTLB_EHIP;
@@ -707,6 +763,7 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   P.kapx = reinterpret_cast<const float*>(ws + L.kx);
   P.part_d = reinterpret_cast<double*>(ws + L.pd);
   P.part_f = reinterpret_cast<float*>(ws + L.pf);
+  h->gdev = reinterpret_cast<double*>(ws + L.gl);
   P.nx = h->nx;
   P.ny = h->ny;
   P.plane = (long)h->nx * h->ny;
@@ -763,8 +820,14 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
       set_error("hipStreamSynchronize", e);
       rc = FFTLB_EHIP;
     }
+    if (rc == FFTLB_OK && (e = hipEventCreateWithFlags(&h->replayed, hipEventDisableTiming)) != hipSuccess) {
+      set_error("hipEventCreateWithFlags", e);
+      rc = FFTLB_EHIP;
+    }
+    // the step graphs are captured here, so that no capture falls inside a caller's timed steps
+    if (rc == FFTLB_OK && graphs) rc = ensure_graphs(h);
     if (rc != FFTLB_OK) {
-      delete h;
+      release_handle(h);
       return rc;
     }
   }
@@ -772,22 +835,33 @@ int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const 
   return FFTLB_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int fftlb_workspace_bytes(const fftlb_config* cfg, size_t* bytes) {
+  if (!config_ok(cfg) || !bytes) return FFTLB_EINVAL;
+  *bytes = make_layout(cfg->nx, cfg->ny).total;
+  return FFTLB_OK;
+}
+
+int fftlb_init(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const float* rho0, const float* ux0,
+               const float* uy0, const float* T0, void* stream, fftlb_handle** out) {
+  return init_handle(cfg, workspace, ws_bytes, rho0, ux0, uy0, T0, stream, true, out);
+}
 int fftlb_step(fftlb_handle* h, int64_t nsteps, void* stream) {
   if (!h || nsteps < 0) return FFTLB_EINVAL;
   if (nsteps == 0) return FFTLB_OK;
   DeviceGuard dg(h->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (!h->g1) RC_TRY(capture(h, 1, &h->g1));
-  if (nsteps >= kStepsPerGraph && !h->gN) RC_TRY(capture(h, kStepsPerGraph, &h->gN));
-  int64_t left = nsteps;
-  while (left >= kStepsPerGraph) {
-    HIP_TRY(hipGraphLaunch(h->gN, s));
-    left -= kStepsPerGraph;
-  }
-  while (left > 0) {
-    HIP_TRY(hipGraphLaunch(h->g1, s));
-    --left;
-  }
+  RC_TRY(ensure_graphs(h));
+  const hipGraphExec_t top = h->g[kGraphLevels - 1];
+  for (int64_t left = nsteps / kStepsPerGraph; left > 0; --left) HIP_TRY(hipGraphLaunch(top, s));
+  const int rest = (int)(nsteps % kStepsPerGraph);
+  for (int i = kGraphLevels - 2; i >= 0; --i)
+    if (rest & (1 << i)) HIP_TRY(hipGraphLaunch(h->g[i], s));
+  HIP_TRY(hipEventRecord(h->replayed, s));
+  h->pending = true;
   h->steps += nsteps;
   return FFTLB_OK;
 }
@@ -811,16 +885,20 @@ int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, d
   for (int i = 0; i < 4; ++i)
     if (outs[i])
       HIP_TRY(hipMemcpyAsync(outs[i], h->I.P.macro + (size_t)i * h->nx * h->ny, pb, hipMemcpyDeviceToDevice, s));
-  if (globals) {
-    const StepLaunch L = single_launch(h, h->plan);
-    RC_TRY(enqueue_stage(L, ST_S1_COLS, s));
-    RC_TRY(enqueue_stage(L, ST_S2_ROWS, s));
-    RC_TRY(enqueue_residual(L, s));
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->I.P.part_d, h->I.nblk, h->I.P.part_f, h->I.nblk,
-                       h->cfg.dx * h->cfg.dy, h->cfg.dt, (double)h->steps, globals);
-    RC_TRY(check_launch("moments"));
-  }
+  if (globals) RC_TRY(enqueue_globals(h, globals, s));
   return FFTLB_OK;
+}
+
+int fftlb_poll(fftlb_handle* h, double* globals, void* stream) {
+  if (!h) return FFTLB_EINVAL;
+  DeviceGuard dg(h->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  double g[FFTLB_NGLOBALS];
+  RC_TRY(enqueue_globals(h, h->gdev, s));
+  HIP_TRY(hipMemcpyAsync(g, h->gdev, sizeof g, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (globals) std::memcpy(globals, g, sizeof g);
+  return g[6] != 0.0 ? FFTLB_EUNSTABLE : FFTLB_OK;
 }
 
 int fftlb_get_state(fftlb_handle* h, float* f, void* stream) {
@@ -861,6 +939,7 @@ int fftlb_get_plan(const fftlb_handle* h, fftlb_plan* plan) {
 
 int fftlb_set_plan(fftlb_handle* h, const fftlb_plan* plan) {
   if (!h || !plan) return FFTLB_EINVAL;
+  DeviceGuard dg(h->device);
   return set_plan(h, ColPlan{plan->conv_cols, plan->multi_cols, plan->conv_radix, plan->multi_radix});
 }
 
@@ -877,12 +956,11 @@ int fftlb_destroy(fftlb_handle* h) {
   if (!h) return FFTLB_EINVAL;
   {
     DeviceGuard dg(h->device);
-    // graphs may still be running on the caller's streams
+    // other work of the caller's streams may still read the workspace through the handle's
+    // launches; the graphs themselves are waited for by release_handle
     (void)hipDeviceSynchronize();
-    drop_graphs(h);
-    if (h->cap) (void)hipStreamDestroy(h->cap);
   }
-  delete h;
+  release_handle(h);
   return FFTLB_OK;
 }
 
@@ -935,7 +1013,7 @@ int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, siz
     const fftlb_config& c = cfgs[i];
     fftlb_handle* h = nullptr;
     const size_t wsz = make_layout(c.nx, c.ny).total;
-    const int rc = fftlb_init(&c, ws + L.ws[i], wsz, rho0[i], ux0[i], uy0[i], T0[i], stream, &h);
+    const int rc = init_handle(&c, ws + L.ws[i], wsz, rho0[i], ux0[i], uy0[i], T0[i], stream, false, &h);
     if (rc) {
       fftlb_batch_destroy(b);
       return rc;
@@ -982,6 +1060,9 @@ int fftlb_batch_autotune(fftlb_batch* b, int32_t reps, const char* cache_path, v
     g.plan = p;
     for (int i : g.members) RC_TRY(set_plan(b->inst[i], p));
   }
+  // the batch graph of the old plans: destroyed once its replays have finished (the
+  // autotuner synchronised `s`, where fftlb_batch_run launches it)
+  HIP_TRY(hipStreamSynchronize(s));
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   b->graph = nullptr;
   return FFTLB_OK;
@@ -1014,6 +1095,8 @@ int fftlb_batch_run(fftlb_batch* b, double tol, int32_t consecutive, int32_t pol
   std::vector<long long> steps(b->n);
   HIP_TRY(hipMemcpy(steps.data(), b->st.steps, b->n * sizeof(long long), hipMemcpyDeviceToHost));
   for (int i = 0; i < b->n; ++i) b->inst[i]->steps = steps[i];
+  // an instance retired on a non-finite value (read_state left the flags current)
+  if (std::count(b->hstate.begin(), b->hstate.end(), 2)) return FFTLB_EUNSTABLE;
   return FFTLB_OK;
 }
 

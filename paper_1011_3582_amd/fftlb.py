@@ -96,6 +96,7 @@ def _load():
         "fftlb_init": (ctypes.c_int, [cfgp, vp, sz, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]),
         "fftlb_step": (ctypes.c_int, [vp, i64, vp]),
         "fftlb_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "fftlb_poll": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), vp]),
         "fftlb_get_state": (ctypes.c_int, [vp, vp, vp]),
         "fftlb_set_state": (ctypes.c_int, [vp, vp, vp]),
         "fftlb_derivative": (ctypes.c_int, [vp, vp, vp, i32, vp]),
@@ -201,19 +202,23 @@ class Solver:
             _check(_lib.fftlb_step(self.handle, int(nsteps), _stream(self.device)), "fftlb_step")
 
     def moments(self, globals_: bool = True):
-        """Returns (rho, ux, uy, T) float32 device tensors and a dict of FP64 globals."""
+        """Returns (rho, ux, uy, T) float32 device tensors and a dict of FP64 globals (None
+        without globals_).  The globals come from fftlb_poll, which synchronises and returns
+        FFTLB_EUNSTABLE for a non-finite state (raised here as FFTLBError)."""
         with torch.cuda.device(self.device):
             outs = [torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) for _ in range(4)]
-            g = torch.empty(NGLOBALS, dtype=torch.float64, device=self.device) if globals_ else None
-            _check(_lib.fftlb_moments(self.handle, *(_ptr(o) for o in outs), _ptr(g), _stream(self.device)),
+            _check(_lib.fftlb_moments(self.handle, *(_ptr(o) for o in outs), None, _stream(self.device)),
                    "fftlb_moments")
-            glob = None
-            if g is not None:
-                vals = g.cpu().tolist()
-                glob = dict(zip(GLOBAL_NAMES, vals))
-                if glob["nonfinite"] != 0.0:
-                    raise FFTLBError(FFTLB_EUNSTABLE, "fftlb_moments")
+            glob = self.poll() if globals_ else None
         return outs, glob
+
+    def poll(self):
+        """FP64 globals of the current state as a dict (fftlb_poll: synchronising; raises
+        FFTLBError with code FFTLB_EUNSTABLE if the state holds non-finite values)."""
+        g = (ctypes.c_double * NGLOBALS)()
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_poll(self.handle, g, _stream(self.device)), "fftlb_poll")
+        return dict(zip(GLOBAL_NAMES, g[:]))
 
     def globals_tensor(self, out):
         """Enqueue the FP64 globals into a device float64[8] tensor (no host sync)."""
@@ -334,10 +339,17 @@ class Batch:
             _check(_lib.fftlb_batch_autotune(self.handle, int(reps), cache_path.encode() if cache_path else None,
                                              _stream(self.device)), "fftlb_batch_autotune")
 
-    def run(self, tol: float, consecutive: int = 3, poll_every: int = 100, max_steps: int = 10**6):
+    def run(self, tol: float, consecutive: int = 3, poll_every: int = 100, max_steps: int = 10**6,
+            allow_unstable: bool = False) -> int:
+        """fftlb_batch_run.  It returns FFTLB_EUNSTABLE when an instance has retired on a
+        non-finite value: raised as FFTLBError unless allow_unstable, in which case the code
+        is returned (the other instances were advanced; status() tells which retired)."""
         with torch.cuda.device(self.device):
-            _check(_lib.fftlb_batch_run(self.handle, float(tol), int(consecutive), int(poll_every), int(max_steps),
-                                        _stream(self.device)), "fftlb_batch_run")
+            rc = _lib.fftlb_batch_run(self.handle, float(tol), int(consecutive), int(poll_every), int(max_steps),
+                                      _stream(self.device))
+        if not (allow_unstable and rc == FFTLB_EUNSTABLE):
+            _check(rc, "fftlb_batch_run")
+        return rc
 
     def status(self):
         """dict of numpy arrays: steps, steps_to_tol (-1 unless converged), residual, state."""

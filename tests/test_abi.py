@@ -13,7 +13,8 @@ def test_library_exports_every_declared_function():
     assert {"fftlb_init", "fftlb_step", "fftlb_moments", "fftlb_get_state", "fftlb_set_state",
             "fftlb_destroy", "fftlb_workspace_bytes", "fftlb_strerror", "fftlb_derivative",
             "fftlb_last_error", "fftlb_batch_create", "fftlb_batch_run", "fftlb_autotune", "fftlb_cnn_create",
-            "fftlb_cnn_forward", "fftlb_cnn_gradient", "fftlb_cnn_adam_step", "fftlb_cnn_warm_start"} <= set(names)
+            "fftlb_cnn_forward", "fftlb_cnn_gradient", "fftlb_cnn_adam_step", "fftlb_cnn_warm_start",
+            "fftlb_poll"} <= set(names)
     lib = F.library()
     for n in names:
         assert hasattr(lib, n), n
@@ -66,6 +67,8 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.fftlb_step(None, 1, None) == F.FFTLB_EINVAL
     assert lib.fftlb_moments(None, None, None, None, None, None, None) == F.FFTLB_EINVAL
     assert lib.fftlb_get_state(None, None, None) == F.FFTLB_EINVAL
+    assert lib.fftlb_poll(None, None, None) == F.FFTLB_EINVAL
+    assert lib.fftlb_set_plan(None, None) == F.FFTLB_EINVAL
     assert lib.fftlb_destroy(None) == F.FFTLB_EINVAL
     assert lib.fftlb_strerror(F.FFTLB_ENOSPC).decode().startswith("workspace")
 

@@ -8,6 +8,7 @@ solver with the same plan, so
 every instance must match a single solver started from the same fields bitwise, and the
 FP64 oracle to the one-step tolerance of the parity tests.
 """
+import ctypes
 import math
 import os
 import sys
@@ -194,13 +195,18 @@ def test_batch_retires_converged_and_nonfinite_instances():
     bad.T[7, 9] = np.nan                              # non-finite from the first step on
     with F.Batch([tensors(uni), tensors(act), tensors(bad)]) as b:
         f_uni = None
-        b.run(tol=1e-12, consecutive=3, poll_every=5, max_steps=40)
+        with pytest.raises(F.FFTLBError) as ei:
+            b.run(tol=1e-12, consecutive=3, poll_every=5, max_steps=40)
+        assert ei.value.code == F.FFTLB_EUNSTABLE          # returned by the C ABI itself
         st = b.status()
         assert st["state"][0] == 1 and st["steps_to_tol"][0] == 5 and st["steps"][0] == 15
         assert st["state"][1] == 0 and st["steps"][1] == 40 and st["residual"][1] > 1e-12
         assert st["state"][2] == 2 and st["steps"][2] == 5
         f_uni = b.instance(0).get_state().clone()
-        b.run(tol=1e-12, consecutive=3, poll_every=5, max_steps=10)
+        # the C entry point, called directly, still reports the retired non-finite instance
+        rc = F.library().fftlb_batch_run(b.handle, 1e-12, 3, 5, 10,
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == F.FFTLB_EUNSTABLE
         st2 = b.status()
         assert torch.equal(b.instance(0).get_state(), f_uni)    # retired: untouched
         assert st2["steps"][0] == 15 and st2["steps"][1] == 50 and st2["steps"][2] == 5
@@ -220,3 +226,22 @@ def test_batch_autotune_applies_one_plan_per_size(tmp_path):
                 s.set_plan(*b.instance(i).plan)
                 s.step(8)
                 assert torch.equal(b.instance(i).get_state(), s.get_state()), i
+
+
+def test_batch_512_instance_matches_oracle():
+    """A 512 x 512 droplet (column transforms of length 512, as in the 64-instance workload)
+    beside a 96 x 48 instance: one batch step against one oracle step."""
+    big = W.droplet(512, 512, radius=60, t_ratio=0.85, width=4.0)
+    small = W.smooth_random(48, 96, seed=41, T0=1.2)
+    p = F.Params()
+    with F.Batch([tensors(big), tensors(small)]) as b:
+        b.autotune(reps=2)
+        b.run(tol=0.0, poll_every=2, max_steps=2)
+        f0 = b.instance(0).get_state().cpu().numpy().astype(np.float64)
+        b.run(tol=0.0, poll_every=1, max_steps=1)
+        f1 = b.instance(0).get_state().cpu().numpy().astype(np.float64)
+        plan = b.instance(0).plan
+    ref = O.step(f0, oparams(p), workers=-1)
+    err = np.abs(f1 - ref).max() / np.abs(ref).max()
+    sys.stderr.write(f"[batch 512^2 one step, plan {plan}] max err / max f = {err:.3e}\n")
+    assert err < 3e-7

@@ -11,6 +11,7 @@ Tolerances.  The GPU computes in FP32 and stores f in FP32; the oracle is FP64.
     which the multiplier scales by up to k_max (k_max^2 for the Laplacian), so
     |D g - D_oracle g| <= eps log2(nx ny) max|g| k_max (eps = 6e-8).
 """
+import ctypes
 import math
 import sys
 
@@ -62,7 +63,10 @@ def relerr(a, b):
 
 SHAPES = [(64, 64), (32, 128), (128, 32), (4, 512), (32, 8), (16, 256),
           # lengths 3 * 2^p (a radix-3 pass in every transform)
-          (96, 48), (48, 96), (192, 192), (384, 16), (64, 384), (768, 8)]
+          (96, 48), (48, 96), (192, 192), (384, 16), (64, 384), (768, 8),
+          # columns of 512 (as in the 512^2 batch instances); 2048-point rows (their own row
+          # geometry: four sites per thread, radix-16 passes) and 2048-point columns
+          (512, 32), (16, 2048), (2048, 16)]
 
 
 def _fields_for(ny, nx, seed=0):
@@ -132,7 +136,8 @@ def test_derivative_of_sinusoid_is_exact_in_fp32():
 
 
 @pytest.mark.parametrize("case", ["slab64", "smooth64", "slab_4x512", "smooth_128x32", "smooth_32x8",
-                                  "smooth_96x48", "smooth_192", "slab_16x384"])
+                                  "smooth_96x48", "smooth_192", "slab_16x384", "smooth_512x32",
+                                  "slab_16x2048", "smooth_2048x16", "zeta_H_64"])
 def test_one_step_from_shared_state(case):
     if case == "slab64":
         fld = W.slab_64()
@@ -148,9 +153,18 @@ def test_one_step_from_shared_state(case):
         fld = W.smooth_random(192, 192, seed=7, T0=1.2)
     elif case == "slab_16x384":
         fld = W.slab(384, 16, t_ratio=0.85, width=3.0, noise=1e-3, seed=8)
+    elif case == "smooth_512x32":
+        fld = W.smooth_random(32, 512, seed=15, T0=1.2)
+    elif case == "slab_16x2048":
+        fld = W.slab(2048, 16, t_ratio=0.85, width=3.0, noise=1e-3, seed=16)
+    elif case == "smooth_2048x16":
+        fld = W.smooth_random(16, 2048, seed=17, T0=1.25)
+    elif case == "zeta_H_64":
+        fld = W.smooth_random(64, 64, seed=18, T0=1.2)
     else:
         fld = W.slab(8, 32, t_ratio=0.9, width=1.5, noise=1e-3, seed=5)
-    p = F.Params()
+    # bulk viscosity zeta (Eqs. (21), (22)) and the temperature part H of M = K + H T (Eq. (19))
+    p = F.Params(zeta=2e-3, H=4e-6) if case == "zeta_H_64" else F.Params()
     with solver(fld, p) as s:
         s.step(3)
         f0 = state64(s)
@@ -305,6 +319,61 @@ def test_free_streaming_mode():
         moved = max(moved, np.abs(ref - ref0).max())
         assert np.abs(f[q] - ref).max() < tol, (q, np.abs(f[q] - ref).max(), tol)
     assert moved > 30 * tol
+
+
+def test_graph_ladder_is_bitwise_identical_to_other_splits():
+    # 45 = 2 x 16 + 8 + 4 + 1 replays; the same 45 steps in other call sizes
+    fld = W.slab(64, 64, noise=1e-3, seed=19)
+    with solver(fld) as a, solver(fld) as b:
+        a.step(45)
+        for n in (1, 3, 7, 2, 16, 9, 7):
+            b.step(n)
+        assert torch.equal(a.get_state(), b.get_state())
+        _, g = a.moments()
+        assert g["steps"] == 45
+
+
+def _arch():
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def test_plan_change_right_after_steps_without_sync(tmp_path):
+    # set_plan and the autotuner's cache-hit path are called while the previous plan's step
+    # graphs may still be queued on the stream; the handle must wait for them before it
+    # destroys them.  The trajectory equals that of a solver synchronised before each change.
+    fld = W.smooth_random(128, 128, seed=14, T0=1.2)
+    plans = [(4, 2, 8, 16), (16, 4, 16, 8), (1, 1, 16, 16)]
+    cache = tmp_path / "plans.txt"
+    cache.write_text(f"{_arch()} 128 128 8 2 16 8\n")
+    with solver(fld) as a, solver(fld) as b:
+        for p in plans:
+            a.step(64)
+            a.set_plan(*p)
+            b.step(64)
+            torch.cuda.synchronize()
+            b.set_plan(*p)
+        a.step(37)
+        assert a.autotune(reps=1, cache_path=str(cache)) == (8, 2, 16, 8)    # cached: no timing
+        a.step(21)
+        b.step(37)
+        torch.cuda.synchronize()
+        b.set_plan(8, 2, 16, 8)
+        b.step(21)
+        assert torch.equal(a.get_state(), b.get_state())
+
+
+def test_poll_returns_unstable_through_the_c_abi():
+    lib = F.library()
+    with solver(W.uniform(64, 64)) as s:
+        g = (ctypes.c_double * 8)()
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        assert lib.fftlb_poll(s.handle, g, stream) == F.FFTLB_OK and g[6] == 0.0 and g[0] > 0
+        f = s.get_state().clone()
+        f[7, 3, 40] = float("inf")
+        s.set_state(f)
+        assert lib.fftlb_poll(s.handle, g, stream) == F.FFTLB_EUNSTABLE and g[6] == 1.0
+        assert lib.fftlb_poll(s.handle, None, stream) == F.FFTLB_EUNSTABLE
+        assert lib.fftlb_poll(None, g, stream) == F.FFTLB_EINVAL
 
 
 def test_graph_chunks_are_bitwise_identical_to_single_steps():

@@ -1,5 +1,6 @@
 """FP64 CPU oracle of the warm-start network: a small convolutional encoder-decoder that
-maps (rho0, T0, T_target) on a periodic grid to near-equilibrium (rho, T).
+maps (rho0, T0, T_target) on a periodic grid to near-equilibrium (rho, T), and of the
+transform that turns its prediction into the initial fields of an FFT-LB run.
 
 TEST INFRASTRUCTURE ONLY.  This module is the plain reference the GPU network kernels are
 checked against; only the test suite may import it, and it shares no code with the HIP
@@ -183,3 +184,66 @@ def adam(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ----------------------------------------------------------------------------
+# Warm-start transform: network prediction -> initial fields of the run
+# ----------------------------------------------------------------------------
+#
+# The prediction (rho_hat / rho_c, T_hat / T_c) becomes a physical start:
+#   1. the density is clipped to [1e-3 rho_c, rho_max] (rho_max < 1/b keeps the van der
+#      Waals pressure of Eq. (18) finite);
+#   2. one pass of the periodic binomial filter (1 2 1)/4 along x, then along y: it removes
+#      the grid-scale content the upsampling layers leave (the Nyquist mode exactly), which
+#      the windowed derivatives barely act on;
+#   3. the total mass of the initial field is restored by moving the interfaces: the
+#      deficit is added in proportion to w = |grad rho| (central differences), so the bulk
+#      densities stay; a field without interfaces (sum w <= 1e-6 sum rho) is rescaled;
+#      then the density is clipped again and rescaled to the exact initial mass (a closed
+#      periodic system keeps its mass, and relaxes to the equilibrium that mass selects);
+#   4. the temperature is uniform at the mean of the predicted temperature (equilibria are
+#      isothermal), at least 1e-2 T_c.
+# The run then matches the total energy of the initial state by a uniform temperature shift
+# (fftlb_oracle.match_energy), since energy is the other invariant that selects the
+# equilibrium.
+
+RHO_MIN_FRACTION = 1e-3
+T_MIN_FRACTION = 1e-2
+
+
+def binomial_filter(g):
+    """Periodic (1 2 1)/4 along x (axis 1), then along y (axis 0)."""
+    g = np.asarray(g, dtype=np.float64)
+    h = 0.25 * np.roll(g, 1, axis=1) + 0.5 * g + 0.25 * np.roll(g, -1, axis=1)
+    return 0.25 * np.roll(h, 1, axis=0) + 0.5 * h + 0.25 * np.roll(h, -1, axis=0)
+
+
+def interface_weight(rho):
+    """w = |grad rho| by periodic central differences in grid units:
+    0.5 sqrt((rho[x+1] - rho[x-1])^2 + (rho[y+1] - rho[y-1])^2)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    gx = np.roll(rho, -1, axis=1) - np.roll(rho, 1, axis=1)
+    gy = np.roll(rho, -1, axis=0) - np.roll(rho, 1, axis=0)
+    return 0.5 * np.sqrt(gx * gx + gy * gy)
+
+
+def warm_start_transform(pred, rho0, rho_c, T_c, rho_max):
+    """Initial fields (rho, T) of a warm-started run from the network prediction
+    pred[2, h, w] = (rho_hat / rho_c, T_hat / T_c) and the run's initial density rho0 (steps
+    1-4 above; the energy match is separate).  Returns FP64 arrays (rho, T)."""
+    pred = np.asarray(pred, dtype=np.float64)
+    rho_min = RHO_MIN_FRACTION * rho_c
+    rho = np.clip(rho_c * pred[0], rho_min, rho_max)
+    rho = binomial_filter(rho)
+    m0 = float(np.asarray(rho0, dtype=np.float64).sum())
+    m = float(rho.sum())
+    w = interface_weight(rho)
+    wsum = float(w.sum())
+    if wsum > 1e-6 * m:
+        rho = rho + (m0 - m) * w / wsum
+    else:
+        rho = rho * (m0 / m)
+    rho = np.clip(rho, rho_min, rho_max)
+    rho = rho * (m0 / float(rho.sum()))
+    t = max(float((T_c * pred[1]).mean()), T_MIN_FRACTION * T_c)
+    return rho, np.full_like(rho, t)

@@ -400,6 +400,26 @@ def globals_of(f, p: Params, workers=None):
                 umax=float(np.sqrt(ux * ux + uy * uy).max()))
 
 
+def fields_energy(rho, ux, uy, T, p: Params, workers=None) -> float:
+    """Total energy of macroscopic fields, sum e_T dx dy with e_T of Eq. (17) and the
+    windowed derivatives of rho (the energy of the state f^eq(rho, u, T))."""
+    rho, ux, uy, T = (np.asarray(a, dtype=np.float64) for a in (rho, ux, uy, T))
+    D = Deriv(rho.shape[0], rho.shape[1], p, workers)
+    e = total_energy_density(rho, ux, uy, T, D.x(rho), D.y(rho), p)
+    return float(e.sum() * p.dx * p.dy)
+
+
+def match_energy(rho, ux, uy, T, energy: float, p: Params, workers=None):
+    """Temperature field shifted uniformly so that the fields carry the total energy
+    `energy`.  In Eq. (17) the temperature enters e_T only through rho T, so a uniform
+    shift dT changes the total by dT sum rho dx dy (the mass): dT = (energy - E) / mass.
+    Returns T + dT (density and velocity are left as they are)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    mass = float(rho.sum() * p.dx * p.dy)
+    dT = (energy - fields_energy(rho, ux, uy, T, p, workers)) / mass
+    return np.asarray(T, dtype=np.float64) + dT
+
+
 def residual(conv, p: Params) -> float:
     """dt max_sites |sum_q C_q|: the density change per step carried by convection
     (the collision and the force conserve mass at every site, Eqs. (7), (11))."""

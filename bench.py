@@ -9,6 +9,8 @@ windowed FFT, collision, force, moments).  Inputs are resident in HBM when timin
 Prints one JSON line.  value = site-velocity updates per second = 33 nx ny steps / s.
 roofline: the dominant kernel's algorithmic bytes per launch over its mean launch time,
 timed with HIP events on the stream it runs on, against 8 TB/s.
+batch: the 64-instance batched workload's throughput; time_to_equilibrium: steps and wall
+time of a batch of instances (compensated state) to the residual 1e-8.
 cpu_baseline: the FP64 oracle timed on this host on one step of the same workload.
 """
 from __future__ import annotations
@@ -93,7 +95,7 @@ def write_traffic(fetch_csv, write_csv, calib_mib, nx, ny):
                 vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
         return vals
 
-    want = f"{STAGE_KERNELS[DOMINANT]}<{nx}, 0>"
+    want = f"{STAGE_KERNELS[DOMINANT]}<{nx}, 0, false>"
     rec = {"source_hash": kernel_source_hash(), "nx": nx, "ny": ny, "kernel": want,
            "calib_copy_kib": calib_mib * 1024}
     total = 0.0
@@ -117,9 +119,7 @@ def write_traffic(fetch_csv, write_csv, calib_mib, nx, ny):
 def batch_leg(args, F, W, dev):
     """64 independent instances of uneven grid sizes (128..512 squared; droplets and slabs at
     0.80..0.98 T_c) advanced together: aggregate site-velocity updates per second over
-    `--batch-steps` steps (residual tolerance 0, nothing retires), and optionally the
-    steps and wall time until every instance's residual is below `--equilibrium`."""
-    import numpy as np
+    `--batch-steps` steps (residual tolerance 0, nothing retires)."""
     import torch
     inst = W.batch_instances(64, seed=3)
     fields = [tuple(torch.from_numpy(a) for a in (f.rho, f.ux, f.uy, f.T)) for _, _, _, _, f in inst]
@@ -138,32 +138,55 @@ def batch_leg(args, F, W, dev):
     plans = {}
     for i, (_, N, _, _, _) in enumerate(inst):
         plans.setdefault(str(N), list(b.instance(i).plan))
-    out = {"workload": "64 instances, N x N with N uniform over {128, 192, 256, 384, 512}, T/Tc uniform over "
-                       "0.80..0.98, droplet (R 10..60) or slab, tanh width 4 (seed 3)",
-           "instances": len(inst), "sites": sites, "steps": steps, "ms_per_step": wall / steps * 1e3,
-           "value": 33.0 * sites * steps / wall, "unit": "site·velocity updates/s", "plans": plans}
-    if args.equilibrium > 0:
-        print(f"[bench] batch to residual {args.equilibrium:g}", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        done = 0
-        while done < args.equilibrium_cap:
-            b.run(tol=args.equilibrium, consecutive=3, poll_every=100, max_steps=20000)
-            done += 20000
-            st = b.status()
-            print(f"[bench]   {time.perf_counter() - t0:.0f} s: {int((st['state'] != 0).sum())} retired, "
-                  f"median residual {np.median(st['residual']):.2e}", file=sys.stderr, flush=True)
-            if (st["state"] != 0).all():
-                break
+    b.close()
+    return {"workload": "64 instances, N x N with N uniform over {128, 192, 256, 384, 512}, T/Tc uniform over "
+                        "0.80..0.98, droplet (R 10..60) or slab, tanh width 4 (seed 3)",
+            "instances": len(inst), "sites": sites, "steps": steps, "ms_per_step": wall / steps * 1e3,
+            "value": 33.0 * sites * steps / wall, "unit": "site·velocity updates/s", "plans": plans}
+
+
+def equilibrium_leg(F, W, dev, n, sizes, tol, cap, seed=3):
+    """Time to equilibrium: n instances of the batched workload (grid sizes `sizes`) with the
+    compensated state (precision 1: increments below half an FP32 ulp accumulate, so the
+    residual can fall below the FP32 state's floor of about 4e-8..1e-7), run until each one's
+    residual dt max|D.(rho u)| (= max |rho^{n+1} - rho^n|) stays below tol at 3 polls 100
+    steps apart, or `cap` steps."""
+    import numpy as np
+    import torch
+    inst = W.batch_instances(n, seed=seed, sizes=sizes)
+    fields = [tuple(torch.from_numpy(a) for a in (f.rho, f.ux, f.uy, f.T)) for _, _, _, _, f in inst]
+    sites = sum(N * N for _, N, _, _, _ in inst)
+    print(f"[bench] time to residual {tol:g}: {n} instances ({sites} sites), cap {cap} steps",
+          file=sys.stderr, flush=True)
+    b = F.Batch(fields, F.Params(precision=1), device=dev)
+    b.autotune(reps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < cap:
+        chunk = min(20000, cap - done)
+        b.run(tol=tol, consecutive=3, poll_every=100, max_steps=chunk, allow_unstable=True)
+        done += chunk
         st = b.status()
-        conv = st["steps_to_tol"][st["state"] == 1]
-        out["time_to_equilibrium"] = {
-            "tol": args.equilibrium, "wall_s": time.perf_counter() - t0, "converged": int(len(conv)),
-            "unstable": int((st["state"] == 2).sum()), "capped": int((st["state"] == 0).sum()),
+        print(f"[bench]   {time.perf_counter() - t0:.0f} s, {done} steps: {int((st['state'] != 0).sum())}/{n} "
+              f"retired, median residual {np.median(st['residual']):.2e}", file=sys.stderr, flush=True)
+        if (st["state"] != 0).all():
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = b.status()
+    b.close()
+    conv = st["steps_to_tol"][st["state"] == 1]
+    per = [{"kind": k, "N": N, "T/Tc": t, "R": R, "steps_to_tol": int(s)}
+           for (k, N, t, R, _), s in zip(inst, st["steps_to_tol"])]
+    return {"workload": f"{n} instances of the batched workload with N in {list(sizes)} (seed {seed}), "
+                        "compensated FP32 state", "tol": tol, "cap": cap, "sites": sites, "wall_s": wall,
+            "converged": int(len(conv)), "unstable": int((st["state"] == 2).sum()),
+            "capped": int((st["state"] == 0).sum()),
             "steps_to_tol": {"min": int(conv.min()) if len(conv) else None,
                              "median": float(np.median(conv)) if len(conv) else None,
-                             "max": int(conv.max()) if len(conv) else None}}
-    b.close()
-    return out
+                             "max": int(conv.max()) if len(conv) else None},
+            "instances": per}
 
 
 def cpu_baseline(fields, params, nx, ny):
@@ -191,9 +214,13 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default column plan")
     ap.add_argument("--batch-steps", type=int, default=200,
                     help="timed steps of the 64-instance batch (0: skip the batch leg)")
-    ap.add_argument("--equilibrium", type=float, default=0.0, metavar="TOL",
-                    help="also run the batch until every instance's residual is below TOL (long)")
-    ap.add_argument("--equilibrium-cap", type=int, default=2_000_000)
+    ap.add_argument("--equilibrium-tol", type=float, default=1e-8, metavar="TOL",
+                    help="residual tolerance of the time-to-equilibrium leg (the batched workload's 1e-8)")
+    ap.add_argument("--equilibrium-instances", type=int, default=16,
+                    help="instances of the time-to-equilibrium leg (0: skip it)")
+    ap.add_argument("--equilibrium-sizes", default="128,192",
+                    help="grid sizes of the time-to-equilibrium leg (comma separated)")
+    ap.add_argument("--equilibrium-cap", type=int, default=400_000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (traffic calibration under rocprofv3)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -253,6 +280,11 @@ def main():
     s.close()
 
     batch = batch_leg(args, F, W, dev) if args.batch_steps > 0 else None
+    equil = None
+    if args.equilibrium_instances > 0:
+        sizes = tuple(int(v) for v in args.equilibrium_sizes.split(","))
+        equil = equilibrium_leg(F, W, dev, args.equilibrium_instances, sizes, args.equilibrium_tol,
+                                args.equilibrium_cap)
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -315,6 +347,8 @@ def main():
     }
     if batch is not None:
         out["batch"] = batch
+    if equil is not None:
+        out["time_to_equilibrium"] = equil
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline (1 step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(fields, params, nx, ny)

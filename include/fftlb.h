@@ -61,19 +61,26 @@ extern "C" {
  *  q             Prandtl-number parameter of C_q (Eq. (23)).
  *  a, b          van der Waals constants of P = rho T/(1 - b rho) - a rho^2 (Eq. (18)
  *                with the paper's 3/(3 - rho) and 9/8 written as 1/(1 - b rho) and a), >= 0.
- *  filter_order  0 = exact wavenumber k, 1..4 = windowed k_1..k_4 (Eqs. (44)-(47)). */
+ *  filter_order  0 = exact wavenumber k, 1..4 = windowed k_1..k_4 (Eqs. (44)-(47)).
+ *  precision     storage of the distribution: 0 = FP32; 1 = compensated, f = hi + lo with
+ *                both parts FP32 (|lo| at most half an ulp of hi): each update adds its
+ *                increment exactly, so increments below half an FP32 ulp of f, which an
+ *                FP32 state loses, still accumulate (long relaxations to small residuals);
+ *                33 more planes of workspace and of collide traffic.  Arithmetic is FP32
+ *                in both (the transforms and the convection term take hi). */
 typedef struct fftlb_config {
   int32_t nx, ny;
   double dx, dy, dt;
   double tau, K, H, zeta, q;
   double a, b;
   int32_t filter_order;
-  int32_t reserved; /* must be 0 */
+  int32_t precision;
 } fftlb_config;
 
 typedef struct fftlb_handle fftlb_handle;
 
-/* Bytes of device workspace fftlb_init needs for `cfg` (about 88 * nx * ny * 4 bytes).
+/* Bytes of device workspace fftlb_init needs for `cfg` (about 88 * nx * ny * 4 bytes; 121 for
+ * a compensated state).
  * Returns FFTLB_EINVAL for an unsupported configuration. */
 int fftlb_workspace_bytes(const fftlb_config* cfg, size_t* bytes);
 
@@ -112,7 +119,18 @@ int fftlb_moments(fftlb_handle* h, float* rho, float* ux, float* uy, float* T, d
  * (a blown-up run), else FFTLB_OK; the globals are written in both cases. */
 int fftlb_poll(fftlb_handle* h, double* globals, void* stream);
 
-/* Copy the distribution out to / in from a device [33][ny][nx] float32 buffer. */
+/* Match the total energy: shift the temperature field of the current state uniformly by
+ * dT = (energy - E) / M, with E and M the FP64 total energy (Eq. (17), as global [3] of
+ * fftlb_moments) and mass (global [0]) of the current state, and restart from the local
+ * equilibrium f := f^eq(rho, u, T + dT) of Eq. (3).  Since T enters e_T only through rho T,
+ * the new state has total energy `energy` (up to FP32 rounding of T + dT).  For starting a
+ * run from predicted fields with the invariants of a given initial state: the mass through
+ * the fields themselves, the energy through this call.  Asynchronous on `stream`; a
+ * non-positive T + dT is the caller's responsibility (check with fftlb_poll). */
+int fftlb_match_energy(fftlb_handle* h, double energy, void* stream);
+
+/* Copy the distribution out to / in from a device [33][ny][nx] float32 buffer.  For a
+ * compensated state get_state copies hi (f rounded to FP32) and set_state sets lo to 0. */
 int fftlb_get_state(fftlb_handle* h, float* f, void* stream);
 int fftlb_set_state(fftlb_handle* h, const float* f, void* stream);
 

@@ -19,7 +19,8 @@
  *
  * Arithmetic: every convolution, forward and backward, runs on the bf16 matrix cores with
  * FP32 accumulation (operands rounded to bf16 to nearest even on the way in); activations,
- * parameters, gradients and Adam state are FP32.  Loss: mean squared error over all output
+ * parameters, gradients and Adam state are FP32.  The weight gradient is summed over
+ * pixel chunks in a fixed order, so training is deterministic.  Loss: mean squared error over all output
  * values.  Adam: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected.
  *
  * Conventions as in fftlb.h: device pointers, caller-owned workspace, asynchronous on
@@ -70,16 +71,26 @@ int fftlb_cnn_set_params(fftlb_cnn* c, const float* params, void* stream);
 int fftlb_cnn_read_buffer(const fftlb_cnn* c, int32_t layer, int32_t kind, float* dst, size_t count,
                           void* stream);
 
-/* Warm start of one run: rho0, T0 device [h][w] initial fields, T_target the run's
- * temperature, rho_c, T_c the normalisation (critical point).  Writes the predicted
- * rho_out, T_out [h][w]: the density clamped to [1e-3 rho_c, rho_max] (rho_max below 1/b
- * keeps the equation of state finite), passed once through the periodic binomial filter
- * (1 2 1)/4 along each axis (it removes grid-scale content, which the windowed derivatives
- * barely move) and brought to the initial total mass by adding (M0 - M) |grad rho| /
- * sum |grad rho| (the interfaces move, the bulk densities stay; a field without
- * interfaces is rescaled instead); the
- * temperature uniform at the mean of the predicted temperature field (equilibria are
- * isothermal), at least 1e-2 T_c. */
+/* Warm-start transform of a prediction into the initial fields of a run (the network is
+ * not part of the paper; this prepares its output for fftlb_init).  pred: device [2][h][w],
+ * the predicted rho / rho_c and T / T_c; rho0: device [h][w], the run's initial density (its
+ * total is the mass to keep).  Writes device [h][w] rho_out and T_out:
+ *   1. rho = clip(rho_c pred_0, 1e-3 rho_c, rho_max) (rho_max < 1/b keeps the pressure of
+ *      Eq. (18) finite; rho_max > 1e-3 rho_c);
+ *   2. one pass of the periodic binomial filter (1 2 1)/4 along x, then y (it removes the
+ *      grid-scale content, which the windowed derivatives barely move);
+ *   3. the mass deficit M0 - M (M0 = sum rho0) added in proportion to the interface weight
+ *      w = |grad rho| (periodic central differences), so the bulk densities stay (a field
+ *      with sum w <= 1e-6 M is rescaled instead); clipped again; rescaled to the exact M0;
+ *   4. T uniform at the mean of T_c pred_1, at least 1e-2 T_c.
+ * Sums are FP64 in a fixed order (deterministic).  The total energy is matched afterwards on
+ * the solver (fftlb_match_energy).  Uses the network's input buffer as scratch. */
+int fftlb_cnn_project(fftlb_cnn* c, const float* pred, const float* rho0, float rho_c, float T_c, float rho_max,
+                      float* rho_out, float* T_out, void* stream);
+
+/* Warm start of one run: the network's prediction from the initial fields rho0, T0 (device
+ * [h][w]) and the run's temperature T_target (input channels rho0 / rho_c, T0 / T_c,
+ * T_target / T_c), then fftlb_cnn_project of that prediction into rho_out, T_out. */
 int fftlb_cnn_warm_start(fftlb_cnn* c, const float* rho0, const float* T0, float T_target, float rho_c,
                          float T_c, float rho_max, float* rho_out, float* T_out, void* stream);
 

@@ -25,6 +25,7 @@ def _load():
         "fftlb_cnn_set_params": [vp, vp, vp],
         "fftlb_cnn_read_buffer": [vp, i32, i32, vp, sz, vp],
         "fftlb_cnn_warm_start": [vp, vp, vp, f32, f32, f32, f32, vp, vp, vp],
+        "fftlb_cnn_project": [vp, vp, vp, f32, f32, f32, vp, vp, vp],
         "fftlb_cnn_destroy": [vp],
     }
     for name, args in sig.items():
@@ -140,6 +141,20 @@ class Network:
             _F._check(_lib.fftlb_cnn_warm_start(self.handle, _ptr(r0), _ptr(t0), float(T_target), float(rho_c),
                                                 float(T_c), float(rho_max), _ptr(rho), _ptr(T),
                                                 _stream(self.device)), "fftlb_cnn_warm_start")
+        return rho, T
+
+    def project(self, pred, rho0, rho_c: float, T_c: float, rho_max: float):
+        """fftlb_cnn_project: the warm-start transform of a prediction pred [2, h, w]
+        (normalised rho, T) into (rho, T) [h, w] device tensors."""
+        p = torch.as_tensor(pred, dtype=torch.float32).to(self.device).contiguous()
+        r0 = torch.as_tensor(rho0, dtype=torch.float32).to(self.device).contiguous()
+        if p.shape != (2, self.h, self.w) or r0.shape != (self.h, self.w):
+            raise ValueError("pred must be [2, h, w] and rho0 [h, w]")
+        with torch.cuda.device(self.device):
+            rho = torch.empty_like(r0)
+            T = torch.empty_like(r0)
+            _F._check(_lib.fftlb_cnn_project(self.handle, _ptr(p), _ptr(r0), float(rho_c), float(T_c), float(rho_max),
+                                             _ptr(rho), _ptr(T), _stream(self.device)), "fftlb_cnn_project")
         return rho, T
 
     def close(self):

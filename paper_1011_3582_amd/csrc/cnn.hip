@@ -2,6 +2,7 @@
 // of the forward pass, the backward pass and Adam, and the warm-start transform.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <new>
@@ -21,8 +22,12 @@ thread_local char g_cnn_error[256] = "";
 size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
 
 struct CnnLayout {
-  size_t theta, grad, m, v, z[kLayers], a[kLayers], dz[kLayers], y, x, sums, total;
+  size_t theta, grad, m, v, z[kLayers], a[kLayers], dz[kLayers], y, x, wpart, part, sums, total;
 };
+
+// Pixels per K chunk of the weight-gradient GEMM (each chunk of each sample writes one
+// partial gradient).
+constexpr int kWChunk = 4096;
 
 // Output size of layer l for an h x w input.
 void layer_out(int l, int h, int w, int* ho, int* wo) {
@@ -57,7 +62,16 @@ CnnLayout make_layout(int h, int w, int nmax) {
   }
   L.y = take((size_t)nmax * 2 * h * w * sizeof(float));
   L.x = take((size_t)3 * h * w * sizeof(float));
-  L.sums = take(4 * sizeof(double));
+  size_t wp = 0;  // largest per-layer set of weight-gradient partials
+  for (int l = 0; l < kLayers; ++l) {
+    int ho, wo;
+    layer_out(l, h, w, &ho, &wo);
+    const size_t chunks = ((size_t)ho * wo + kWChunk - 1) / kWChunk;
+    wp = std::max(wp, (size_t)nmax * chunks * kCout[l] * (kCin[l] * 9 + 1));
+  }
+  L.wpart = take(wp * sizeof(float));
+  L.part = take((size_t)kWsMaxBlocks * kWsSums * sizeof(double));
+  L.sums = take(8 * sizeof(double));
   L.total = o;
   return L;
 }
@@ -74,6 +88,9 @@ int launch_gemm(const Pb& pb, int M, int N, int Z, hipStream_t s) {
 
 int grid_for(long count) { return (int)std::min<long>(4096, (count + 255) / 256); }
 
+// Grid of the kernels that write per-block partial sums (at most kWsMaxBlocks blocks).
+int sum_grid(long count) { return (int)std::min<long>(kWsMaxBlocks, (count + 255) / 256); }
+
 }  // namespace
 
 struct fftlb_cnn {
@@ -84,7 +101,9 @@ struct fftlb_cnn {
   float* grad;
   float* m;
   float* v;
-  double* sums;
+  double* sums;   // [0] sum of squared errors; warm start: M0, M, sum w, sum T, M after the shift
+  double* part;   // per-block partial sums
+  float* wpart;   // weight-gradient partials
   int adam_t;
   int have_grad;
   float* ptr(size_t off) const { return reinterpret_cast<float*>(ws + off); }
@@ -127,10 +146,10 @@ int forward(fftlb_cnn* c, const float* x, int n, hipStream_t s) {
 // Backward pass after forward(): loss, dL/dZ of every layer and the parameter gradient.
 int backward(fftlb_cnn* c, const float* x, const float* target, int n, hipStream_t s) {
   const long out_count = (long)n * 2 * c->h * c->w;
-  hipLaunchKernelGGL(k_fill_d, dim3(1), dim3(64), 0, s, c->sums, 4);
-  hipLaunchKernelGGL(k_mse, dim3(grid_for(out_count)), dim3(256), 0, s, c->ptr(c->L.y), target,
-                     c->ptr(c->L.dz[kLayers - 1]), out_count, c->sums);
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(kParams)), dim3(256), 0, s, c->grad, (long)kParams, 0.0f);
+  const int mse_blocks = sum_grid(out_count);
+  hipLaunchKernelGGL(k_mse, dim3(mse_blocks), dim3(256), 0, s, c->ptr(c->L.y), target,
+                     c->ptr(c->L.dz[kLayers - 1]), out_count, c->part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, c->part, mse_blocks, 1, 1, c->sums);
   for (int l = kLayers - 1; l >= 0; --l) {
     const Geom g = c->geom(l);
     const long P = (long)g.hout * g.wout;
@@ -140,13 +159,16 @@ int backward(fftlb_cnn* c, const float* x, const float* target, int n, hipStream
     wg.g = g;
     wg.X = X;
     wg.dZ = c->ptr(c->L.dz[l]);
-    wg.dW = c->grad + param_offset(l);
-    wg.db = wg.dW + (long)g.cout * g.cin * 9;
+    wg.part = c->wpart;
     wg.xs = xs;
     wg.zs = g.cout * P;
-    wg.chunk = 1024;
+    wg.chunk = kWChunk;
     wg.nchunks = (int)((P + wg.chunk - 1) / wg.chunk);
-    if (launch_gemm(wg, g.cout, g.cin * 9 + 1, n * wg.nchunks, s)) return FFTLB_EHIP;
+    const int ncol = g.cin * 9 + 1;
+    if (launch_gemm(wg, g.cout, ncol, n * wg.nchunks, s)) return FFTLB_EHIP;
+    float* dW = c->grad + param_offset(l);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((g.cout * ncol + 255) / 256), dim3(256), 0, s, c->wpart,
+                       n * wg.nchunks, g.cout, ncol, dW, dW + (long)g.cout * g.cin * 9);
     if (l == 0) break;
     BwdDataProblem bd{};
     bd.g = g;
@@ -170,6 +192,26 @@ int check(const char* what) {
     return FFTLB_EHIP;
   }
   return FFTLB_OK;
+}
+
+// The warm-start transform of a prediction pred [2][h][w] (normalised density and
+// temperature) into rho_out, T_out (see fftlb_cnn_project); the network input buffer holds
+// the filter's intermediate and then the interface weights.
+int project(fftlb_cnn* c, const float* pred, const float* rho0, float rho_c, float T_c, float rho_max, float* rho_out,
+            float* T_out, hipStream_t s) {
+  const long P = (long)c->h * c->w;
+  const int G = sum_grid(P);
+  float* tmp = c->ptr(c->L.x);
+  const float rmin = 1e-3f * rho_c;
+  hipLaunchKernelGGL(k_ws_clip, dim3(G), dim3(256), 0, s, pred, rho_out, P, rho_c, rmin, rho_max);
+  hipLaunchKernelGGL(k_ws_smooth_x, dim3(G), dim3(256), 0, s, rho_out, tmp, c->h, c->w);
+  hipLaunchKernelGGL(k_ws_smooth_y, dim3(G), dim3(256), 0, s, tmp, rho_out, c->h, c->w);
+  hipLaunchKernelGGL(k_ws_weights, dim3(G), dim3(256), 0, s, rho0, rho_out, pred + P, tmp, c->h, c->w, T_c, c->part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, c->part, G, kWsSums, 4, c->sums);
+  hipLaunchKernelGGL(k_ws_shift, dim3(G), dim3(256), 0, s, rho_out, tmp, P, rmin, rho_max, c->sums, c->part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, c->part, G, kWsSums, 1, c->sums + 4);
+  hipLaunchKernelGGL(k_ws_finish, dim3(G), dim3(256), 0, s, rho_out, T_out, P, 1e-2f * T_c, c->sums);
+  return check("cnn warm-start transform");
 }
 
 }  // namespace
@@ -201,6 +243,8 @@ int fftlb_cnn_create(int32_t h, int32_t w, int32_t max_batch, void* workspace, s
   c->m = c->ptr(L.m);
   c->v = c->ptr(L.v);
   c->sums = reinterpret_cast<double*>(c->ws + L.sums);
+  c->part = reinterpret_cast<double*>(c->ws + L.part);
+  c->wpart = c->ptr(L.wpart);
   c->adam_t = 0;
   c->have_grad = 0;
   if (hipGetDevice(&c->device) != hipSuccess) {
@@ -292,26 +336,25 @@ int fftlb_cnn_read_buffer(const fftlb_cnn* c, int32_t layer, int32_t kind, float
              : FFTLB_EHIP;
 }
 
+int fftlb_cnn_project(fftlb_cnn* c, const float* pred, const float* rho0, float rho_c, float T_c, float rho_max,
+                      float* rho_out, float* T_out, void* stream) {
+  if (!c || !pred || !rho0 || !rho_out || !T_out || !(rho_c > 0.0f) || !(T_c > 0.0f) || !(rho_max > 1e-3f * rho_c))
+    return FFTLB_EINVAL;
+  return project(c, pred, rho0, rho_c, T_c, rho_max, rho_out, T_out, reinterpret_cast<hipStream_t>(stream));
+}
+
 int fftlb_cnn_warm_start(fftlb_cnn* c, const float* rho0, const float* T0, float T_target, float rho_c, float T_c,
                          float rho_max, float* rho_out, float* T_out, void* stream) {
   if (!c || !rho0 || !T0 || !rho_out || !T_out || !(rho_c > 0.0f) || !(T_c > 0.0f) || !(T_target > 0.0f) ||
-      !(rho_max > 0.0f))
+      !(rho_max > 1e-3f * rho_c))
     return FFTLB_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const long P = (long)c->h * c->w;
   float* x = c->ptr(c->L.x);
-  hipLaunchKernelGGL(k_fill_d, dim3(1), dim3(64), 0, s, c->sums, 4);
   hipLaunchKernelGGL(k_ws_input, dim3(grid_for(P)), dim3(256), 0, s, rho0, T0, x, P, 1.0f / rho_c, 1.0f / T_c,
-                     T_target / T_c, c->sums);
+                     T_target / T_c);
   if (forward(c, x, 1, s)) return check("cnn warm start");
-  hipLaunchKernelGGL(k_ws_output, dim3(grid_for(P)), dim3(256), 0, s, c->ptr(c->L.y), rho_out, P, rho_c, T_c,
-                     1e-3f * rho_c, rho_max, c->sums);
-  // the network input buffer is free now: it holds the filter's intermediate
-  hipLaunchKernelGGL(k_ws_smooth_x, dim3(grid_for(P)), dim3(256), 0, s, rho_out, x, c->h, c->w);
-  hipLaunchKernelGGL(k_ws_smooth_y, dim3(grid_for(P)), dim3(256), 0, s, x, rho_out, c->h, c->w);
-  hipLaunchKernelGGL(k_ws_interface, dim3(grid_for(P)), dim3(256), 0, s, rho_out, x, c->h, c->w, c->sums);
-  hipLaunchKernelGGL(k_ws_project, dim3(grid_for(P)), dim3(256), 0, s, rho_out, x, T_out, P, 1e-2f * T_c, c->sums);
-  return check("cnn warm start");
+  return project(c, c->ptr(c->L.y), rho0, rho_c, T_c, rho_max, rho_out, T_out, s);
 }
 
 int fftlb_cnn_destroy(fftlb_cnn* c) {

@@ -1,12 +1,13 @@
 // Warm-start network on gfx950: every convolution (forward, input gradient, weight gradient)
 // is one implicit GEMM on the bf16 matrix cores with FP32 accumulation.
 //
-// A wave computes a 16 x 64 block of C = A B (four v_mfma_f32_16x16x16_bf16 per 16-deep
-// slice of K); A and B elements are gathered straight from the FP32 tensors in global
-// memory by the problem's accessors and rounded to bf16 on the way into the matrix core.
-// Operand layouts of the 16x16x16 instruction (lane l of the wave, i = 0..3):
-//   A: row l % 16, k = 4 (l / 16) + i      B: k = 4 (l / 16) + i, column l % 16
-//   C: row 4 (l / 16) + i, column l % 16
+// A block of four waves computes a 16 x 256 block of C = A B (each wave 16 x 64: four
+// v_mfma_f32_16x16x32_bf16 per 32-deep slice of K).  The A tile of a slice is gathered once
+// per block into LDS as bf16; B elements are gathered straight from the FP32 tensors by the
+// problem's accessors and rounded to bf16 on the way into the matrix core.  Operand layouts
+// of the 16x16x32 instruction (lane l of the wave):
+//   A: row l % 16, k = 8 (l / 16) + i (i = 0..7)   B: k = 8 (l / 16) + i, column l % 16
+//   C: row 4 (l / 16) + i (i = 0..3), column l % 16
 //
 // Network (3 x 3 taps, periodic padding, cross-correlation; per layer W[Cout][Cin][3][3], b):
 //   1: 3 -> 32 conv   2: 32 -> 32 conv stride 2   3: 32 -> 32 conv stride 2
@@ -20,7 +21,8 @@
 namespace fftlb {
 namespace cnn {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));   // bf16 bit patterns
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));  // operand type of the gfx950 bf16 MFMA
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLayers = 6;
@@ -157,13 +159,14 @@ struct BwdDataProblem {
 
 // Weight gradient: dW[co][k] = sum_p dZ[co][p] X-gather[k][p] over the pixels of every
 // sample; column cin * 9 gathers ones and yields db.  Blocks split the pixel sum (the
-// K dimension) into chunks and accumulate with atomic adds.
+// K dimension) into chunks of every sample (z = sample * nchunks + chunk); each writes its
+// partial sums to part[z][co][k], which k_wgrad_reduce adds in a fixed order (the gradient,
+// and so training, is deterministic).
 struct WGradProblem {
   Geom g;
   const float* X;   // layer input [n][cin][hin][win]
   const float* dZ;  // [n][cout][hout][wout]
-  float* dW;        // [cout][cin * 9]
-  float* db;        // [cout]
+  float* part;      // [n * nchunks][cout][cin * 9 + 1]
   long xs, zs;
   int chunk, nchunks;
   __device__ int M() const { return g.cout; }
@@ -179,64 +182,88 @@ struct WGradProblem {
     if (n == g.cin * 9) return 1.0f;
     return fwd_gather(X + sample(z) * xs, g, n / 9, n % 9, k / g.wout, k % g.wout);
   }
-  __device__ void store(int m, int n, float v, int) const {
-    if (n < g.cin * 9)
-      atomicAdd(&dW[(long)m * g.cin * 9 + n], v);
-    else
-      atomicAdd(&db[m], v);
-  }
+  __device__ void store(int m, int n, float v, int z) const { part[((long)z * M() + m) * N() + n] = v; }
 };
 
-// One wave: a 16 x 64 block of C; a block of 256 threads: 16 x 256.  Grid: x over N / 256,
-// y over M / 16, z over the problem's samples (and K chunks).
+// dW[co][k] (k < cin * 9) and db[co] (k = cin * 9) = the sum over z = 0..nz-1 of
+// part[z][co][k], in order of z, accumulated in FP64.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nz, int cout, int ncol,
+                                                      float* __restrict__ dW, float* __restrict__ db) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int mn = cout * ncol;
+  if (i >= mn) return;
+  double acc = 0.0;
+  for (int z = 0; z < nz; ++z) acc += part[(long)z * mn + i];
+  const int m = i / ncol, k = i % ncol;
+  if (k < ncol - 1)
+    dW[(long)m * (ncol - 1) + k] = (float)acc;
+  else
+    db[m] = (float)acc;
+}
+
+// One wave: a 16 x 64 block of C; a block of 256 threads (four waves): 16 x 256.  Grid: x
+// over N / 256, y over M / 16, z over the problem's samples (and K chunks).  Per 32-deep
+// slice of K the block stages the 16 x 32 A tile, shared by its four waves, in LDS as bf16
+// (each element gathered once per block instead of once per wave), then every wave gathers
+// its B columns and issues four v_mfma_f32_16x16x32_bf16.
 template <class Pb>
 __global__ __launch_bounds__(256) void k_gemm(Pb pb) {
+  // A tile rows padded to 40 bf16 (80 bytes): the 8 values of a lane are one aligned 16-byte read
+  __shared__ __attribute__((aligned(16))) short As[16][40];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 16;
   const int n0 = (blockIdx.x * 4 + wave) * 64;
   const int z = blockIdx.z;
   const int M = pb.M(), N = pb.N();
-  if (n0 >= N) return;  // whole wave past the end (no barriers in this kernel)
+  const bool active = n0 < N;  // a wave past the end still stages A and meets the barriers
   int kb, ke;
   pb.krange(z, kb, ke);
-  const int row = lane & 15, kq = (lane >> 4) * 4;
+  const int row = lane & 15, kq = (lane >> 4) * 8, crow = (lane >> 4) * 4;
+  const int sr = threadIdx.x >> 4, sk = (threadIdx.x & 15) * 2;  // this thread's two staged A elements
   f32x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    bf16x4 av;
+  for (int k0 = kb; k0 < ke; k0 += 32) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int k = k0 + kq + i, m = m0 + row;
-      av[i] = bf16_bits(k < ke && m < M ? pb.a(m, k, z) : 0.0f);
+    for (int e = 0; e < 2; ++e) {
+      const int k = k0 + sk + e, m = m0 + sr;
+      As[sr][sk + e] = bf16_bits(k < ke && m < M ? pb.a(m, k, z) : 0.0f);
     }
+    __syncthreads();
+    if (active) {
+      const s16x8 av = *reinterpret_cast<const s16x8*>(&As[row][kq]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      bf16x4 bv;
-      const int n = n0 + 16 * j + row;
+      for (int j = 0; j < 4; ++j) {
+        s16x8 bv;
+        const int n = n0 + 16 * j + row;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + kq + i;
-        bv[i] = bf16_bits(k < ke && n < N ? pb.b(k, n, z) : 0.0f);
+        for (int i = 0; i < 8; ++i) {
+          const int k = k0 + kq + i;
+          bv[i] = bf16_bits(k < ke && n < N ? pb.b(k, n, z) : 0.0f);
+        }
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                         acc[j], 0, 0, 0);
       }
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
     }
+    __syncthreads();
   }
+  if (!active) return;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int n = n0 + 16 * j + row;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int m = m0 + kq + i;
+      const int m = m0 + crow + i;
       if (m < M && n < N) pb.store(m, n, acc[j][i], z);
     }
   }
 }
 
-// Mean squared error of y against t over `count` values: dL/dy into dy, the sum of squared
-// errors added to *sse (FP64).
+// Mean squared error of y against t over `count` values: dL/dy into dy, and the block
+// partials of the sum of squared errors (FP64) into part[blockIdx.x] (summed by
+// k_sum_partials in a fixed order).
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t,
-                                             float* __restrict__ dy, long count, double* sse) {
+                                             float* __restrict__ dy, long count, double* part) {
   __shared__ double red[256];
   double acc = 0.0;
   const float s = 2.0f / (float)count;
@@ -251,15 +278,11 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const 
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(sse, red[0]);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, long count, float v) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < count; i += (long)gridDim.x * 256) p[i] = v;
-}
-
-__global__ void k_fill_d(double* p, int count) {
-  if ((int)threadIdx.x < count) p[threadIdx.x] = 0.0;
 }
 
 // Adam with bias correction (bc1 = 1 - beta1^t, bc2 = 1 - beta2^t).
@@ -276,58 +299,65 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ th, const floa
   th[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// Warm start: network input (rho0 / rho_c, T0 / T_c, T_target / T_c) and the FP64 sum of rho0.
-__global__ __launch_bounds__(256) void k_ws_input(const float* __restrict__ rho0, const float* __restrict__ T0,
-                                                  float* __restrict__ x, long P, float irc, float itc, float tt,
-                                                  double* sum) {
+// ---------------------------------------------------------------------------
+// Warm-start transform: prediction -> initial fields of the run.  Every sum is formed as
+// per-block FP64 partials (block tree in shared memory) and one fixed-order final sum, so
+// the transform is deterministic.
+// ---------------------------------------------------------------------------
+
+constexpr int kWsMaxBlocks = 1024;  // grid of the transform kernels (grid-stride loops)
+constexpr int kWsSums = 4;          // partial sums per block
+
+// Fixed-order tree sum of v over the 256 threads of a block into part[blockIdx.x * stride + c].
+__device__ __forceinline__ void block_sum(double v, double* red, double* part, int stride, int c) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long)blockIdx.x * stride + c] = red[0];
+  __syncthreads();
+}
+
+// out[c] = sum over blocks b of part[b * stride + c], c < nval, in block order (one block).
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nblocks, int stride,
+                                                      int nval, double* __restrict__ out) {
   __shared__ double red[256];
-  double acc = 0.0;
+  for (int c = 0; c < nval; ++c) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) acc += part[(long)b * stride + c];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+    __syncthreads();
+  }
+}
+
+// Network input (rho0 / rho_c, T0 / T_c, T_target / T_c).
+__global__ __launch_bounds__(256) void k_ws_input(const float* __restrict__ rho0, const float* __restrict__ T0,
+                                                  float* __restrict__ x, long P, float irc, float itc, float tt) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256) {
     x[i] = rho0[i] * irc;
     x[P + i] = T0[i] * itc;
     x[2 * P + i] = tt;
-    acc += rho0[i];
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(sum, red[0]);
-}
-
-// Network output -> density clamped to the physical range; FP64 sums of the density
-// (sums[1]) and of the predicted temperature (sums[2]).
-__global__ __launch_bounds__(256) void k_ws_output(const float* __restrict__ y, float* __restrict__ rho, long P,
-                                                   float rc, float tc, float rmin, float rmax, double* sums) {
-  __shared__ double red[256][2];
-  double acc = 0.0, acct = 0.0;
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256) {
-    const float r = fminf(fmaxf(y[i] * rc, rmin), rmax);
-    rho[i] = r;
-    acc += r;
-    acct += y[P + i] * tc;
-  }
-  red[threadIdx.x][0] = acc;
-  red[threadIdx.x][1] = acct;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      red[threadIdx.x][0] += red[threadIdx.x + w][0];
-      red[threadIdx.x][1] += red[threadIdx.x + w][1];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    atomicAdd(&sums[1], red[0][0]);
-    atomicAdd(&sums[2], red[0][1]);
   }
 }
 
-// One pass of the periodic binomial filter (1 2 1)/4 along x then y, src -> dst (tmp holds
-// the intermediate).  It removes the grid-scale content that upsampling layers leave in a
-// prediction (the Nyquist mode exactly), which the windowed derivatives, nearly blind at
+// Step 1: rho = clip(rho_c pred_0, rmin, rmax).
+__global__ __launch_bounds__(256) void k_ws_clip(const float* __restrict__ pred, float* __restrict__ rho, long P,
+                                                 float rc, float rmin, float rmax) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256)
+    rho[i] = fminf(fmaxf(pred[i] * rc, rmin), rmax);
+}
+
+// Step 2: one pass of the periodic binomial filter (1 2 1)/4 along x then y, src -> dst (tmp
+// holds the intermediate).  It removes the grid-scale content that upsampling layers leave in
+// a prediction (the Nyquist mode exactly), which the windowed derivatives, nearly blind at
 // those wavenumbers, would otherwise carry for a long time; it conserves the total.
 __global__ __launch_bounds__(256) void k_ws_smooth_x(const float* __restrict__ src, float* __restrict__ tmp, int h,
                                                      int w) {
@@ -346,45 +376,57 @@ __global__ __launch_bounds__(256) void k_ws_smooth_y(const float* __restrict__ t
   }
 }
 
-// Interface weight w = |grad rho| (central differences, periodic) into w, and its FP64
-// total into sums[3].
-__global__ __launch_bounds__(256) void k_ws_interface(const float* __restrict__ rho, float* __restrict__ w, int h,
-                                                      int wd, double* sums) {
+// Step 3a: interface weight w = |grad rho| (periodic central differences in grid units) into
+// wt, and the block partials of [sum rho0, sum rho, sum w, sum T_c pred_1].
+__global__ __launch_bounds__(256) void k_ws_weights(const float* __restrict__ rho0, const float* __restrict__ rho,
+                                                    const float* __restrict__ pred_t, float* __restrict__ wt, int h,
+                                                    int wd, float tc, double* __restrict__ part) {
   __shared__ double red[256];
-  double acc = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < (long)h * wd; i += (long)gridDim.x * 256) {
     const int y = (int)(i / wd), x = (int)(i % wd);
     const float gx = rho[(long)y * wd + (x + 1) % wd] - rho[(long)y * wd + (x + wd - 1) % wd];
     const float gy = rho[(long)((y + 1) % h) * wd + x] - rho[(long)((y + h - 1) % h) * wd + x];
     const float g = 0.5f * sqrtf(gx * gx + gy * gy);
-    w[i] = g;
-    acc += g;
+    wt[i] = g;
+    s0 += rho0[i];
+    s1 += rho[i];
+    s2 += g;
+    s3 += pred_t[i] * tc;
   }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(&sums[3], red[0]);
+  block_sum(s0, red, part, kWsSums, 0);
+  block_sum(s1, red, part, kWsSums, 1);
+  block_sum(s2, red, part, kWsSums, 2);
+  block_sum(s3, red, part, kWsSums, 3);
 }
 
-// Restore the initial total mass M0 = sums[0] from the prediction's sums[1] by adding
-// (M0 - M) w / sum(w): the mass goes to or comes from the interfaces, which move slightly,
-// while the bulk densities stay at the predicted values (a uniform rescaling would move
-// both phases off coexistence, and that relaxes only by slow evaporation and
-// condensation).  Without interfaces (sum(w) == 0) the density is rescaled.  The
-// temperature is the mean of the prediction, uniform (the model's equilibria are
-// isothermal, and a non-uniform start would relax only by slow conduction).
-__global__ __launch_bounds__(256) void k_ws_project(float* __restrict__ rho, const float* __restrict__ w,
-                                                    float* __restrict__ T, long P, float tmin, const double* sums) {
-  const double dm = sums[0] - sums[1];
-  const bool shift = sums[3] > 1e-6 * sums[1];
-  const float a = shift ? (float)(dm / sums[3]) : 0.0f;
+// Step 3b: the mass deficit M0 - M (sums[0] - sums[1]) added in proportion to w (a field
+// without interfaces, sum w <= 1e-6 M, is rescaled instead), clipped again; block partials
+// of the new total.
+__global__ __launch_bounds__(256) void k_ws_shift(float* __restrict__ rho, const float* __restrict__ wt, long P,
+                                                  float rmin, float rmax, const double* __restrict__ sums,
+                                                  double* __restrict__ part) {
+  __shared__ double red[256];
+  const bool shift = sums[2] > 1e-6 * sums[1];
+  const float a = shift ? (float)((sums[0] - sums[1]) / sums[2]) : 0.0f;
   const float sc = shift ? 1.0f : (float)(sums[0] / sums[1]);
-  const float t = fmaxf((float)(sums[2] / (double)P), tmin);
+  double acc = 0.0;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256) {
-    rho[i] = shift ? rho[i] + a * w[i] : rho[i] * sc;
+    const float r = fminf(fmaxf(shift ? fmaf(a, wt[i], rho[i]) : rho[i] * sc, rmin), rmax);
+    rho[i] = r;
+    acc += r;
+  }
+  block_sum(acc, red, part, kWsSums, 0);
+}
+
+// Step 3c and 4: rescale to the exact initial mass (sums[0] / sums[4]); the temperature
+// uniform at the mean of the prediction (sums[3] / P), at least tmin.
+__global__ __launch_bounds__(256) void k_ws_finish(float* __restrict__ rho, float* __restrict__ T, long P, float tmin,
+                                                   const double* __restrict__ sums) {
+  const float sc = (float)(sums[0] / sums[4]);
+  const float t = fmaxf((float)(sums[3] / (double)P), tmin);
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256) {
+    rho[i] *= sc;
     T[i] = t;
   }
 }

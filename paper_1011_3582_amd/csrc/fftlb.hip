@@ -90,12 +90,12 @@ bool config_ok(const fftlb_config* c) {
   if (!nonneg(c->K) || !nonneg(c->H) || !nonneg(c->a) || !nonneg(c->b)) return false;
   if (!std::isfinite(c->zeta) || !std::isfinite(c->q)) return false;
   if (c->filter_order < 0 || c->filter_order > 4) return false;
-  if (c->reserved != 0) return false;
+  if (c->precision != 0 && c->precision != 1) return false;
   return true;
 }
 
 struct Layout {
-  size_t f, sf, spec, macro, cpl, twx, twy, kx, ky, pd, pf, gl, total;
+  size_t f, flo, sf, spec, macro, cpl, twx, twy, kx, ky, pd, pf, gl, total;
 };
 
 // Planes of the spectral block (contiguous, so that a column pass addresses them by index).
@@ -103,7 +103,9 @@ enum : int { SB_SM = 0, SB_S1 = 4, SB_S2I = 10, SB_S2O = 15, SB_PLANES = 18 };
 
 size_t align_up(size_t v) { return (v + FFTLB_WORKSPACE_ALIGN - 1) / FFTLB_WORKSPACE_ALIGN * FFTLB_WORKSPACE_ALIGN; }
 
-Layout make_layout(int nx, int ny) {
+// Workspace layout of a configuration (a compensated state adds the 33 low-part planes).
+Layout make_layout(const fftlb_config& c) {
+  const int nx = c.nx, ny = c.ny;
   const size_t plane = (size_t)nx * ny * sizeof(float);  // a real plane, or a half-spectrum plane
   const size_t nblk = (size_t)ny / row_rows_per_block(nx);
   Layout L{};
@@ -114,6 +116,7 @@ Layout make_layout(int nx, int ny) {
     return at;
   };
   L.f = take(33 * plane);
+  L.flo = take(c.precision == 1 ? 33 * plane : 0);
   L.sf = take(32 * plane);
   L.spec = take(SB_PLANES * plane);
   L.macro = take(4 * plane);
@@ -303,7 +306,7 @@ int rows_inverse_real(const fftlb_handle* h, const float2* sa, float* a, hipStre
 }
 
 StepLaunch single_launch(const fftlb_handle* h, const ColPlan& plan) {
-  return StepLaunch{&h->self, nullptr, 1, nullptr, h->nx, h->ny, h->tw, h->I.nblk, plan};
+  return StepLaunch{&h->self, nullptr, 1, nullptr, h->nx, h->ny, h->tw, h->I.nblk, plan, h->cfg.precision == 1};
 }
 
 // ---------------------------------------------------------------------------
@@ -593,6 +596,7 @@ struct fftlb_batch {
   BatchState st;
   struct Group {
     int nx, ny, tw, nblk;
+    bool comp;
     ColPlan plan;
     std::vector<int> members;  // all instances of this size
   };
@@ -632,7 +636,7 @@ int batch_layout(int n, const fftlb_config* cfgs, BatchLayout* out) {
   L.resid = take(n * sizeof(double));
   for (int i = 0; i < n; ++i) {
     if (!config_ok(&cfgs[i])) return FFTLB_EINVAL;
-    L.ws.push_back(take(make_layout(cfgs[i].nx, cfgs[i].ny).total));
+    L.ws.push_back(take(make_layout(cfgs[i]).total));
   }
   L.total = o;
   *out = L;
@@ -656,7 +660,7 @@ void batch_launches(fftlb_batch* b, std::vector<std::vector<int>>* ids, std::vec
     const auto& g = b->groups[k];
     if ((*ids)[k].empty()) continue;
     out->push_back(StepLaunch{(*ptrs)[k].data(), (*ids)[k].data(), (int)(*ids)[k].size(), b->st.state, g.nx, g.ny,
-                              g.tw, g.nblk, g.plan});
+                              g.tw, g.nblk, g.plan, g.comp});
   }
 }
 
@@ -723,7 +727,7 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   *out = nullptr;
   if (!config_ok(cfg) || !rho0 || !ux0 || !uy0 || !T0) return FFTLB_EINVAL;
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % FFTLB_WORKSPACE_ALIGN)) return FFTLB_ENOSPC;
-  const Layout L = make_layout(cfg->nx, cfg->ny);
+  const Layout L = make_layout(*cfg);
   if (ws_bytes < L.total) return FFTLB_ENOSPC;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
@@ -750,6 +754,7 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   I = Inst{};
   Planes& P = I.P;
   P.f = reinterpret_cast<float*>(ws + L.f);
+  P.flo = cfg->precision == 1 ? reinterpret_cast<float*>(ws + L.flo) : nullptr;
   const long hp = (long)h->nx * h->ny / 2;  // complex values per spectral plane
   P.sf = reinterpret_cast<float2*>(ws + L.sf);
   I.spec = reinterpret_cast<float2*>(ws + L.spec);
@@ -841,7 +846,7 @@ extern "C" {
 
 int fftlb_workspace_bytes(const fftlb_config* cfg, size_t* bytes) {
   if (!config_ok(cfg) || !bytes) return FFTLB_EINVAL;
-  *bytes = make_layout(cfg->nx, cfg->ny).total;
+  *bytes = make_layout(*cfg).total;
   return FFTLB_OK;
 }
 
@@ -899,6 +904,22 @@ int fftlb_poll(fftlb_handle* h, double* globals, void* stream) {
   HIP_TRY(hipStreamSynchronize(s));
   if (globals) std::memcpy(globals, g, sizeof g);
   return g[6] != 0.0 ? FFTLB_EUNSTABLE : FFTLB_OK;
+}
+
+int fftlb_match_energy(fftlb_handle* h, double energy, void* stream) {
+  if (!h || !std::isfinite(energy)) return FFTLB_EINVAL;
+  DeviceGuard dg(h->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long P = (long)h->nx * h->ny;
+  float* mac = h->I.P.macro;
+  RC_TRY(enqueue_globals(h, h->gdev, s));
+  hipLaunchKernelGGL(k_shift_temperature, dim3((int)std::min<long>(1024, (P + 255) / 256)), dim3(256), 0, s,
+                     mac + 3 * P, P, h->gdev, energy);
+  // f := f^eq of the macroscopic planes (each thread reads its own sites before it writes them)
+  Inputs in{};
+  for (int c = 0; c < 4; ++c) in.a[c] = mac + c * P;
+  RC_TRY(rows(single_launch(h, h->plan), RK_INIT, in, s));
+  return check_launch("match_energy");
 }
 
 int fftlb_get_state(fftlb_handle* h, float* f, void* stream) {
@@ -1012,7 +1033,7 @@ int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, siz
   for (int i = 0; i < n; ++i) {
     const fftlb_config& c = cfgs[i];
     fftlb_handle* h = nullptr;
-    const size_t wsz = make_layout(c.nx, c.ny).total;
+    const size_t wsz = make_layout(c).total;
     const int rc = init_handle(&c, ws + L.ws[i], wsz, rho0[i], ux0[i], uy0[i], T0[i], stream, false, &h);
     if (rc) {
       fftlb_batch_destroy(b);
@@ -1020,9 +1041,11 @@ int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, siz
     }
     b->inst.push_back(h);
     auto g = std::find_if(b->groups.begin(), b->groups.end(),
-                          [&](const fftlb_batch::Group& gg) { return gg.nx == c.nx && gg.ny == c.ny; });
+                          [&](const fftlb_batch::Group& gg) {
+                            return gg.nx == c.nx && gg.ny == c.ny && gg.comp == (c.precision == 1);
+                          });
     if (g == b->groups.end()) {
-      b->groups.push_back(fftlb_batch::Group{c.nx, c.ny, h->tw, h->I.nblk, h->plan, {}});
+      b->groups.push_back(fftlb_batch::Group{c.nx, c.ny, h->tw, h->I.nblk, c.precision == 1, h->plan, {}});
       g = b->groups.end() - 1;
     }
     g->members.push_back(i);

@@ -115,6 +115,7 @@ __device__ __forceinline__ const T& elem(const T* base, unsigned i) {
 // Pointers into the workspace (and the caller's buffers for the init/set modes).
 struct Planes {
   float* f;          // [33][ny][nx]
+  float* flo;        // [33][ny][nx] low parts of a compensated state f = f + flo (null: FP32 state)
   float2* sf;        // [32] row spectra of f_1..f_32 (in place: convection spectra after the column pass)
   float2* sm;        // [4]  row spectra of rho, ux, uy, T
   float2* s1;        // [6]  stage-1 y-derivative spectra
@@ -956,7 +957,11 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 // (MODE_SET); then moments of the new f and forward row transforms of f_1..f_32 and of
 // rho, ux, uy, T for the next step.  The 32 moving populations go in four rounds of one
 // speed group (8 populations, 4 complex row transforms) each.
-template <int NX, int MODE>
+//
+// COMP: the state is compensated, f = hi + lo with the low parts in P.flo: the update adds
+// every increment exactly (relax_update_comp), the moments add the sums of the low parts,
+// and the row transforms (the next convection terms) take hi; INIT and SET zero lo.
+template <int NX, int MODE, bool COMP = false>
 __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, const Inputs& in, int blk) {
   extern __shared__ float2 lds[];
   using G = RowGeom<NX>;
@@ -997,6 +1002,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // transforms), f^n of the round's populations during its inverse transforms (16
   // registers each).
   constexpr bool PREF = MODE == MODE_STEP && J == 2;
+  if constexpr (COMP) __builtin_assume(P.flo != nullptr);
   BatchFetch<NX, G::NPB> cf;
   Site st[J];
   if constexpr (MODE == MODE_STEP) {
@@ -1040,19 +1046,33 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   }
 
   float m0[J], mx[J], my[J], me[J];
+  // sums of the low parts of a compensated state (moments of hi + lo = moments of hi + these)
+  float l0[COMP ? J : 1], lx[COMP ? J : 1], ly[COMP ? J : 1], le[COMP ? J : 1];
   // rest particle
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const unsigned s = rt.site(j);
-    float fn;
+    float fn, ln = 0.0f;
     if constexpr (MODE == MODE_STEP) {
-      fn = relax_update(st[j], M, elem(P.f + rb, s), feq_rest(st[j]), 0.0f, 0.0f, 0.0f, force_k0(st[j], M, 0.0f));
+      if constexpr (COMP) {
+        const float2 hl = relax_update_comp(st[j], M, elem(P.f + rb, s), elem(P.flo + rb, s), feq_rest(st[j]), 0.0f,
+                                            0.0f, 0.0f, force_k0(st[j], M, 0.0f));
+        fn = hl.x;
+        ln = hl.y;
+      } else {
+        fn = relax_update(st[j], M, elem(P.f + rb, s), feq_rest(st[j]), 0.0f, 0.0f, 0.0f, force_k0(st[j], M, 0.0f));
+      }
     } else if constexpr (MODE == MODE_INIT) {
       fn = rounded(feq_rest(st[j]));
     } else {
       fn = elem(in.a[0] + rb, s);
     }
     elem(P.f + rb, s) = fn;
+    if constexpr (COMP) {
+      elem(P.flo + rb, s) = ln;
+      l0[j] = ln;
+      lx[j] = ly[j] = le[j] = 0.0f;
+    }
     m0[j] = fn;
     mx[j] = my[j] = me[j] = 0.0f;
   }
@@ -1110,11 +1130,13 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
         float* fA = P.f + (long)qa * P.plane + rb;
         float* fB = P.f + (long)qb * P.plane + rb;
+        float* lA = COMP ? P.flo + (long)qa * P.plane + rb : nullptr;
+        float* lB = COMP ? P.flo + (long)qb * P.plane + rb : nullptr;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
           const unsigned x = rt.site(j);
           const unsigned li = rt.at(slot, j);
-          float fa, fb;
+          float fa, fb, la = 0.0f, lb = 0.0f;
           if constexpr (MODE == MODE_SET) {
             fa = elem(in.a[0] + (long)qa * P.plane + rb, x);
             fb = elem(in.a[0] + (long)qb * P.plane + rb, x);
@@ -1125,8 +1147,17 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
               const float2 c = lds[li];
               const float f0a = PREF ? fpre[2 * slot][j] : elem(fA, x);
               const float f0b = PREF ? fpre[2 * slot + 1][j] : elem(fB, x);
-              fa = relax_update(st[j], M, f0a, ea, c.x, vxa, vya, k0[j]);
-              fb = relax_update(st[j], M, f0b, eb, c.y, vxb, vyb, k0[j]);
+              if constexpr (COMP) {
+                const float2 ha = relax_update_comp(st[j], M, f0a, elem(lA, x), ea, c.x, vxa, vya, k0[j]);
+                const float2 hb = relax_update_comp(st[j], M, f0b, elem(lB, x), eb, c.y, vxb, vyb, k0[j]);
+                fa = ha.x;
+                la = ha.y;
+                fb = hb.x;
+                lb = hb.y;
+              } else {
+                fa = relax_update(st[j], M, f0a, ea, c.x, vxa, vya, k0[j]);
+                fb = relax_update(st[j], M, f0b, eb, c.y, vxb, vyb, k0[j]);
+              }
             } else {
               fa = rounded(ea);
               fb = rounded(eb);
@@ -1134,6 +1165,14 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
           }
           elem(fA, x) = fa;
           elem(fB, x) = fb;
+          if constexpr (COMP) {
+            elem(lA, x) = la;
+            elem(lB, x) = lb;
+            l0[j] += la + lb;
+            lx[j] += vxa * la + vxb * lb;
+            ly[j] += vya * la + vyb * lb;
+            le[j] += v2 * (la + lb);
+          }
           m0[j] += fa + fb;
           mx[j] += vxa * fa + vxb * fb;
           my[j] += vya * fa + vyb * fb;
@@ -1155,6 +1194,12 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // moments of the new state and their row spectra
 #pragma unroll
   for (int j = 0; j < J; ++j) {
+    if constexpr (COMP) {
+      m0[j] += l0[j];
+      mx[j] += lx[j];
+      my[j] += ly[j];
+      me[j] += le[j];
+    }
     const unsigned s = rt.site(j);
     const float r = m0[j];
     const float ir = 1.0f / r;
@@ -1171,12 +1216,12 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   rows_forward_batch<NX, 2>(lds, mo, P.sg, twx, row0, tid);
 }
 
-template <int NX, int MODE>
+template <int NX, int MODE, bool COMP>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(RowArgs A, Inputs in) {
   const int s = blockIdx.y;
   if (retired(A.state, A.id[s])) return;
   assume_planes(A.P[s]);
-  rows_collide<NX, MODE>(A.P[s], A.M[s], in, blockIdx.x);
+  rows_collide<NX, MODE, COMP>(A.P[s], A.M[s], in, blockIdx.x);
 }
 
 // Residual pass, step 1: momentum j = rho u of the current state and its row spectra

@@ -34,6 +34,7 @@ struct StepLaunch {
   const int* state;         // device array of retired flags (null: none)
   int nx, ny, tw, nblk;
   ColPlan plan;
+  bool comp;                // compensated state (every instance of the launch)
 };
 
 // Block buffers of the column kernels are kept within 64 KB (in float2 elements).

@@ -27,9 +27,24 @@ int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s
     const RowArgs a = row_args(L, first, count);
     switch (kernel) {
       case RK_STAGE2: hipLaunchKernelGGL(k_rows_stage2<NX>, grid, block, G::LDS * sizeof(float2), s, a); break;
-      case RK_COLLIDE: hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP>), grid, block, lds, s, a, in); break;
-      case RK_INIT: hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT>), grid, block, lds, s, a, in); break;
-      case RK_SET: hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET>), grid, block, lds, s, a, in); break;
+      case RK_COLLIDE:
+        if (L.comp)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, true>), grid, block, lds, s, a, in);
+        else
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, false>), grid, block, lds, s, a, in);
+        break;
+      case RK_INIT:
+        if (L.comp)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT, true>), grid, block, lds, s, a, in);
+        else
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT, false>), grid, block, lds, s, a, in);
+        break;
+      case RK_SET:
+        if (L.comp)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET, true>), grid, block, lds, s, a, in);
+        else
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET, false>), grid, block, lds, s, a, in);
+        break;
       case RK_MOMENTUM: hipLaunchKernelGGL(k_rows_momentum<NX>, grid, block, lds, s, a); break;
       case RK_RESIDUAL: hipLaunchKernelGGL(k_rows_residual<NX>, grid, block, lds, s, a); break;
     }

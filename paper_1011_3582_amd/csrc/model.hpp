@@ -151,11 +151,26 @@ __device__ __forceinline__ float force_k0(const Site& s, const Model& M, float v
 // f^{n+1} = f - dt C - omega (f - feq) + dt I with I = -(s0 + sx vx + sy vy + cc |v|^2) feq,
 // k0 = force_k0(v^2).  The increment is formed first and added once: f is rounded to FP32
 // a single time and no O(eps) multiple of f (e.g. from rounding 1 - omega) biases the mass.
+__device__ __forceinline__ float relax_increment(const Site& s, const Model& M, float f, float feq, float conv,
+                                                 float vx, float vy, float k0) {
+  const float kf = fmaf(s.dsx, vx, fmaf(s.dsy, vy, k0));  // -dt (s0 + sx vx + sy vy + cc v^2)
+  return fmaf(M.omega, feq - f, fmaf(kf, feq, -M.dt * conv));
+}
+
 __device__ __forceinline__ float relax_update(const Site& s, const Model& M, float f, float feq, float conv,
                                               float vx, float vy, float k0) {
-  const float kf = fmaf(s.dsx, vx, fmaf(s.dsy, vy, k0));  // -dt (s0 + sx vx + sy vy + cc v^2)
-  const float inc = fmaf(M.omega, feq - f, fmaf(kf, feq, -M.dt * conv));
-  return f + inc;
+  return f + relax_increment(s, M, f, feq, conv, vx, vy, k0);
+}
+
+// The same update of a compensated state f = hi + lo (|lo| <= half an ulp of hi): the
+// increment (formed from hi) is added to lo first, and the rounding error of adding the
+// result to hi is kept as the new lo (Fast2Sum: exact because |hi| exceeds the addend), so
+// increments below half an ulp of f accumulate instead of being lost.  Returns (hi, lo).
+__device__ __forceinline__ float2 relax_update_comp(const Site& s, const Model& M, float hi, float lo, float feq,
+                                                    float conv, float vx, float vy, float k0) {
+  const float t = lo + relax_increment(s, M, hi, feq, conv, vx, vy, k0);
+  const float h = hi + t;
+  return make_float2(h, t - (h - hi));
 }
 
 }  // namespace fftlb

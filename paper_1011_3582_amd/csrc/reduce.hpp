@@ -47,6 +47,15 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   }
 }
 
+// Uniform temperature shift dT = (energy - E) / M from the globals g (g[3] = E, g[0] = M) of
+// the state: T += dT at every site of the temperature plane.
+__global__ __launch_bounds__(256) void k_shift_temperature(float* __restrict__ T, long P,
+                                                           const double* __restrict__ g, double energy) {
+  const double dT = (energy - g[3]) / g[0];
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < P; i += (long)gridDim.x * 256)
+    T[i] = (float)((double)T[i] + dT);
+}
+
 // Per-instance convergence bookkeeping of a batch, in device memory.
 struct BatchState {
   int* state;              // 0 running, 1 converged, 2 non-finite

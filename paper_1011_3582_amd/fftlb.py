@@ -39,7 +39,7 @@ class Config(ctypes.Structure):
                 ("tau", ctypes.c_double), ("K", ctypes.c_double), ("H", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("q", ctypes.c_double),
                 ("a", ctypes.c_double), ("b", ctypes.c_double),
-                ("filter_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("filter_order", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
@@ -66,10 +66,11 @@ class Params:
     a: float = 2.0
     b: float = 0.4
     m: int = 4
+    precision: int = 0   # 0: f stored in FP32; 1: compensated hi + lo (see fftlb_config)
 
     def config(self, nx: int, ny: int) -> Config:
         return Config(nx, ny, self.dx, self.dy, self.dt, self.tau, self.K, self.H, self.zeta, self.q,
-                      self.a, self.b, self.m, 0)
+                      self.a, self.b, self.m, self.precision)
 
 
 def _load():
@@ -97,6 +98,7 @@ def _load():
         "fftlb_step": (ctypes.c_int, [vp, i64, vp]),
         "fftlb_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "fftlb_poll": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), vp]),
+        "fftlb_match_energy": (ctypes.c_int, [vp, ctypes.c_double, vp]),
         "fftlb_get_state": (ctypes.c_int, [vp, vp, vp]),
         "fftlb_set_state": (ctypes.c_int, [vp, vp, vp]),
         "fftlb_derivative": (ctypes.c_int, [vp, vp, vp, i32, vp]),
@@ -225,6 +227,12 @@ class Solver:
         with torch.cuda.device(self.device):
             _check(_lib.fftlb_moments(self.handle, None, None, None, None, _ptr(out), _stream(self.device)),
                    "fftlb_moments")
+
+    def match_energy(self, energy: float):
+        """fftlb_match_energy: shift T uniformly so that the state's total energy (Eq. (17))
+        equals `energy`, and restart from the local equilibrium."""
+        with torch.cuda.device(self.device):
+            _check(_lib.fftlb_match_energy(self.handle, float(energy), _stream(self.device)), "fftlb_match_energy")
 
     def run_stage(self, stage: int, reps: int = 1):
         """Enqueue `reps` launches of one kernel of the step (see fftlb_run_stage)."""

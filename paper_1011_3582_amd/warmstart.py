@@ -6,7 +6,8 @@
 2. train(): Adam on the mean squared error, through the library's bf16 matrix-core
    kernels (forward, backward and update all run on the GPU).
 3. evaluate(): held-out instances started cold (from their initial fields) and warm (from
-   f^eq of the network's prediction, mass-projected) in one batch, each run until its
+   f^eq of the network's prediction, with the mass and the total energy of the cold start)
+   in one batch, each run until its
    residual stays below the evaluation tolerance; steps to tolerance compared.  Also the
    best-of-two start: both starts run a short probe, the one with the smaller residual
    continues (its cost counts the other start's probe steps too).
@@ -37,18 +38,22 @@ def _tensors(fl):
     return tuple(torch.from_numpy(np.ascontiguousarray(a)) for a in fl)
 
 
-def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0):
+def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0, energy_from=None):
     """Run instances (list of (rho, ux, uy, T) arrays) until each has retired or `cap` steps.
     Returns (status dict, [(rho, T) numpy of every instance], wall seconds); with probe > 0
-    the status also holds "probe_residual", every instance's residual after `probe` steps."""
+    the status also holds "probe_residual", every instance's residual after `probe` steps.
+    energy_from {i: j}: before the run, instance i takes the total energy of instance j's
+    initial state (fftlb_match_energy)."""
     b = F.Batch([_tensors(f) for f in fields])
+    for i, j in (energy_from or {}).items():
+        b.instance(i).match_energy(b.instance(j).poll()["energy"])
     b.autotune(reps=3)
     t0 = time.perf_counter()
     done = 0
     probe_res = None
     while done < cap:
         n = min(probe if (probe and done == 0) else chunk, cap - done)
-        b.run(tol=tol, consecutive=3, poll_every=poll, max_steps=n)
+        b.run(tol=tol, consecutive=3, poll_every=poll, max_steps=n, allow_unstable=True)
         done += n
         st = b.status()
         if probe and probe_res is None:
@@ -132,7 +137,8 @@ def evaluate(net, n, seed, size, tol, cap, probe=1000):
         infer.append(time.perf_counter() - t0)
         r, Tn = rho.cpu().numpy(), T.cpu().numpy()
         warm.append((r, np.zeros_like(r), np.zeros_like(r), Tn))
-    st, relaxed, wall = run_batch(cold + warm, tol, cap, probe=probe)
+    # the warm starts take the total energy of their cold starts (mass is kept by the transform)
+    st, relaxed, wall = run_batch(cold + warm, tol, cap, probe=probe, energy_from={n + k: k for k in range(n)})
     s = st["steps_to_tol"]
     sc, sw = s[:n], s[n:]
     ok = (sc > 0) & (sw > 0)

@@ -140,6 +140,19 @@ int fftlb_set_state(fftlb_handle* h, const float* f, void* stream);
  * Uses the handle's stage-1 buffers: do not overlap it with fftlb_step on another stream. */
 int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): fftlb_derivative without a handle or workspace.  The
+ * windowed derivative op (0 = D_x, 1 = D_y, 2 = D_x D_x + D_y D_y) of the device [ny][nx]
+ * field g into out (may not alias g), for the grid, spacings and window of `cfg` (its other
+ * fields are checked but unused); results equal fftlb_derivative's up to FP32 rounding of
+ * the tables (computed here on the device).  The two spectral planes and the tables live in
+ * a static device array the library holds on each GPU it runs on until the process ends
+ * (about 2.1 MB): nx * ny may not exceed 512 * 512 (FFTLB_EINVAL, with the reason in
+ * fftlb_last_error).  It calls no allocating routine.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller; calls on one stream are ordered. */
+int fftlb_derivative_static(const fftlb_config* cfg, const float* g, float* out, int32_t op, void* stream);
+
 /* Enqueue `reps` launches of one kernel of the time step, without graph capture:
  * stage 0 = stage-1 derivative column pass together with the convection column pass of
  * 16 of the 24 populations with v_y != 0 (one launch), 1 = stage-2 row kernel (closure of

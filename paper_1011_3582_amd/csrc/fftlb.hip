@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -134,12 +135,12 @@ Layout make_layout(const fftlb_config& c) {
 
 // Windowed wavenumber k_m (Eqs. (44)-(47)) of signed index n on a grid of N points with
 // spacing d; the Nyquist index -N/2 gets 0.  m = 0 is the exact wavenumber.
-double windowed_k(int n, int N, double d, int m) {
+__host__ __device__ double windowed_k(int n, int N, double d, int m) {
   if (2 * n == -N || 2 * n == N) return 0.0;
   const double k = 2.0 * M_PI * n / (N * d);
   if (m == 0) return k;
-  static const double c[4] = {1.0, 1.0 / 6.0, 3.0 / 40.0, 5.0 / 112.0};
-  const double s = std::sin(M_PI * (double)n / N);
+  const double c[4] = {1.0, 1.0 / 6.0, 3.0 / 40.0, 5.0 / 112.0};
+  const double s = sin(M_PI * (double)n / N);
   double acc = 0.0, sp = s;
   for (int j = 0; j < m; ++j) {
     acc += c[j] * sp;
@@ -188,11 +189,11 @@ ColLaunch stage2_groups() {
   return b;
 }
 
-// fftlb_derivative: s1 plane 0 -> s1 plane 1 through the full 2D pass.
-ColLaunch derivative_group(int op) {
+// fftlb_derivative: spectral plane p -> plane p + 1 through the full 2D pass.
+ColLaunch derivative_group(int op, int p) {
   const int kinds[3] = {MK_IKX, MK_IKY, MK_LAP};
   ColLaunch d{};
-  d.g[0] = group({SB_S1}, {SB_S1 + 1}, {{kinds[op]}});
+  d.g[0] = group({p}, {p + 1}, {{kinds[op]}});
   return d;
 }
 
@@ -283,22 +284,21 @@ int col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, in
   return FFTLB_EINVAL;
 }
 
-int rows_forward_real(const fftlb_handle* h, const float* a, float2* sa, hipStream_t s) {
-  const int nblk = h->I.nblk;
-  switch (h->nx) {
+// Real plane -> packed row spectra, and back, for an instance's grid, twiddles and k_x table.
+int rows_forward_real(const Inst& I, int nx, const float* a, float2* sa, hipStream_t s) {
+  switch (nx) {
 #define X(n) \
-  case n: return launch_rows_forward_real<n>(nblk, a, nullptr, sa, nullptr, h->I.P.sg, h->I.P.twx, s);
+  case n: return launch_rows_forward_real<n>(I.nblk, a, nullptr, sa, nullptr, I.P.sg, I.P.twx, s);
     FFTLB_FOR_ROW_SIZES(X)
 #undef X
   }
   return FFTLB_EINVAL;
 }
 
-int rows_inverse_real(const fftlb_handle* h, const float2* sa, float* a, hipStream_t s) {
-  const int nblk = h->I.nblk;
-  switch (h->nx) {
+int rows_inverse_real(const Inst& I, int nx, const float2* sa, float* a, hipStream_t s) {
+  switch (nx) {
 #define X(n) \
-  case n: return launch_rows_inverse_real<n>(nblk, sa, nullptr, a, nullptr, h->I.P.sg, h->I.P.twx, h->I.P.kapx, s);
+  case n: return launch_rows_inverse_real<n>(I.nblk, sa, nullptr, a, nullptr, I.P.sg, I.P.twx, I.P.kapx, s);
     FFTLB_FOR_ROW_SIZES(X)
 #undef X
   }
@@ -840,6 +840,62 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   return FFTLB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free windowed derivative (fftlb_derivative_static): the two spectral planes and
+// the tables live in a file-scope device array instead of a caller's workspace.
+// ---------------------------------------------------------------------------
+
+constexpr long kStaticMaxSites = 1L << 18;  // nx * ny at most (512 x 512)
+constexpr size_t kStaticPlane = kStaticMaxSites * sizeof(float);  // a half-spectrum plane
+constexpr size_t kStaticTwx = 2 * kStaticPlane;
+constexpr size_t kStaticTwy = kStaticTwx + kMaxN * sizeof(float2);
+constexpr size_t kStaticKx = kStaticTwy + kMaxN * sizeof(float2);
+constexpr size_t kStaticKy = kStaticKx + kMaxN * sizeof(float);
+constexpr size_t kStaticBytes = kStaticKy + kMaxN * sizeof(float);
+constexpr int kMaxDevices = 64;
+
+// Twiddles exp(-2 pi i j / N) of both axes and the windowed wavenumbers, in FP64, stored FP32
+// (the tables fftlb_init computes on the host).
+__global__ __launch_bounds__(256) void k_static_tables(float2* twx, float2* twy, float* kx, float* ky, int nx, int ny,
+                                                       double dx, double dy, int m) {
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < (nx > ny ? nx : ny); j += gridDim.x * 256) {
+    double sn, cs;
+    if (j < nx) {
+      sincospi(2.0 * j / nx, &sn, &cs);
+      twx[j] = make_float2((float)cs, (float)-sn);
+    }
+    if (j < ny) {
+      sincospi(2.0 * j / ny, &sn, &cs);
+      twy[j] = make_float2((float)cs, (float)-sn);
+      ky[j] = (float)windowed_k(j < ny / 2 ? j : j - ny, ny, dy, m);
+    }
+    if (j < nx / 2) kx[j] = (float)windowed_k(j, nx, dx, m);
+  }
+}
+
+std::mutex g_static_mu;
+unsigned char* g_static_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+// Device address of `scratch` on device `dev` (current), looked up once per device: each GPU
+// holds its own copy of the array, and in host code the array's name is only a stand-in.
+int static_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return FFTLB_EINVAL;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_static_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_static_ptr[dev];
+  return FFTLB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -945,11 +1001,50 @@ int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, vo
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   float2* src = h->I.P.s1;
   float2* dst = h->I.P.s1 + (long)h->nx * h->ny / 2;
-  RC_TRY(rows_forward_real(h, g, src, s));
+  RC_TRY(rows_forward_real(h->I, h->nx, g, src, s));
   // the derivative entry point runs every operator through the full 2D pass
-  RC_TRY(col_multi(single_launch(h, h->plan), derivative_group(op), 1, s));
-  RC_TRY(rows_inverse_real(h, dst, out, s));
+  RC_TRY(col_multi(single_launch(h, h->plan), derivative_group(op, SB_S1), 1, s));
+  RC_TRY(rows_inverse_real(h->I, h->nx, dst, out, s));
   return check_launch("derivative");
+}
+
+int fftlb_derivative_static(const fftlb_config* cfg, const float* g, float* out, int32_t op, void* stream) {
+  if (!config_ok(cfg) || !g || !out || g == out || op < 0 || op > 2) return FFTLB_EINVAL;
+  const int nx = cfg->nx, ny = cfg->ny;
+  if ((long)nx * ny > kStaticMaxSites) {
+    std::snprintf(g_last_error, sizeof g_last_error,
+                  "fftlb_derivative_static: nx * ny = %ld exceeds the static scratch maximum of %ld points",
+                  (long)nx * ny, kStaticMaxSites);
+    return FFTLB_EINVAL;
+  }
+  int dev;
+  HIP_TRY(hipGetDevice(&dev));
+  unsigned char* ptr = nullptr;
+  RC_TRY(static_scratch(dev, &ptr));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // the instance the kernels see: spectral planes 0 and 1, tables, all in the scratch array
+  Inst I{};
+  I.spec = reinterpret_cast<float2*>(ptr);
+  I.P.twx = reinterpret_cast<const float2*>(ptr + kStaticTwx);
+  I.twy = reinterpret_cast<const float2*>(ptr + kStaticTwy);
+  I.P.kapx = reinterpret_cast<const float*>(ptr + kStaticKx);
+  I.kapy = reinterpret_cast<const float*>(ptr + kStaticKy);
+  const int tw = tile_width(nx);
+  I.P.sg.ny = ny;
+  I.P.sg.tw = tw;
+  I.P.sg.log2tw = ilog2(tw);
+  I.M.scale = (float)(1.0 / ((double)nx * ny));
+  I.nblk = ny / row_rows_per_block(nx);
+  hipLaunchKernelGGL(k_static_tables, dim3((std::max(nx, ny) + 255) / 256), dim3(256), 0, s,
+                     reinterpret_cast<float2*>(ptr + kStaticTwx), reinterpret_cast<float2*>(ptr + kStaticTwy),
+                     reinterpret_cast<float*>(ptr + kStaticKx), reinterpret_cast<float*>(ptr + kStaticKy), nx, ny,
+                     cfg->dx, cfg->dy, cfg->filter_order);
+  const Inst* self = &I;
+  const StepLaunch L{&self, nullptr, 1, nullptr, nx, ny, tw, I.nblk, default_plan(ny, tw), false};
+  RC_TRY(rows_forward_real(I, nx, g, I.spec, s));
+  RC_TRY(col_multi(L, derivative_group(op, 0), 1, s));
+  RC_TRY(rows_inverse_real(I, nx, I.spec + (long)nx * ny / 2, out, s));
+  return check_launch("derivative_static");
 }
 
 int fftlb_get_plan(const fftlb_handle* h, fftlb_plan* plan) {

@@ -102,6 +102,7 @@ def _load():
         "fftlb_get_state": (ctypes.c_int, [vp, vp, vp]),
         "fftlb_set_state": (ctypes.c_int, [vp, vp, vp]),
         "fftlb_derivative": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+        "fftlb_derivative_static": (ctypes.c_int, [cfgp, vp, vp, i32, vp]),
         "fftlb_run_stage": (ctypes.c_int, [vp, i32, i32, vp]),
         "fftlb_destroy": (ctypes.c_int, [vp]),
         "fftlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),

@@ -85,3 +85,16 @@ def test_cnn_host_checks():
     assert lib.fftlb_cnn_create(64, 64, 1, None, 0, None, None, ctypes.byref(c)) == F.FFTLB_EINVAL
     assert lib.fftlb_cnn_forward(None, None, None, 1, None) == F.FFTLB_EINVAL
     assert N.PARAMS == 38466
+
+
+def test_static_derivative_rejects_sizes_beyond_its_scratch():
+    # checked on the host before any device work: fake pointers are never dereferenced
+    lib = F.library()
+    fake, fake2 = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    for nx, ny in [(1024, 512), (2048, 256), (1024, 1024)]:
+        cfg = F.Params().config(nx, ny)
+        assert lib.fftlb_derivative_static(ctypes.byref(cfg), fake, fake2, 0, None) == F.FFTLB_EINVAL
+        assert "static scratch" in lib.fftlb_last_error().decode()
+    cfg = F.Params().config(64, 64)
+    assert lib.fftlb_derivative_static(ctypes.byref(cfg), fake, fake, 0, None) == F.FFTLB_EINVAL   # aliasing
+    assert lib.fftlb_derivative_static(ctypes.byref(cfg), fake, fake2, 3, None) == F.FFTLB_EINVAL  # bad op

@@ -83,3 +83,48 @@ def test_relaxed_slabs_follow_the_maxwell_coexistence_curve():
                          f"residual {float(st['residual'][i]):.2e}\n")
     batch.close()
     assert worst < 1e-4, worst
+
+
+def test_laplace_law_surface_tension():
+    """Three droplets (R = 26, 32, 38 grid units on 128 x 128, K = 1e-5, T = 0.95 T_c) relax for
+    400,000 steps: the slope of dP = P_in - P_out against 1/R (Sec. 4.2, Eq. (55)) matches the
+    surface tension of the planar interface, sigma = K int rho'^2 dz (Eq. (56)), at the relaxed
+    temperature.  The paper's own fits differ from its theory by 1..4%; the full study (five
+    radii per K, three K, 10^6 steps on 192 x 192) measures -2.3% at this K.  Tolerance 8%."""
+    from paper_1011_3582_amd import validation as V
+    res = V.laplace(n=128, radii=(26, 32, 38), Ks=(1e-5,), cap=400_000, tol=1e-9)
+    k = res["K"]["1e-05"]
+    sys.stderr.write(f"[gpu-test] sigma fit {k['sigma_fit']:.4e}, theory {k['sigma_theory']:.4e}\n")
+    assert abs(k["sigma_fit"] - k["sigma_theory"]) < 0.08 * k["sigma_theory"]
+    # dP grows as the radius shrinks, by about sigma/R
+    dps = [d["dP"] for d in k["droplets"]]
+    assert dps[0] > dps[1] > dps[2] > 0
+
+
+def test_planar_interface_relaxes_to_the_equilibrium_profile():
+    """A slab whose interfaces start twice as wide as at equilibrium (16% of the density gap
+    off the square-gradient profile) relaxes onto that profile (Eqs. (51)-(53)): within 2% of
+    the gap after 200,000 steps (the 400,000-step study: 0.6%)."""
+    from paper_1011_3582_amd import validation as V
+    res = V.profile(cap=200_000)
+    sys.stderr.write(f"[gpu-test] profile error {res['max_err_of_gap']:.2e} of the gap "
+                     f"(start {res['start_max_err_of_gap']:.2e})\n")
+    assert res["max_err_of_gap"] < 0.02 and res["max_err_of_gap"] < 0.2 * res["start_max_err_of_gap"]
+
+
+def test_quenched_slabs_move_onto_the_coexistence_curve():
+    """Slabs at 0.80, 0.86, 0.90 T_c started with the coexistence densities of T + 0.02 T_c
+    (Sec. 4.1's cooling steps) approach the Maxwell curve at their relaxed temperature (the
+    latent heat of condensation warms them) monotonically once the first 150,000 steps of sound
+    and heat transients have passed: the distance shrinks at every later 50,000-step check and
+    ends below 0.75 of its start after 300,000 steps (measured 0.47 and
+    0.59 at 0.80 and 0.86; the exchange of mass between the phases is slow, 10^6 steps bring it
+    to 0.1..0.4% of the gap)."""
+    from paper_1011_3582_amd import validation as V
+    res = V.coexistence(temps=(0.80, 0.86, 0.90), cap=300_000)
+    for i, r in enumerate(res["slabs"]):
+        sys.stderr.write(f"[gpu-test] T/Tc {r['T/Tc']:.2f}: distance {r['gap_error']:.2e} "
+                         f"(start {r['start_gap_error']:.2e}) of the gap\n")
+        hist = [h["gap_error"][i] for h in res["history"]][2:]
+        assert all(b <= a for a, b in zip(hist, hist[1:])), hist
+        assert r["gap_error"] < 0.75 * r["start_gap_error"]

@@ -11,7 +11,8 @@ roofline: the dominant kernel's algorithmic bytes per launch over its mean launc
 timed with HIP events on the stream it runs on, against 8 TB/s.
 batch: the 64-instance batched workload's throughput; time_to_equilibrium: steps and wall
 time of a batch of instances (compensated state) to the residual 1e-8.
-cpu_baseline: the FP64 oracle timed on this host on one step of the same workload.
+cpu_baseline: the FP64 oracle timed on this host's cores (a bounded sample of the same
+workload, plus the 64^2 and 256^2 configurations and a single-core figure).
 """
 from __future__ import annotations
 
@@ -189,19 +190,50 @@ def equilibrium_leg(F, W, dev, n, sizes, tol, cap, seed=3):
             "instances": per}
 
 
-def cpu_baseline(fields, params, nx, ny):
-    """FP64 oracle, as it stands, on one step of the same workload (single-threaded)."""
+def cpu_baseline(params, cores=None):
+    """The FP64 oracle, as it stands, timed on this host: the 1024 x 1024 quench (one warm-up
+    step, then 2 steps on all the host cores given to this process (at most 16, the CPU share
+    of one GPU) and 1 step on one core), and, on all cores, the 64 x 64 slab (30 steps after
+    one) and the 256 x 256 droplet (4 steps after one).  About 15 s of CPU work."""
     import numpy as np
+    import scipy
     from oracle import fftlb_oracle as O
+    from paper_1011_3582_amd import workloads as W
+    avail = len(os.sched_getaffinity(0))
+    cores = cores or min(16, avail)
     op = O.Params(dx=params.dx, dy=params.dy, dt=params.dt, tau=params.tau, K=params.K, H=params.H,
                   zeta=params.zeta, q=params.q, a=params.a, b=params.b, m=params.m)
-    f0 = O.feq(*fields.as_f64())
-    t0 = time.perf_counter()
-    O.step(f0, op)
-    dt = time.perf_counter() - t0
-    return {"value": 33.0 * nx * ny / dt, "unit": "site·velocity updates/s", "cores": 1,
-            "kind": "oracle", "sample": f"1 step of the {nx}x{ny} workload, FP64 NumPy/SciPy, "
-                                        f"{dt:.1f} s on the host CPU"}
+
+    def rate(fields, steps, workers, warmup):
+        f = O.feq(*fields.as_f64())
+        for _ in range(warmup):
+            f = O.step(f, op, workers=workers)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f = O.step(f, op, workers=workers)
+        dt = (time.perf_counter() - t0) / steps
+        return 33.0 * f.shape[1] * f.shape[2] / dt, dt
+
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    spin = W.spinodal_1024()
+    v_all, t_all = rate(spin, 2, cores, 1)
+    v_one, t_one = rate(spin, 1, 1, 0)
+    v64, t64 = rate(W.slab_64(), 30, cores, 1)
+    v256, t256 = rate(W.droplet_256(), 4, cores, 1)
+    return {"value": v_all, "unit": "site·velocity updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"2 steps of the 1024x1024 quench after 1 warm-up step, FP64 NumPy/SciPy (pocketfft, "
+                      f"{cores} workers): {t_all:.2f} s per step",
+            "single_core": {"value": v_one, "s_per_step": t_one},
+            "host": {"cpu": model, "cpus_available": avail, "numpy": np.__version__, "scipy": scipy.__version__},
+            "configs": {"slab 64x64 (30 steps)": {"value": v64, "s_per_step": t64},
+                        "droplet 256x256 (4 steps)": {"value": v256, "s_per_step": t256}}}
 
 
 def main():
@@ -350,8 +382,8 @@ def main():
     if equil is not None:
         out["time_to_equilibrium"] = equil
     if not args.no_cpu_baseline:
-        print("[bench] oracle CPU baseline (1 step)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(fields, params, nx, ny)
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(params)
     print(json.dumps(out))
 
 

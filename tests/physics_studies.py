@@ -1,0 +1,199 @@
+"""Physics studies of the FFT-LB step at the paper's equation-of-state constants (a = 9/8,
+b = 1/3, T_c = rho_c = 1): runs on the GPU through the library (paper_1011_3582_amd.validation),
+references from the van der Waals free energy (oracle/thermo.py).  Test infrastructure: the
+GPU tests in test_gpu_physics.py call shorter versions; the full studies write the summaries
+under profiles/.
+
+  laplace(): droplets of several radii at T = 0.95 for K = 1e-5, 7.5e-6, 5e-6 relax in one
+      batch; the pressure jump dP = P_in - P_out (P_in the mean bulk pressure over the sites
+      within R/2 of the centre, P_out over those beyond 3R/2, Sec. 4.2) against 1/R gives the
+      surface tension as the slope (Laplace law, Eq. (55)), compared with
+      sigma = K int (d rho/dz)^2 dz of the planar equilibrium interface (Eq. (56));
+  profile(): a relaxed planar slab against the equilibrium profile of the square-gradient
+      model (the interface integral of Eqs. (51)-(53));
+  coexistence(): slabs started with the densities of a temperature 0.02 T_c higher than
+      their own relax to the coexistence curve of the Maxwell construction (Sec. 4.1, the
+      temperature steps of the coexistence-curve study);
+  energy(): Delta e_T of the phase separation for k1..k4 and exact k, also measured with one
+      common (exact-gradient) energy definition.
+
+Usage (one MI355X): python tests/physics_studies.py laplace|profile|coexistence|energy [--cap N]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import thermo  # noqa: E402
+from paper_1011_3582_amd import fftlb as F  # noqa: E402
+from paper_1011_3582_amd import validation as V  # noqa: E402
+
+A, B = 9.0 / 8.0, 1.0 / 3.0
+log = V.log
+
+
+def laplace(n=192, radii=(24, 28, 32, 36, 40), Ks=(1e-5, 7.5e-6, 5e-6), t_ratio=0.95, tol=1e-9, cap=1_000_000):
+    T = t_ratio * 8 * A / (27 * B)
+    fields, params, keys = [], [], []
+    for K in Ks:
+        p = F.Params(a=A, b=B, K=K, precision=1)
+        for R in radii:
+            fields.append(V.droplet_from_profile(n, R, lambda s, K=K: thermo.planar_profile(s, T, A, B, K), T, p.dx))
+            params.append(p)
+            keys.append((K, R))
+    dx = F.Params().dx
+    history = []
+
+    def fits(relaxed):
+        out = {}
+        for K in Ks:
+            sel = [i for i, (k, _) in enumerate(keys) if k == K]
+            inv_r = [1.0 / (V.equimolar_radius(relaxed[i][0]) * dx) for i in sel]
+            dps = [V.pressure_jump(relaxed[i][0], relaxed[i][1], V.equimolar_radius(relaxed[i][0])) for i in sel]
+            out[K] = np.polyfit(inv_r, dps, 1)
+        return out
+
+    def monitor(steps, relaxed):
+        f = fits(relaxed)
+        history.append({"steps": steps, "sigma_fit": {f"{K:g}": float(f[K][0]) for K in Ks}})
+        log("  sigma fits " + ", ".join(f"{K:g}: {f[K][0]:.4e}" for K in Ks))
+
+    st, relaxed = V.relax(fields, params, tol, cap, label="laplace", monitor=monitor)
+    res = {"n": n, "T/Tc": t_ratio, "tol": tol, "cap": cap, "history": history, "K": {}}
+    for K in Ks:
+        inv_r, dps, rows = [], [], []
+        for (k, R0), (rho, Tf), steps, state, resid in zip(keys, relaxed, st["steps"], st["state"], st["residual"]):
+            if k != K:
+                continue
+            Req = V.equimolar_radius(rho)
+            dp = V.pressure_jump(rho, Tf, Req)
+            inv_r.append(1.0 / (Req * dx))
+            dps.append(dp)
+            rows.append({"R0": R0, "R_equimolar": Req, "dP": dp, "T_mean": float(Tf.mean()), "steps": int(steps),
+                         "state": int(state), "residual": float(resid)})
+        slope, intercept = np.polyfit(inv_r, dps, 1)
+        t_end = float(np.mean([r["T_mean"] for r in rows]))
+        sigma = thermo.surface_tension(t_end, A, B, K)
+        res["K"][f"{K:g}"] = {"sigma_fit": float(slope), "intercept": float(intercept), "sigma_theory": sigma,
+                              "rel_err": abs(slope - sigma) / sigma, "T_end": t_end, "droplets": rows}
+        log(f"K {K:g}: sigma fit {slope:.4e}, theory {sigma:.4e} (T {t_end:.5f}), intercept {intercept:.2e}")
+    return res
+
+
+def coexistence(temps=(0.80, 0.82, 0.84, 0.86, 0.88, 0.90, 0.92, 0.94, 0.96, 0.98), step=0.02, nx=256, ny=4,
+                tol=1e-10, cap=1_000_000):
+    """Slabs (liquid in nx/4 < x <= 3nx/4) at T, started from the coexistence densities of T + step
+    (tanh interfaces of the equilibrium width at T + step): the bulk densities must move to
+    the coexistence curve at the relaxed temperature."""
+    t_c = 8 * A / (27 * B)
+    fields, params = [], []
+    x = np.arange(nx, dtype=np.float64)
+    for tr in temps:
+        p = F.Params(a=A, b=B, precision=1)
+        hot = min(tr + step, 0.995) * t_c
+        dist = np.minimum(x - nx / 4.0, 3.0 * nx / 4.0 - x) * p.dx
+        fields.append(V.slab_start(nx, ny, thermo.planar_profile(dist, hot, A, B, p.K), tr * t_c))
+        params.append(p)
+    history = []
+
+    def monitor(steps, relaxed):
+        row = {"steps": steps, "gap_error": []}
+        for (rho, T) in relaxed:
+            rv, rl = V.bulk_densities(rho)
+            mv, ml = thermo.maxwell(float(T.mean()), A, B)
+            row["gap_error"].append(max(abs(rv - mv), abs(rl - ml)) / (ml - mv))
+        history.append(row)
+        log("  worst distance to the curve (of the gap): " + f"{max(row['gap_error']):.2e}")
+
+    st, relaxed = V.relax(fields, params, tol, cap, label="coexistence", monitor=monitor)
+    rows = []
+    for tr, (rho, T), steps, state in zip(temps, relaxed, st["steps"], st["state"]):
+        rv, rl = V.bulk_densities(rho)
+        t_end = float(T.mean())
+        mv, ml = thermo.maxwell(t_end, A, B)
+        sv, sl = thermo.maxwell(min(tr + step, 0.995) * t_c, A, B)
+        rows.append({"T/Tc": tr, "T_end": t_end, "rho_v": rv, "rho_l": rl, "maxwell_v": mv, "maxwell_l": ml,
+                     "start_v": sv, "start_l": sl, "gap_error": max(abs(rv - mv), abs(rl - ml)) / (ml - mv),
+                     "start_gap_error": max(abs(sv - mv), abs(sl - ml)) / (ml - mv), "steps": int(steps),
+                     "state": int(state)})
+    return {"nx": nx, "ny": ny, "step": step, "tol": tol, "cap": cap, "slabs": rows, "history": history}
+
+
+def profile(t_ratio=0.95, K=1e-5, nx=256, ny=4, start_width=2.0, tol=1e-10, cap=400_000):
+    """A slab started from the equilibrium profile stretched by start_width (a non-equilibrium
+    interface) relaxes; the relaxed profile is compared with the equilibrium profile of the
+    square-gradient model at the relaxed temperature, centred at the relaxed interface."""
+    t_c = 8 * A / (27 * B)
+    T = t_ratio * t_c
+    p = F.Params(a=A, b=B, K=K, precision=1)
+    x = np.arange(nx, dtype=np.float64)
+    dist = np.minimum(x - nx / 4.0, 3.0 * nx / 4.0 - x) * p.dx
+    start = thermo.planar_profile(dist / start_width, T, A, B, K)
+    st, relaxed = V.relax([V.slab_start(nx, ny, start, T)], [p], tol, cap, label="profile")
+    rho, Tf = relaxed[0]
+    prof = rho.mean(axis=0)
+    t_end = float(Tf.mean())
+    mv, ml = thermo.maxwell(t_end, A, B)
+    # interface positions: where the profile crosses the mid density (linear interpolation)
+    mid = 0.5 * (prof[:nx // 2].min() + prof[nx // 4: 3 * nx // 4].max())
+    i = int(np.argmax(prof[: nx // 2] > mid))
+    x0 = i - 1 + (mid - prof[i - 1]) / (prof[i] - prof[i - 1])
+    theory = thermo.planar_profile((x - x0) * p.dx, t_end, A, B, K)
+    win = slice(int(x0) - 24, int(x0) + 25)
+    err = np.abs(prof[win] - theory[win]).max() / (ml - mv)
+    start_err = np.abs(start[win] - thermo.planar_profile((x[win] - nx / 4) * p.dx, T, A, B, K)).max()
+    return {"T/Tc": t_ratio, "K": K, "nx": nx, "start_width_factor": start_width, "T_end": t_end,
+            "interface_x": x0, "max_err_of_gap": float(err), "start_max_err_of_gap": float(start_err / (ml - mv)),
+            "steps": int(st["steps"][0]), "state": int(st["state"][0]), "residual": float(st["residual"][0]),
+            "profile": [float(v) for v in prof[win]], "theory": [float(v) for v in theory[win]]}
+
+
+def energy(cap=500_000, orders=(1, 2, 3, 4, 0)):
+    """Delta e_T of the 128 x 128 phase separation (paper_1011_3582_amd.validation.energy) for each
+    window, as each run measures it (its own windowed gradient in K |grad rho|^2 / 2) and with one
+    common definition: the energy of Eq. (17) of the initial and final macroscopic fields with the
+    exact spectral gradient (oracle.fftlb_oracle.fields_energy, m = 0), so that the windows are
+    compared on the same quantity."""
+    from oracle import fftlb_oracle as O
+    res = V.energy(cap=cap, orders=orders, keep_fields=True)
+    kept = res.pop("fields")
+    n = res["n"]
+    p = F.Params(a=A, b=B)
+    area = n * n * p.dx * p.dy
+
+    def e_exact(fields):
+        op = O.Params(dx=p.dx, dy=p.dy, dt=p.dt, tau=p.tau, K=p.K, H=p.H, zeta=p.zeta, q=p.q, a=A, b=B, m=0)
+        return O.fields_energy(*fields, op) / area
+
+    e0 = e_exact(kept["initial"])
+    res["de_T_exact_gradient"] = {k: e_exact(v) - e0 for k, v in kept.items() if k != "initial"}
+    res["gradient_energy_final"] = {}
+    for k, (rho, ux, uy, T) in kept.items():
+        if k == "initial":
+            continue
+        op = O.Params(dx=p.dx, dy=p.dy, dt=p.dt, tau=p.tau, K=p.K, H=p.H, zeta=p.zeta, q=p.q, a=A, b=B, m=0)
+        D = O.Deriv(n, n, op)
+        res["gradient_energy_final"][k] = float((0.5 * p.K * (D.x(rho) ** 2 + D.y(rho) ** 2)).mean())
+    log("Delta e_T (own window): " + ", ".join(f"{k}: {v:.4e}" for k, v in res["final_de_T"].items()))
+    log("Delta e_T (exact gradient): " + ", ".join(f"{k}: {v:.4e}" for k, v in res["de_T_exact_gradient"].items()))
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy"])
+    ap.add_argument("--cap", type=int, default=1_000_000)
+    args = ap.parse_args()
+    fn = {"laplace": laplace, "coexistence": coexistence, "profile": profile, "energy": energy}[args.study]
+    print(json.dumps(fn(cap=args.cap)))
+
+
+if __name__ == "__main__":
+    main()

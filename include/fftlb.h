@@ -61,7 +61,10 @@ extern "C" {
  *  q             Prandtl-number parameter of C_q (Eq. (23)).
  *  a, b          van der Waals constants of P = rho T/(1 - b rho) - a rho^2 (Eq. (18)
  *                with the paper's 3/(3 - rho) and 9/8 written as 1/(1 - b rho) and a), >= 0.
- *  filter_order  0 = exact wavenumber k, 1..4 = windowed k_1..k_4 (Eqs. (44)-(47)).
+ *  filter_order  0 = exact wavenumber k, 1..4 = windowed k_1..k_4 (Eqs. (44)-(47)), 5 = the
+ *                second-order central difference of Sec. 3.1 for every derivative (the CD + CD
+ *                comparison scheme): on the periodic grid the stencil (g[J+1] - g[J-1]) / (2 d)
+ *                is the multiplier i sin(k d) / d, applied in the same spectral passes.
  *  precision     storage of the distribution: 0 = FP32; 1 = compensated, f = hi + lo with
  *                both parts FP32 (|lo| at most half an ulp of hi): each update adds its
  *                increment exactly, so increments below half an FP32 ulp of f, which an

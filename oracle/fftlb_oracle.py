@@ -165,17 +165,27 @@ def wavenumbers(n: int, delta: float) -> np.ndarray:
     return 2.0 * np.pi * np.fft.fftfreq(n, d=delta)
 
 
+# Derivative order m = CENTRAL_DIFFERENCE selects the second-order central difference of
+# Sec. 3.1, (g[J+1] - g[J-1]) / (2 delta), for every derivative (the CD + CD comparison scheme of
+# the paper's Fig. 2); the oracle applies it as that stencil in real space.
+CENTRAL_DIFFERENCE = 5
+
+
 def kappa(n: int, delta: float, m: int) -> np.ndarray:
     """Windowed wavenumber k_m of Eqs. (44)-(47); m = 0 is the exact k.
 
     k_m = (2/delta) sum_{j<m} c_j sin^(2j+1)(k delta / 2) with c = (1, 1/6, 3/40, 5/112).
     The Nyquist entry n' = -n/2 is zero (reading R1): it keeps the operator real.
+    m = CENTRAL_DIFFERENCE: the symbol of the central-difference stencil, sin(k delta) / delta
+    (the stencil multiplies the mode exp(i k x) by (e^(i k delta) - e^(-i k delta)) / (2 delta)).
     """
     if n % 2:
         raise ValueError("grid size must be even")
     k = wavenumbers(n, delta)
     if m == 0:
         kap = k.copy()
+    elif m == CENTRAL_DIFFERENCE:
+        kap = np.sin(k * delta) / delta
     else:
         if not 1 <= m <= len(ARCSIN_COEFFS):
             raise ValueError("window order m must be 0..4")
@@ -202,9 +212,12 @@ class Deriv:
     """The windowed-FFT first-derivative operators D_x, D_y on one periodic grid.
 
     D_alpha g = Re IFFT2[ i kappa_m(k_alpha) FFT2(g) ]  (Eq. (42) with k -> k_m; R4, R5).
+    With m = CENTRAL_DIFFERENCE: the stencil (g[J+1] - g[J-1]) / (2 delta) along alpha (Sec. 3.1).
     """
 
     def __init__(self, ny: int, nx: int, p: Params, workers=None):
+        self.cd = p.m == CENTRAL_DIFFERENCE
+        self.dx, self.dy = p.dx, p.dy
         self.kx = kappa(nx, p.dx, p.m)[None, :]
         self.ky = kappa(ny, p.dy, p.m)[:, None]
         self.workers = workers
@@ -216,9 +229,13 @@ class Deriv:
         return ifft2(G, self.workers).real
 
     def x(self, g):
+        if self.cd:
+            return (np.roll(g, -1, axis=1) - np.roll(g, 1, axis=1)) / (2.0 * self.dx)
         return self.from_spectrum(1j * self.kx * self.spectrum(g))
 
     def y(self, g):
+        if self.cd:
+            return (np.roll(g, -1, axis=0) - np.roll(g, 1, axis=0)) / (2.0 * self.dy)
         return self.from_spectrum(1j * self.ky * self.spectrum(g))
 
 
@@ -226,10 +243,14 @@ def convection(f, v, D: Deriv):
     """Convection term v_q . grad f_q by windowed FFT (Sec. 3.6, Fig. 3 flow chart).
 
     By linearity of Eq. (42), FT[v.grad f] = i (v_x k_x + v_y k_y) FT[f]; one
-    forward and one inverse transform per moving population.  C_0 = 0.
+    forward and one inverse transform per moving population.  C_0 = 0.  With the central
+    difference: v_x D_x f + v_y D_y f by the stencil (the conservative form of Sec. 3.1).
     """
     out = np.zeros_like(f)
     for q in range(1, f.shape[0]):
+        if D.cd:
+            out[q] = v[q, 0] * D.x(f[q]) + v[q, 1] * D.y(f[q])
+            continue
         mult = 1j * (v[q, 0] * D.kx + v[q, 1] * D.ky)
         out[q] = D.from_spectrum(mult * D.spectrum(f[q]))
     return out

@@ -90,7 +90,7 @@ bool config_ok(const fftlb_config* c) {
   if (!(c->tau > 0.0) || std::isnan(c->tau)) return false;
   if (!nonneg(c->K) || !nonneg(c->H) || !nonneg(c->a) || !nonneg(c->b)) return false;
   if (!std::isfinite(c->zeta) || !std::isfinite(c->q)) return false;
-  if (c->filter_order < 0 || c->filter_order > 4) return false;
+  if (c->filter_order < 0 || c->filter_order > 5) return false;
   if (c->precision != 0 && c->precision != 1) return false;
   return true;
 }
@@ -134,11 +134,14 @@ Layout make_layout(const fftlb_config& c) {
 }
 
 // Windowed wavenumber k_m (Eqs. (44)-(47)) of signed index n on a grid of N points with
-// spacing d; the Nyquist index -N/2 gets 0.  m = 0 is the exact wavenumber.
+// spacing d; the Nyquist index -N/2 gets 0.  m = 0 is the exact wavenumber; m = 5 the
+// symbol sin(k d) / d of the second-order central difference (g[J+1] - g[J-1]) / (2 d) of
+// Sec. 3.1: on a periodic grid that stencil is multiplication by i sin(k d) / d.
 __host__ __device__ double windowed_k(int n, int N, double d, int m) {
   if (2 * n == -N || 2 * n == N) return 0.0;
   const double k = 2.0 * M_PI * n / (N * d);
   if (m == 0) return k;
+  if (m == 5) return sin(2.0 * M_PI * (double)n / N) / d;
   const double c[4] = {1.0, 1.0 / 6.0, 3.0 / 40.0, 5.0 / 112.0};
   const double s = sin(M_PI * (double)n / N);
   double acc = 0.0, sp = s;

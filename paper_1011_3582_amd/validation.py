@@ -12,9 +12,12 @@ tests/physics_studies.py build the start fields from them and compare.
       the 128 x 128 phase separation of Sec. 3.5 (rho = 1 + 1e-3 noise, T = 0.85) for the
       windows k1..k4 and the exact wavenumber (Sec. 3.6, Fig. 8's comparison);
   triangle(): an equilateral triangular droplet with a sharp interface relaxes to a circle
-      (Sec. 4.2); the largest speed u^s_max(t) for k1..k4 (Fig. 19's comparison).
+      (Sec. 4.2); the largest speed u^s_max(t) for k1..k4 (Fig. 19's comparison);
+  sod(): the modified Sod shock tube of the ideal-gas special case (a = b = K = q = 0, so the
+      force term vanishes: the Watari-Tsutahara model), with the exact wavenumber and k1..k4
+      (Sec. 3.6, Figs. 6-7), on a periodic grid holding the tube and its mirror image.
 
-Run as `python -m paper_1011_3582_amd.validation energy|triangle`; each prints one JSON line.
+Run as `python -m paper_1011_3582_amd.validation energy|triangle|sod`; each prints one JSON line.
 """
 from __future__ import annotations
 
@@ -122,6 +125,11 @@ def equimolar_radius(rho):
     return math.sqrt((rho - rho_out).sum() / (math.pi * (rho_in - rho_out)))
 
 
+def window_name(m):
+    """Name of a derivative order: exact, k1..k4, CD (the central difference, order 5)."""
+    return "exact" if m == 0 else ("CD" if m == 5 else f"k{m}")
+
+
 def _chunked(b, n_inst, cap, every, record):
     """Advance a batch (nothing retires: tolerance 0) in chunks of `every` steps up to cap,
     calling record(steps) after each chunk; instances that go non-finite stop advancing."""
@@ -162,7 +170,7 @@ def energy(n=128, orders=(1, 2, 3, 4, 0), cap=200_000, every=2000, seed=0, dt=1e
             series[m].append({"t": steps * params[i].dt, "de_T": e - e0[m], "umax": g["umax"]})
         if steps % (10 * every) == 0:
             log(f"energy {time.perf_counter() - t0:.0f} s, {steps} steps: " + ", ".join(
-                f"k{m}: {series[m][-1]['de_T']}" for m in orders))
+                f"{window_name(m)}: {series[m][-1]['de_T']}" for m in orders))
 
     _chunked(b, len(orders), cap, every, record)
     kept = None
@@ -170,12 +178,12 @@ def energy(n=128, orders=(1, 2, 3, 4, 0), cap=200_000, every=2000, seed=0, dt=1e
         kept = {"initial": tuple(a.astype(np.float64) for a in (rho, z, z, T))}
         for i, m in enumerate(orders):
             outs, _ = b.instance(i).moments(globals_=False)
-            kept[f"k{m}" if m else "exact"] = tuple(o.cpu().numpy().astype(np.float64) for o in outs)
+            kept[window_name(m)] = tuple(o.cpu().numpy().astype(np.float64) for o in outs)
     b.close()
-    final = {f"k{m}" if m else "exact": series[m][-1]["de_T"] for m in orders}
+    final = {window_name(m): series[m][-1]["de_T"] for m in orders}
     return {"n": n, "T": 0.85, "a": A_PAPER, "b": B_PAPER, "noise": 1e-3, "seed": seed, "steps": cap, "dt": dt,
             "e_T0": e0, "final_de_T": final,
-            "series": {(f"k{m}" if m else "exact"): series[m] for m in orders},
+            "series": {(window_name(m)): series[m] for m in orders},
             **({"fields": kept} if keep_fields else {})}
 
 
@@ -215,16 +223,59 @@ def triangle(n=128, side=64.0, orders=(1, 2, 3, 4), cap=3_000_000, every=20_000,
         rr = _periodic_radius(n, cx, cy)
         mid = 0.5 * (1.46 + 0.58)
         ring = np.abs(r - mid) < 0.15
-        shapes[f"k{m}"] = {"radius_mean": float(rr[ring].mean()), "radius_std": float(rr[ring].std())}
+        shapes[window_name(m)] = {"radius_mean": float(rr[ring].mean()), "radius_std": float(rr[ring].std())}
     b.close()
     return {"n": n, "side": side, "T": 0.95, "K": 1e-5, "precision": precision, "steps": cap,
-            "final_umax": {f"k{m}": series[m][-1]["umax"] for m in orders}, "shape": shapes,
-            "series": {f"k{m}": series[m] for m in orders}}
+            "final_umax": {window_name(m): series[m][-1]["umax"] for m in orders}, "shape": shapes,
+            "series": {window_name(m): series[m] for m in orders}}
+
+
+def sod(nx=768, ny=4, orders=(0, 1, 2, 3, 4), steps=20_000, every=2000):
+    """The modified Sod tube (Sec. 3.6): (rho, u, T) = (1, 0, 1) for x <= 0 and (0.125, 0, 0.5)
+    for x > 0, dx = dy = 2.5e-3, dt = 1e-5, tau = 3e-4, a = b = K = q = 0, to t = 0.2.  The
+    periodic grid holds the tube (cell centres x_i = (i - nx/2 + 1/2) dx) and, across its ends,
+    the mirror problem; at t = 0.2 their waves have not met (|x| < 0.6 of the 0.96 half-width
+    is the tube's own solution).  Returns x and the row-averaged rho, u_x, T at t = 0.2 of every
+    window (None where the run became non-finite) and the largest speed over time."""
+    dx = 2.5e-3
+    x = (np.arange(nx) - nx / 2 + 0.5) * dx
+    left = x <= 0.0
+    rho = np.broadcast_to(np.where(left, 1.0, 0.125)[None, :], (ny, nx)).copy()
+    T = np.broadcast_to(np.where(left, 1.0, 0.5)[None, :], (ny, nx)).copy()
+    z = np.zeros_like(rho)
+    params = [F.Params(dx=dx, dy=dx, dt=1e-5, tau=3e-4, K=0.0, H=0.0, zeta=0.0, q=0.0, a=0.0, b=0.0, m=m)
+              for m in orders]
+    b = F.Batch([_tensors(rho, z, z, T) for _ in orders], params)
+    umax = {m: [] for m in orders}
+
+    def record(n):
+        for i, m in enumerate(orders):
+            try:
+                umax[m].append((n * 1e-5, b.instance(i).poll()["umax"]))
+            except F.FFTLBError:
+                umax[m].append((n * 1e-5, None))
+
+    _chunked(b, len(orders), steps, every, record)
+    prof = {}
+    for i, m in enumerate(orders):
+        name = window_name(m)
+        try:
+            b.instance(i).poll()
+        except F.FFTLBError:
+            prof[name] = None
+            continue
+        (r, ux, _, t), _ = b.instance(i).moments(globals_=False)
+        prof[name] = {"rho": r.cpu().numpy().astype(np.float64).mean(axis=0).tolist(),
+                      "u": ux.cpu().numpy().astype(np.float64).mean(axis=0).tolist(),
+                      "T": t.cpu().numpy().astype(np.float64).mean(axis=0).tolist()}
+    b.close()
+    return {"nx": nx, "dx": dx, "t": steps * 1e-5, "x": x.tolist(), "profiles": prof,
+            "umax": {(window_name(m)): v for m, v in umax.items()}}
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["energy", "triangle"])
+    ap.add_argument("study", choices=["energy", "triangle", "sod"])
     ap.add_argument("--cap", type=int, default=1_000_000)
     ap.add_argument("--dt", type=float, default=1e-5, help="time step of the energy study")
     ap.add_argument("--orders", default="1,2,3,4,0", help="window orders of the energy study (0: exact k)")
@@ -232,6 +283,8 @@ def main():
     if args.study == "energy":
         out = energy(cap=args.cap, dt=args.dt, orders=tuple(int(v) for v in args.orders.split(",")),
                      every=max(1000, int(round(2000 * 1e-5 / args.dt))))
+    elif args.study == "sod":
+        out = sod()
     else:
         out = triangle(cap=args.cap)
     print(json.dumps(out))

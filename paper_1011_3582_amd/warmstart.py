@@ -38,12 +38,13 @@ def _tensors(fl):
     return tuple(torch.from_numpy(np.ascontiguousarray(a)) for a in fl)
 
 
-def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0, energy_from=None):
+def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0, energy_from=None, trace=False):
     """Run instances (list of (rho, ux, uy, T) arrays) until each has retired or `cap` steps.
     Returns (status dict, [(rho, T) numpy of every instance], wall seconds); with probe > 0
     the status also holds "probe_residual", every instance's residual after `probe` steps.
     energy_from {i: j}: before the run, instance i takes the total energy of instance j's
-    initial state (fftlb_match_energy)."""
+    initial state (fftlb_match_energy).  trace: the status also holds "trace", the steps and
+    every instance's residual after each chunk."""
     b = F.Batch([_tensors(f) for f in fields])
     for i, j in (energy_from or {}).items():
         b.instance(i).match_energy(b.instance(j).poll()["energy"])
@@ -51,11 +52,14 @@ def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0, energy_from=None
     t0 = time.perf_counter()
     done = 0
     probe_res = None
+    hist = []
     while done < cap:
         n = min(probe if (probe and done == 0) else chunk, cap - done)
         b.run(tol=tol, consecutive=3, poll_every=poll, max_steps=n, allow_unstable=True)
         done += n
         st = b.status()
+        if trace:
+            hist.append((done, st["residual"].copy()))
         if probe and probe_res is None:
             probe_res = st["residual"].copy()
         log(f"  {time.perf_counter() - t0:.0f} s, {done} steps: {int((st['state'] != 0).sum())}/{len(fields)} retired")
@@ -66,6 +70,8 @@ def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0, energy_from=None
     st = b.status()
     if probe_res is not None:
         st["probe_residual"] = probe_res
+    if trace:
+        st["trace"] = hist
     out = []
     for i in range(len(fields)):
         (rho, _, _, T), _ = b.instance(i).moments(globals_=False)
@@ -122,9 +128,22 @@ def train(x, y, epochs, batch, lr, seed=0, net=None):
     return net, hist, time.perf_counter() - t0
 
 
-def evaluate(net, n, seed, size, tol, cap, probe=1000):
+def decay_fit(steps, resid, lo, hi):
+    """Exponential fit r = r0 exp(-lam s) of a residual history over the points with
+    lo < r < hi (the tail before retirement): (r0, lam) or None with fewer than 3 points."""
+    sel = [(s, r) for s, r in zip(steps, resid) if lo < r < hi]
+    if len(sel) < 3:
+        return None
+    s_, r_ = np.array(sel, dtype=np.float64).T
+    slope, icpt = np.polyfit(s_, np.log(r_), 1)
+    return float(np.exp(icpt)), float(-slope)
+
+
+def evaluate(net, n, seed, size, tol, cap, probe=1000, chunk=5000):
     """Cold and warm runs of n held-out instances in one batch; steps to tolerance, and the
-    best-of-two start decided by the residuals after `probe` steps."""
+    best-of-two start decided by the residuals after `probe` steps.  Also, per instance: the
+    RMS distance of each start from the relaxed cold field (normalised by rho_c) and the
+    exponential decay of each run's residual (fitted between 10 tol and 1e-5)."""
     inst = instances(n, seed, size)
     cold, warm, infer = [], [], []
     for kind, Nn, t, R, f in inst:
@@ -138,7 +157,8 @@ def evaluate(net, n, seed, size, tol, cap, probe=1000):
         r, Tn = rho.cpu().numpy(), T.cpu().numpy()
         warm.append((r, np.zeros_like(r), np.zeros_like(r), Tn))
     # the warm starts take the total energy of their cold starts (mass is kept by the transform)
-    st, relaxed, wall = run_batch(cold + warm, tol, cap, probe=probe, energy_from={n + k: k for k in range(n)})
+    st, relaxed, wall = run_batch(cold + warm, tol, cap, chunk=chunk, probe=probe,
+                                  energy_from={n + k: k for k in range(n)}, trace=True)
     s = st["steps_to_tol"]
     sc, sw = s[:n], s[n:]
     ok = (sc > 0) & (sw > 0)
@@ -150,6 +170,12 @@ def evaluate(net, n, seed, size, tol, cap, probe=1000):
     sb = np.where(sch > 0, sch + probe, -1)
     # relaxed states of the two starts of each instance: how far apart they end
     diff = [float(np.abs(relaxed[i][0] - relaxed[n + i][0]).max()) for i in range(n)]
+    # distance of each start from the relaxed cold field, and the residual decay of each run
+    err_cold = [float(np.sqrt(np.mean((cold[i][0] - relaxed[i][0]) ** 2)) / W.RHO_CRIT) for i in range(n)]
+    err_warm = [float(np.sqrt(np.mean((warm[i][0] - relaxed[i][0]) ** 2)) / W.RHO_CRIT) for i in range(n)]
+    tsteps = [h[0] for h in st["trace"]]
+    fits = [decay_fit(tsteps, [h[1][i] for h in st["trace"]], 10 * tol, 1e-5) for i in range(2 * n)]
+    kinds = [(k, float(t), float(R)) for k, _, t, R, _ in inst]
     return {"instances": n, "tol": tol, "cap": cap, "both_converged": int(ok.sum()),
             "cold_capped": int((sc < 0).sum()), "warm_capped": int((sw < 0).sum()),
             "steps_cold_median": float(np.median(np.where(sc > 0, sc, cap))),
@@ -161,14 +187,16 @@ def evaluate(net, n, seed, size, tol, cap, probe=1000):
             "inference_ms_median": 1e3 * float(np.median(infer)),
             "final_rho_maxdiff_median": float(np.median(diff)),
             "steps_cold": [int(v) for v in sc], "steps_warm": [int(v) for v in sw],
-            "steps_best": [int(v) for v in sb]}
+            "steps_best": [int(v) for v in sb], "rms_start_error_cold": err_cold, "rms_start_error_warm": err_warm,
+            "decay_cold": fits[:n], "decay_warm": fits[n:], "instances_kind_T_R": kinds,
+            "trace_steps": tsteps, "trace_residual": [[float(v) for v in h[1]] for h in st["trace"]]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--train", type=int, default=128, help="training instances")
-    ap.add_argument("--eval", type=int, default=32, help="held-out instances")
+    ap.add_argument("--eval", type=int, default=64, help="held-out instances")
     ap.add_argument("--data-tol", type=float, default=1e-6)
     ap.add_argument("--data-cap", type=int, default=100000)
     ap.add_argument("--tol", type=float, default=3e-7)

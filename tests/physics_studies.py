@@ -186,11 +186,49 @@ def energy(cap=500_000, orders=(1, 2, 3, 4, 0)):
     return res
 
 
+def sod():
+    """The modified Sod tube (paper_1011_3582_amd.validation.sod) against the exact Riemann
+    solution of the gamma = 2 ideal gas at t = 0.2: for each window, the L1 errors of rho, u,
+    p = rho T and T over |x| < 0.6, and the overshoot of T above its exact value in the
+    shocked region (the Gibbs oscillations of Fig. 7)."""
+    from oracle import riemann
+    res = V.sod()
+    x = np.array(res["x"])
+    win = np.abs(x) < 0.6
+    ex_rho, ex_u, ex_p = riemann.sample(x[win] / res["t"], 1.0, 0.0, 1.0, 0.125, 0.0, 0.0625, 2.0)
+    ex_T = ex_p / ex_rho
+    p_s, u_s = riemann.star_state(1.0, 0.0, 1.0, 0.125, 0.0, 0.0625, 2.0)
+    out = {"t": res["t"], "star": {"p": p_s, "u": u_s}, "windows": {}}
+    dxw = res["dx"]
+    for name, prof in res["profiles"].items():
+        if prof is None:
+            out["windows"][name] = {"unstable": True}
+            continue
+        r, u, T = (np.array(prof[k])[win] for k in ("rho", "u", "T"))
+        p = r * T
+        l1 = lambda a, b: float(np.sum(np.abs(a - b)) * dxw)
+        shocked = (x[win] > u_s * res["t"] + 0.02) & (ex_rho > 0.2)    # between contact and shock
+        out["windows"][name] = {"L1_rho": l1(r, ex_rho), "L1_u": l1(u, ex_u), "L1_p": l1(p, ex_p),
+                                "L1_T": l1(T, ex_T),
+                                "T_overshoot": float((T[shocked] - ex_T[shocked]).max()) if shocked.any() else None,
+                                "umax_final": res["umax"][name][-1][1]}
+        log(f"sod {name}: L1 rho {out['windows'][name]['L1_rho']:.3e}, u {out['windows'][name]['L1_u']:.3e}, "
+            f"T overshoot {out['windows'][name]['T_overshoot']}")
+    out["x"] = x[win].tolist()
+    out["exact"] = {"rho": ex_rho.tolist(), "u": ex_u.tolist(), "T": ex_T.tolist()}
+    out["profiles"] = {k: ({q: np.array(v[q])[win].tolist() for q in v} if v else None)
+                       for k, v in res["profiles"].items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy"])
+    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod"])
     ap.add_argument("--cap", type=int, default=1_000_000)
     args = ap.parse_args()
+    if args.study == "sod":
+        print(json.dumps(sod()))
+        return
     fn = {"laplace": laplace, "coexistence": coexistence, "profile": profile, "energy": energy}[args.study]
     print(json.dumps(fn(cap=args.cap)))
 

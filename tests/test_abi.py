@@ -37,7 +37,7 @@ def test_workspace_bytes_valid(nx, ny):
     dict(nx=80), dict(nx=24), dict(ny=1536), dict(nx=4), dict(ny=2), dict(nx=4096), dict(ny=3000),
     dict(nx=8, ny=8), dict(nx=48, ny=9),
     dict(dt=0.0), dict(dx=-1.0), dict(tau=0.0), dict(tau=math.nan), dict(K=-1.0), dict(b=-0.1),
-    dict(filter_order=5), dict(filter_order=-1), dict(precision=2), dict(precision=-1), dict(q=math.inf),
+    dict(filter_order=6), dict(filter_order=-1), dict(precision=2), dict(precision=-1), dict(q=math.inf),
 ])
 def test_invalid_configs_rejected(change):
     cfg = F.Params().config(64, 64)

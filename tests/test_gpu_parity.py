@@ -101,7 +101,7 @@ def test_init_is_equilibrium(ny, nx):
 
 
 @pytest.mark.parametrize("ny,nx", SHAPES + [(256, 256)])
-@pytest.mark.parametrize("m", [0, 1, 4])
+@pytest.mark.parametrize("m", [0, 1, 4, 5])
 def test_windowed_derivatives(ny, nx, m):
     rng = np.random.default_rng(ny * 7 + nx + m)
     fld = _fields_for(ny, nx)
@@ -186,9 +186,11 @@ def _c15(gpu_state, ora_state):
                 ux=float(np.abs(gu - ou).max() / vt), uy=float(np.abs(gv - ov).max() / vt))
 
 
-@pytest.mark.parametrize("m", [0, 1, 2, 3])
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 5])
 def test_one_step_other_window_orders(m):
-    """The whole step with the exact wavenumber (m = 0) and the k1..k3 windows (Eqs. (44)-(46))."""
+    """The whole step with the exact wavenumber (m = 0), the k1..k3 windows (Eqs. (44)-(46)) and
+    the second-order central difference (m = 5, Sec. 3.1; the oracle applies it as the stencil
+    in real space, the HIP path as its symbol in the spectral passes)."""
     fld = W.smooth_random(64, 64, seed=11, T0=1.2)
     p = F.Params(m=m)
     with solver(fld, p) as s:

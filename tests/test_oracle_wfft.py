@@ -163,3 +163,46 @@ def test_k4_reaches_round_off_on_sin():
     """Sec. 3.6 (Fig. 5 discussion): with k_4 the error of d/dx sin(x) at N = 128 is round-off."""
     assert _sin_error(128, 4) < 1e-13
     assert _sin_error(128, 1) > 1e-5
+
+
+def test_central_difference_of_a_sinusoid_and_its_order():
+    """The central-difference operator (m = 5, Sec. 3.1): on sin(p x) it gives
+    sin(p dx)/dx cos(p x) exactly, the symbol kappa returns; its error is -dx^2/6 f''' to
+    leading order (second order: halving dx divides it by 4)."""
+    from oracle import fftlb_oracle as O
+    errs = []
+    for n in (64, 128):
+        L = 2 * np.pi
+        dx = L / n
+        p = O.Params(dx=dx, dy=dx, dt=1e-5, tau=1e-2, K=0.0, H=0.0, zeta=0.0, q=0.0, a=0.0, b=0.0,
+                     m=O.CENTRAL_DIFFERENCE)
+        D = O.Deriv(8, n, p)
+        x = np.arange(n) * dx
+        g = np.sin(3 * x + 0.2)[None, :].repeat(8, 0)
+        got = D.x(g)
+        assert np.abs(got - np.sin(3 * dx) / dx * np.cos(3 * x + 0.2)).max() < 1e-12
+        assert O.kappa(n, dx, O.CENTRAL_DIFFERENCE)[3] == pytest.approx(np.sin(3 * dx) / dx, rel=1e-14)
+        errs.append(np.abs(got - 3 * np.cos(3 * x + 0.2)).max())
+        # leading error -dx^2/6 f''' = -dx^2/6 * (-27 cos) at this resolution
+        assert errs[-1] == pytest.approx(27 * dx * dx / 6 * 1.0, rel=0.02)
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.01)
+
+
+def test_central_difference_convection_equals_its_symbol():
+    """The stencil convection of the oracle (real space) equals the spectral product with
+    the central-difference symbol i (v_x sin(k_x dx)/dx + v_y sin(k_y dy)/dy): the two routes
+    agree to round-off (the HIP path uses the spectral one)."""
+    from oracle import fftlb_oracle as O
+    rng = np.random.default_rng(5)
+    ny, nx = 16, 24
+    p = O.Params(dx=1 / 256, dy=1 / 200, dt=1e-5, tau=1e-2, K=1e-5, H=0.0, zeta=0.0, q=-0.004, a=2.0, b=0.4,
+                 m=O.CENTRAL_DIFFERENCE)
+    f = rng.uniform(0.1, 1.0, (33, ny, nx))
+    D = O.Deriv(ny, nx, p)
+    v = O.velocities()
+    got = O.convection(f, v, D)
+    kx = O.kappa(nx, p.dx, p.m)[None, :]
+    ky = O.kappa(ny, p.dy, p.m)[:, None]
+    for q in range(1, 33):
+        ref = np.fft.ifft2(1j * (v[q, 0] * kx + v[q, 1] * ky) * np.fft.fft2(f[q])).real
+        assert np.abs(got[q] - ref).max() < 1e-12 * np.abs(ref).max() + 1e-12

@@ -52,15 +52,17 @@ def test_sod_tube_parity_with_oracle(m):
 
 def test_sod_tube_against_the_exact_solution():
     """At t = 0.2 (20,000 steps) the k1 run follows the exact solution (the paper's Fig. 6):
-    L1 errors over |x| < 0.6 below 1.5e-2 in rho, u, p and T (the discontinuities are spread
-    over a few cells).  The higher windows keep more of the Gibbs oscillations at the shock
-    (Fig. 7): their temperature overshoot behind the shock exceeds k1's, or the run blows up."""
+    L1 errors over |x| < 0.6 below 1e-2 in rho, u, p and T (measured 2.3e-3..8.4e-3: the
+    discontinuities are spread over a few cells).  The higher windows keep grid-scale Gibbs
+    oscillations behind the shock (Fig. 7): k1 has the smallest total variation in excess of
+    the exact solution's (measured in T: k1 0.86, k2..k4 1.9..2.0, exact k 1.1)."""
     import physics_studies as S
     res = S.sod()
     k1 = res["windows"]["k1"]
     sys.stderr.write(f"[sod] {res['windows']}\n")
     for q in ("L1_rho", "L1_u", "L1_p", "L1_T"):
-        assert k1[q] < 1.5e-2, (q, k1[q])
-    for name in ("k3", "k4", "exact"):
+        assert k1[q] < 1e-2, (q, k1[q])
+    for name in ("k2", "k3", "k4", "exact"):
         w = res["windows"][name]
-        assert w.get("unstable") or w["T_overshoot"] > k1["T_overshoot"], (name, w)
+        assert w.get("unstable") or w["TV_excess_T"] > k1["TV_excess_T"], (name, w)
+        assert w.get("unstable") or w["L1_rho"] < 1e-2, (name, w)

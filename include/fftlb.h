@@ -70,7 +70,16 @@ extern "C" {
  *                increment exactly, so increments below half an FP32 ulp of f, which an
  *                FP32 state loses, still accumulate (long relaxations to small residuals);
  *                33 more planes of workspace and of collide traffic.  Arithmetic is FP32
- *                in both (the transforms and the convection term take hi). */
+ *                in both (the transforms and the convection term take hi).
+ *  convection    scheme of the convection term v.grad f: 0 = the derivative operator of
+ *                filter_order (windowed FFT, or CD with filter_order 5); 1 = Lax-Wendroff
+ *                (Sec. 3.1, Eq. (ML-)); 2 = MLW1, LW plus the dispersion correction R3 (Eq. (R3));
+ *                3 = MLW2, LW plus R3 and the dissipation correction R4 (Eq. (R4=)).  The
+ *                one-dimensional stencils act along x and along y and their updates add; the
+ *                CFL numbers are c = v_x dt/dx and v_y dt/dy.  On the periodic grid every such
+ *                stencil is a multiplication of the spectrum, applied in a column pass over all
+ *                32 moving populations (a step then runs five kernels instead of four).  With
+ *                filter_order 5 these are the paper's LW + CD, MLW1 + CD and MLW2 + CD schemes. */
 typedef struct fftlb_config {
   int32_t nx, ny;
   double dx, dy, dt;
@@ -78,6 +87,7 @@ typedef struct fftlb_config {
   double a, b;
   int32_t filter_order;
   int32_t precision;
+  int32_t convection;
 } fftlb_config;
 
 typedef struct fftlb_handle fftlb_handle;

@@ -57,7 +57,9 @@ class Params:
 
     The paper's values are dx = dy = 1/256, dt = 1e-5, tau = 1e-2, K = 1e-5,
     H = 0, zeta = 0, q = -0.004 and the k4 window (m = 4); its EOS is a = 9/8,
-    b = 1/3.  m = 0 selects the exact wavenumber k.
+    b = 1/3.  m = 0 selects the exact wavenumber k.  conv = 0 takes the convection term
+    with the derivative operator of m; LAX_WENDROFF, MLW1 or MLW2 with that
+    finite-difference scheme of Sec. 3.1.
     """
     dx: float = 1.0 / 256.0
     dy: float = 1.0 / 256.0
@@ -70,6 +72,7 @@ class Params:
     a: float = 9.0 / 8.0
     b: float = 1.0 / 3.0
     m: int = 4
+    conv: int = 0
 
 
 def critical_point(a: float, b: float):
@@ -239,15 +242,52 @@ class Deriv:
         return self.from_spectrum(1j * self.ky * self.spectrum(g))
 
 
-def convection(f, v, D: Deriv):
+# Sec. 3.1: finite-difference schemes of the convection term, compared in the paper's
+# Fig. 2 (with the central difference for the force): Lax-Wendroff, Eq. (ML-); MLW1 adds the
+# discretised dispersion term R3, Eq. (R3); MLW2 adds R3 and the dissipation term R4, Eq. (R4=).
+LAX_WENDROFF, MLW1, MLW2 = 1, 2, 3
+
+
+def fd_convection_update(g, c, axis, scheme):
+    """Change of g at every node J in one forward-Euler step from the convection along one
+    axis, as the schemes of Sec. 3.1 write it, with CFL number c = v_alpha dt / d_alpha and
+    the periodic neighbours J-2..J+2 along `axis`:
+      LW  (Eq. (ML-)): -(c/2)(g[J+1] - g[J-1]) + (c^2/2)(g[J+1] - 2 g[J] + g[J-1])
+      R3  (Eq. (R3)):  c (1 - c^2)/12 (g[J+2] - 2 g[J+1] + 2 g[J-1] - g[J-2])     (MLW1, MLW2)
+      R4  (Eq. (R4=)): c^2 (1 - c^2)/8 (g[J+2] - 4 g[J+1] + 6 g[J] - 4 g[J-1] + g[J-2])  (MLW2)
+    """
+    if scheme not in (LAX_WENDROFF, MLW1, MLW2):
+        raise ValueError("scheme must be LAX_WENDROFF, MLW1 or MLW2")
+    gp1 = np.roll(g, -1, axis=axis)   # g[J+1] at J
+    gm1 = np.roll(g, 1, axis=axis)    # g[J-1]
+    du = -0.5 * c * (gp1 - gm1) + 0.5 * c * c * (gp1 - 2.0 * g + gm1)
+    if scheme >= MLW1:
+        gp2 = np.roll(g, -2, axis=axis)
+        gm2 = np.roll(g, 2, axis=axis)
+        du = du + c * (1.0 - c * c) / 12.0 * (gp2 - 2.0 * gp1 + 2.0 * gm1 - gm2)
+        if scheme >= MLW2:
+            du = du + c * c * (1.0 - c * c) / 8.0 * (gp2 - 4.0 * gp1 + 6.0 * g - 4.0 * gm1 + gm2)
+    return du
+
+
+def convection(f, v, D: Deriv, p: Params | None = None):
     """Convection term v_q . grad f_q by windowed FFT (Sec. 3.6, Fig. 3 flow chart).
 
     By linearity of Eq. (42), FT[v.grad f] = i (v_x k_x + v_y k_y) FT[f]; one
     forward and one inverse transform per moving population.  C_0 = 0.  With the central
     difference: v_x D_x f + v_y D_y f by the stencil (the conservative form of Sec. 3.1).
+    With a finite-difference scheme (p.conv): the updates of fd_convection_update along x
+    (c = v_x dt/dx) and along y (c = v_y dt/dy) added (reading R23), returned as the term C
+    that the step subtracts times dt: C = -(du_x + du_y) / dt.
     """
     out = np.zeros_like(f)
+    scheme = p.conv if p is not None else 0
     for q in range(1, f.shape[0]):
+        if scheme:
+            du = (fd_convection_update(f[q], v[q, 0] * p.dt / p.dx, 1, scheme)
+                  + fd_convection_update(f[q], v[q, 1] * p.dt / p.dy, 0, scheme))
+            out[q] = -du / p.dt
+            continue
         if D.cd:
             out[q] = v[q, 0] * D.x(f[q]) + v[q, 1] * D.y(f[q])
             continue
@@ -375,7 +415,7 @@ def step_parts(f, p: Params, workers=None) -> StepParts:
     rho, ux, uy, T = moments(f)
     fc = force_coefficients(rho, ux, uy, T, p, D)
     fe = feq(rho, ux, uy, T)
-    conv = convection(f, velocities(), D)
+    conv = convection(f, velocities(), D, p)
     I = force_term(fe, ux, uy, fc)
     relax = 0.0 if math.isinf(p.tau) else p.dt / p.tau
     f_next = f - p.dt * conv - relax * (f - fe) + p.dt * I

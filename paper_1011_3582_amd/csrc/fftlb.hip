@@ -92,11 +92,12 @@ bool config_ok(const fftlb_config* c) {
   if (!std::isfinite(c->zeta) || !std::isfinite(c->q)) return false;
   if (c->filter_order < 0 || c->filter_order > 5) return false;
   if (c->precision != 0 && c->precision != 1) return false;
+  if (c->convection < 0 || c->convection > 3) return false;
   return true;
 }
 
 struct Layout {
-  size_t f, flo, sf, spec, macro, cpl, twx, twy, kx, ky, pd, pf, gl, total;
+  size_t f, flo, sf, spec, macro, cpl, twx, twy, kx, ky, scx, scy, pd, pf, gl, total;
 };
 
 // Planes of the spectral block (contiguous, so that a column pass addresses them by index).
@@ -126,6 +127,8 @@ Layout make_layout(const fftlb_config& c) {
   L.twy = take((size_t)ny * sizeof(float2));
   L.kx = take((size_t)(nx / 2) * sizeof(float));
   L.ky = take((size_t)ny * sizeof(float));
+  L.scx = take((size_t)(nx / 2) * sizeof(float2));
+  L.scy = take((size_t)ny * sizeof(float2));
   L.pd = take(nblk * 6 * sizeof(double));
   L.pf = take(nblk * 2 * sizeof(float));
   L.gl = take(FFTLB_NGLOBALS * sizeof(double));
@@ -287,6 +290,16 @@ int col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, in
   return FFTLB_EINVAL;
 }
 
+int col_conv_scheme(const StepLaunch& L, hipStream_t s) {
+  switch (L.ny) {
+#define X(n) \
+  case n: return launch_col_conv_scheme<n>(L, s);
+    FFTLB_FOR_COL_SIZES(X)
+#undef X
+  }
+  return FFTLB_EINVAL;
+}
+
 // Real plane -> packed row spectra, and back, for an instance's grid, twiddles and k_x table.
 int rows_forward_real(const Inst& I, int nx, const float* a, float2* sa, hipStream_t s) {
   switch (nx) {
@@ -309,7 +322,9 @@ int rows_inverse_real(const Inst& I, int nx, const float2* sa, float* a, hipStre
 }
 
 StepLaunch single_launch(const fftlb_handle* h, const ColPlan& plan) {
-  return StepLaunch{&h->self, nullptr, 1, nullptr, h->nx, h->ny, h->tw, h->I.nblk, plan, h->cfg.precision == 1};
+  return StepLaunch{&h->self, nullptr, 1,    nullptr,
+                    h->nx,    h->ny,   h->tw, h->I.nblk,
+                    plan,     h->cfg.precision == 1, h->cfg.convection};
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +343,15 @@ enum : int { ST_CONV_S1 = 0, ST_S2_ROWS = 1, ST_S2_COLS = 2, ST_COLLIDE = 3, ST_
 // best, and 16..20 are within 1 us of each other.
 constexpr int kConvSplit = 16;
 
+// With a finite-difference convection scheme the derivative column passes run by themselves
+// and the scheme's column pass of all 32 moving populations follows the stage-1 pass.
 int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
+  if (L.scheme) {
+    switch (stage) {
+      case ST_CONV_S1: RC_TRY(col_multi(L, kStage1, 3, s)); return col_conv_scheme(L, s);
+      case ST_S2_COLS: return col_multi(L, kStage2, 2, s);
+    }
+  }
   switch (stage) {
     case ST_CONV_S1: return col_conv_multi(L, kStage1, 3, 0, kConvSplit, s);
     case ST_S2_ROWS: return rows(L, RK_STAGE2, Inputs{}, s);
@@ -600,6 +623,7 @@ struct fftlb_batch {
   struct Group {
     int nx, ny, tw, nblk;
     bool comp;
+    int scheme;
     ColPlan plan;
     std::vector<int> members;  // all instances of this size
   };
@@ -663,7 +687,7 @@ void batch_launches(fftlb_batch* b, std::vector<std::vector<int>>* ids, std::vec
     const auto& g = b->groups[k];
     if ((*ids)[k].empty()) continue;
     out->push_back(StepLaunch{(*ptrs)[k].data(), (*ids)[k].data(), (int)(*ids)[k].size(), b->st.state, g.nx, g.ny,
-                              g.tw, g.nblk, g.plan, g.comp});
+                              g.tw, g.nblk, g.plan, g.comp, g.scheme});
   }
 }
 
@@ -794,6 +818,22 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   M.b = (float)cfg->b;
   M.scale = (float)(1.0 / ((double)h->nx * h->ny));
 
+  // convection by a finite-difference scheme: LW (1), MLW1 = LW + R3 (2), MLW2 = LW + R3 + R4 (3)
+  I.scheme = cfg->convection;
+  SchemeInst& S = I.sch;
+  S.spec = P.sf;
+  S.twy = I.twy;
+  S.scx = reinterpret_cast<const float2*>(ws + L.scx);
+  S.scy = reinterpret_cast<const float2*>(ws + L.scy);
+  S.nx = h->nx;
+  S.tw = h->tw;
+  S.id = 0;
+  S.cfx = (float)(cfg->dt / cfg->dx);
+  S.cfy = (float)(cfg->dt / cfg->dy);
+  S.r3 = cfg->convection >= 2 ? 1.0f : 0.0f;
+  S.r4 = cfg->convection >= 3 ? 1.0f : 0.0f;
+  S.sdt = (float)(1.0 / ((double)h->nx * h->ny * cfg->dt));
+
   // Twiddles exp(-2 pi i j/N) and windowed wavenumbers, in FP64, stored FP32.
   std::vector<float2> twx(h->nx), twy(h->ny);
   for (int j = 0; j < h->nx; ++j)
@@ -804,6 +844,18 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   for (int k = 0; k < h->nx / 2; ++k) kx[k] = (float)windowed_k(k, h->nx, cfg->dx, cfg->filter_order);
   for (int k = 0; k < h->ny; ++k)
     ky[k] = (float)windowed_k(k < h->ny / 2 ? k : k - h->ny, h->ny, cfg->dy, cfg->filter_order);
+  // (sin theta, cos theta - 1) of the finite-difference schemes, theta = 2 pi k / N of the
+  // signed index (cos theta - 1 = -2 sin^2(theta / 2) keeps small angles accurate); exactly
+  // 0 for the sine at the Nyquist index, so that the multiplier is real there.
+  auto sc = [](int k, int N) {
+    const int ks = 2 * k < N ? k : k - N;
+    const double sh = std::sin(M_PI * ks / N);
+    const float sn = 2 * ks == -N ? 0.0f : (float)std::sin(2.0 * M_PI * ks / N);
+    return make_float2(sn, (float)(-2.0 * sh * sh));
+  };
+  std::vector<float2> scx(h->nx / 2), scy(h->ny);
+  for (int k = 0; k < h->nx / 2; ++k) scx[k] = sc(k, h->nx);
+  for (int k = 0; k < h->ny; ++k) scy[k] = sc(k, h->ny);
 
   int rc = FFTLB_OK;
   {
@@ -812,7 +864,9 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
     if ((e = hipMemcpyAsync(ws + L.twx, twx.data(), twx.size() * sizeof(float2), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(ws + L.twy, twy.data(), twy.size() * sizeof(float2), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(ws + L.kx, kx.data(), kx.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(ws + L.ky, ky.data(), ky.size() * sizeof(float), hipMemcpyHostToDevice, s))) {
+        (e = hipMemcpyAsync(ws + L.ky, ky.data(), ky.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(ws + L.scx, scx.data(), scx.size() * sizeof(float2), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(ws + L.scy, scy.data(), scy.size() * sizeof(float2), hipMemcpyHostToDevice, s))) {
       set_error("table upload", e);
       delete h;
       return FFTLB_EHIP;
@@ -1140,10 +1194,12 @@ int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, siz
     b->inst.push_back(h);
     auto g = std::find_if(b->groups.begin(), b->groups.end(),
                           [&](const fftlb_batch::Group& gg) {
-                            return gg.nx == c.nx && gg.ny == c.ny && gg.comp == (c.precision == 1);
+                            return gg.nx == c.nx && gg.ny == c.ny && gg.comp == (c.precision == 1) &&
+                                   gg.scheme == c.convection;
                           });
     if (g == b->groups.end()) {
-      b->groups.push_back(fftlb_batch::Group{c.nx, c.ny, h->tw, h->I.nblk, c.precision == 1, h->plan, {}});
+      b->groups.push_back(
+          fftlb_batch::Group{c.nx, c.ny, h->tw, h->I.nblk, c.precision == 1, c.convection, h->plan, {}});
       g = b->groups.end() - 1;
     }
     g->members.push_back(i);

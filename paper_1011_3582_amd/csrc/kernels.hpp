@@ -629,6 +629,98 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
 }
 
 
+// Convection by one of the finite-difference schemes of Sec. 3.1 (Lax-Wendroff, Eq. (ML-);
+// MLW1 = LW + R3, MLW2 = LW + R3 + R4, Eqs. (R3), (R4=)), applied per axis and summed.  On
+// the periodic grid each stencil is a multiplication of the spectrum, so the scheme's
+// update of f is applied exactly (up to rounding) in the same column passes: with
+// c = v dt / d (the CFL number of the axis), s = sin(theta), e = cos(theta) - 1 and
+// theta = k d, the stencils of one axis add to f^n the multiple
+//   -i c s [1 - r3 (1 - c^2) e / 3] + c^2 e [1 + r4 (1 - c^2) e / 2]
+// of each mode (the CD term -i c s, the LW term c^2 e, R3 = i c (1 - c^2) s e / 3 and
+// R4 = c^2 (1 - c^2) e^2 / 2), i.e. the convection term D = -(that) / dt, which the collide
+// multiplies by -dt as for the spectral derivative.
+struct SchemeInst {
+  float2* spec;            // the 32 population spectra (in place)
+  const float2* twy;       // column twiddles, ny entries
+  const float2* scx;       // (sin theta, cos theta - 1) of k_x = 0..nx/2-1, theta = 2 pi k_x / nx
+  const float2* scy;       // the same of k_y = 0..ny-1
+  int nx, tw, id;
+  float cfx, cfy;          // dt / dx, dt / dy
+  float r3, r4;            // 1 where the R3 / R4 terms are on, else 0
+  float sdt;               // 1 / (nx ny dt)
+};
+
+constexpr int kSchemeSlots = 8;
+struct SchemeArgs {
+  SchemeInst c[kSchemeSlots];
+  const int* state;
+};
+
+// D of one axis times dt for CFL number c at (s, e): (real, imaginary).
+__device__ __forceinline__ float2 scheme_axis(float c, float2 se, float r3, float r4) {
+  const float w = 1.0f - c * c;
+  const float im = c * se.x * (1.0f - r3 * w * se.y * (1.0f / 3.0f));
+  const float re = -c * c * se.y * (1.0f + r4 * w * se.y * 0.5f);
+  return make_float2(re, im);
+}
+
+// Tile b of nblocks (all 32 moving populations, (nx/2)/CW column tiles each): forward
+// column FFT, multiplication by D_x(kx) + D_y(ky) (scaled by 1/(nx ny)), inverse column FFT.
+// The packed column 0 holds (DC, Nyquist) of the x transform: D_x is 0 at the DC and the
+// real number D_x(pi) at the Nyquist wavenumber, so that column is multiplied by D_y alone
+// and D_x(pi) times its Nyquist part (unchanged by the column transforms, whose product
+// with the scale is 1/nx) is added to the imaginary part afterwards.
+template <int NY, int CW, int NT, int R>
+__device__ __forceinline__ void col_scheme_body(const SchemeInst& In, float2* lds, int b, int nblocks) {
+  const float2* twy = In.twy;
+  const int nx = In.nx;
+  const unsigned tw = In.tw;
+  const int tid = threadIdx.x;
+  const unsigned ut = static_cast<unsigned>(tid);
+  __builtin_assume(ut < static_cast<unsigned>(NT));
+  twy = col_twiddles<NY, R>(lds + lds_alloc(NY * CW), twy, tid, NT);
+  const int nsub = (nx / 2) / CW;
+  b = xcd_remap(b, nblocks);
+  const int p = b / nsub, sub = b % nsub;
+  const unsigned c0 = sub * CW;
+  float2* g = In.spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
+  const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
+  const float cx = vx * In.cfx, cy = vy * In.cfy;
+  const unsigned col = c0 + ut % CW;
+  const float2 dx = scheme_axis(cx, elem(In.scx, col), In.r3, In.r4);
+  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
+    const unsigned y = e / CW, c = e % CW;
+    lds[padu(e)] = elem(g, y * tw + c);
+  });
+  __syncthreads();
+  fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
+  const float sdt = In.sdt;
+  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
+    const float2 dy = scheme_axis(cy, elem(In.scy, e / CW), In.r3, In.r4);
+    const float mr = (dx.x + dy.x) * sdt, mi = (dx.y + dy.y) * sdt;
+    const float2 v = lds[padu(e)];
+    lds[padu(e)] = make_float2(mr * v.x - mi * v.y, mr * v.y + mi * v.x);
+  });
+  __syncthreads();
+  fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
+  // D_x(pi) / nx: twice c^2 (1 - r4 (1 - c^2)) / dt (s = 0, e = -2), times 1/nx
+  const float nyq = 2.0f * cx * cx * (1.0f - In.r4 * (1.0f - cx * cx)) * (sdt * NY);
+  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
+    const unsigned y = e / CW, c = e % CW;
+    float2 v = lds[padu(e)];
+    if (c0 + c == 0) v.y += nyq * elem(g, y * tw + c).y;
+    elem(g, y * tw + c) = v;
+  });
+}
+
+template <int NY, int CW, int NT, int R>
+__global__ __launch_bounds__(NT) void k_col_conv_scheme(SchemeArgs A) {
+  const SchemeInst& In = A.c[blockIdx.y];
+  if (retired(A.state, In.id)) return;
+  extern __shared__ float2 lds[];
+  col_scheme_body<NY, CW, NT, R>(In, lds, blockIdx.x, gridDim.x);
+}
+
 // Column pass of derivative groups: forward column FFTs of the nin input spectra, then
 // each output the linear combination sum_p m_op(kx, ky) X_p, inverse column FFTs, store.
 //
@@ -961,7 +1053,11 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 // COMP: the state is compensated, f = hi + lo with the low parts in P.flo: the update adds
 // every increment exactly (relax_update_comp), the moments add the sums of the low parts,
 // and the row transforms (the next convection terms) take hi; INIT and SET zero lo.
-template <int NX, int MODE, bool COMP = false>
+//
+// XCOL: the convection spectra of all 32 moving populations come from a column pass (the
+// finite-difference schemes, k_col_conv_scheme); otherwise the 8 populations moving along
+// +-x take theirs here from their row spectra.
+template <int NX, int MODE, bool COMP = false, bool XCOL = false>
 __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, const Inputs& in, int blk) {
   extern __shared__ float2 lds[];
   using G = RowGeom<NX>;
@@ -989,11 +1085,13 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       set_term(in, p, 0, 0, S + 2 * p * hp, 1.0f, TERM_ONE);
       set_term(in, p, 1, 0, S + (2 * p + 1) * hp, 1.0f, TERM_ONE);
     }
+    if constexpr (!XCOL) {
 #pragma unroll
     for (int g = 0; g < GPR; ++g) {
       const int qx0 = q0 + 8 * g, qx4 = qx0 + 4;
       set_term(in, 4 * g + 0, 0, 0, S + (8 * g + 0) * hp, c_vel.vx[qx0] / P.nx, TERM_IKX);
       set_term(in, 4 * g + 2, 0, 0, S + (8 * g + 4) * hp, c_vel.vx[qx4] / P.nx, TERM_IKX);
+    }
     }
     return in;
   };
@@ -1216,12 +1314,12 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   rows_forward_batch<NX, 2>(lds, mo, P.sg, twx, row0, tid);
 }
 
-template <int NX, int MODE, bool COMP>
+template <int NX, int MODE, bool COMP, bool XCOL = false>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_collide(RowArgs A, Inputs in) {
   const int s = blockIdx.y;
   if (retired(A.state, A.id[s])) return;
   assume_planes(A.P[s]);
-  rows_collide<NX, MODE, COMP>(A.P[s], A.M[s], in, blockIdx.x);
+  rows_collide<NX, MODE, COMP, XCOL>(A.P[s], A.M[s], in, blockIdx.x);
 }
 
 // Residual pass, step 1: momentum j = rho u of the current state and its row spectra

@@ -23,6 +23,8 @@ struct Inst {
   const float2* twy;   // column twiddles
   const float* kapy;   // windowed k_y
   int nblk;            // row blocks
+  SchemeInst sch;      // convection by a finite-difference scheme (used when scheme != 0)
+  int scheme;          // 0: spectral convection; 1, 2, 3: LW, MLW1, MLW2
 };
 
 // One launch of a step kernel over `ninst` instances of one grid size (split into launches
@@ -35,6 +37,7 @@ struct StepLaunch {
   int nx, ny, tw, nblk;
   ColPlan plan;
   bool comp;                // compensated state (every instance of the launch)
+  int scheme;               // convection scheme of every instance of the launch (Inst::scheme)
 };
 
 // Block buffers of the column kernels are kept within 64 KB (in float2 elements).
@@ -51,6 +54,9 @@ int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, 
 template <int NY>
 int launch_col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, int pfirst, int nplanes,
                           hipStream_t s);
+// the finite-difference convection pass of all 32 moving populations (StepLaunch::scheme != 0)
+template <int NY>
+int launch_col_conv_scheme(const StepLaunch& L, hipStream_t s);
 
 enum : int { RK_STAGE2 = 0, RK_COLLIDE = 1, RK_INIT = 2, RK_SET = 3, RK_MOMENTUM = 4, RK_RESIDUAL = 5 };
 template <int NX>

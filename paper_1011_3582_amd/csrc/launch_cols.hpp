@@ -104,8 +104,33 @@ int launch_col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, 
   return FFTLB_EINVAL;
 }
 
+// One plan for every grid size: 4 columns per block (every supported nx/2 is a multiple
+// of 4 and of the spectral tile width's divisor 4, and 4 columns of 2048 fit the LDS
+// budget) and radix 16.
+template <int NY>
+int launch_col_conv_scheme(const StepLaunch& L, hipStream_t s) {
+  constexpr int CW = 4, R = 16;
+  static_assert(NY * CW <= kColLdsElems, "scheme column tile exceeds the LDS budget");
+  constexpr int NT = col_threads(NY, CW, R);
+  if ((L.nx / 2) % CW || L.tw % CW) return FFTLB_EINVAL;
+  const int nblocks = 32 * ((L.nx / 2) / CW);
+  const size_t lds = (lds_alloc(NY * CW) + NY) * sizeof(float2);
+  for (int first = 0; first < L.ninst; first += kSchemeSlots) {
+    const int count = cmin(kSchemeSlots, L.ninst - first);
+    SchemeArgs a{};
+    a.state = L.state;
+    for (int k = 0; k < count; ++k) {
+      a.c[k] = L.inst[first + k]->sch;
+      a.c[k].id = L.id ? L.id[first + k] : 0;
+    }
+    hipLaunchKernelGGL((k_col_conv_scheme<NY, CW, NT, R>), dim3(nblocks, count), dim3(NT), lds, s, a);
+  }
+  return FFTLB_OK;
+}
+
 #define FFTLB_INSTANTIATE_COLS(NY)                                    \
   template int launch_col_multi<NY>(const StepLaunch&, const ColLaunch&, int, hipStream_t); \
-  template int launch_col_conv_multi<NY>(const StepLaunch&, const ColLaunch&, int, int, int, hipStream_t);
+  template int launch_col_conv_multi<NY>(const StepLaunch&, const ColLaunch&, int, int, int, hipStream_t); \
+  template int launch_col_conv_scheme<NY>(const StepLaunch&, hipStream_t);
 
 }  // namespace fftlb

@@ -28,7 +28,11 @@ int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s
     switch (kernel) {
       case RK_STAGE2: hipLaunchKernelGGL(k_rows_stage2<NX>, grid, block, G::LDS * sizeof(float2), s, a); break;
       case RK_COLLIDE:
-        if (L.comp)
+        if (L.scheme && L.comp)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, true, true>), grid, block, lds, s, a, in);
+        else if (L.scheme)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, false, true>), grid, block, lds, s, a, in);
+        else if (L.comp)
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, true>), grid, block, lds, s, a, in);
         else
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, false>), grid, block, lds, s, a, in);

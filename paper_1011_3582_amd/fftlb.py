@@ -39,7 +39,12 @@ class Config(ctypes.Structure):
                 ("tau", ctypes.c_double), ("K", ctypes.c_double), ("H", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("q", ctypes.c_double),
                 ("a", ctypes.c_double), ("b", ctypes.c_double),
-                ("filter_order", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("filter_order", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("convection", ctypes.c_int32)]
+
+
+# convection schemes (fftlb_config.convection)
+CONV_SPECTRAL, CONV_LW, CONV_MLW1, CONV_MLW2 = 0, 1, 2, 3
 
 
 class Plan(ctypes.Structure):
@@ -67,10 +72,11 @@ class Params:
     b: float = 0.4
     m: int = 4
     precision: int = 0   # 0: f stored in FP32; 1: compensated hi + lo (see fftlb_config)
+    convection: int = 0  # CONV_SPECTRAL, or the finite-difference scheme CONV_LW / CONV_MLW1 / CONV_MLW2
 
     def config(self, nx: int, ny: int) -> Config:
         return Config(nx, ny, self.dx, self.dy, self.dt, self.tau, self.K, self.H, self.zeta, self.q,
-                      self.a, self.b, self.m, self.precision)
+                      self.a, self.b, self.m, self.precision, self.convection)
 
 
 def _load():

@@ -21,9 +21,10 @@ def test_library_exports_every_declared_function():
 
 
 def test_config_struct_matches_header_layout():
-    # int32 nx, ny; 10 doubles; int32 filter_order, precision
-    assert ctypes.sizeof(F.Config) == 8 + 10 * 8 + 8
+    # int32 nx, ny; 10 doubles; int32 filter_order, precision, convection (padded to 8 bytes)
+    assert ctypes.sizeof(F.Config) == 8 + 10 * 8 + 16
     assert F.Config.dx.offset == 8
+    assert F.Config.convection.offset == 8 + 10 * 8 + 8
 
 
 @pytest.mark.parametrize("nx,ny", [(64, 64), (1024, 1024), (512, 4), (8, 32), (2048, 16)])
@@ -38,6 +39,7 @@ def test_workspace_bytes_valid(nx, ny):
     dict(nx=8, ny=8), dict(nx=48, ny=9),
     dict(dt=0.0), dict(dx=-1.0), dict(tau=0.0), dict(tau=math.nan), dict(K=-1.0), dict(b=-0.1),
     dict(filter_order=6), dict(filter_order=-1), dict(precision=2), dict(precision=-1), dict(q=math.inf),
+    dict(convection=4), dict(convection=-1),
 ])
 def test_invalid_configs_rejected(change):
     cfg = F.Params().config(64, 64)

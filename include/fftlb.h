@@ -64,7 +64,13 @@ extern "C" {
  *  filter_order  0 = exact wavenumber k, 1..4 = windowed k_1..k_4 (Eqs. (44)-(47)), 5 = the
  *                second-order central difference of Sec. 3.1 for every derivative (the CD + CD
  *                comparison scheme): on the periodic grid the stencil (g[J+1] - g[J-1]) / (2 d)
- *                is the multiplier i sin(k d) / d, applied in the same spectral passes.
+ *                is the multiplier i sin(k d) / d, applied in the same spectral passes.  6 = the
+ *                nine-point stencils of the NPS scheme (Sec. 3.1; B = 1/12 for the first
+ *                derivatives, F = 1/6 for the Laplacian of the pressure tensor; second
+ *                derivatives of theta are compositions of first ones) for every derivative of the
+ *                force, and with convection 0 for the convection term too; dx must equal dy.
+ *                The stencils couple the axes, so every derivative goes through column passes
+ *                (5 more spectral planes of workspace, and a step of five kernels).
  *  precision     storage of the distribution: 0 = FP32; 1 = compensated, f = hi + lo with
  *                both parts FP32 (|lo| at most half an ulp of hi): each update adds its
  *                increment exactly, so increments below half an FP32 ulp of f, which an
@@ -149,7 +155,8 @@ int fftlb_set_state(fftlb_handle* h, const float* f, void* stream);
 
 /* Windowed-FFT derivative of one device [ny][nx] field g into out (may not alias g), with
  * the handle's grid and window: op 0 = D_x, 1 = D_y, 2 = D_x D_x + D_y D_y (Sec. 3.6,
- * Eq. (42) with k -> k_m; the Nyquist wavenumber of each first derivative is zero).
+ * Eq. (42) with k -> k_m; the Nyquist wavenumber of each first derivative is zero).  With
+ * filter_order 6 these are the NPS stencils' D_x, D_y and nine-point Laplacian (Sec. 3.1).
  * Uses the handle's stage-1 buffers: do not overlap it with fftlb_step on another stream. */
 int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, void* stream);
 
@@ -161,7 +168,8 @@ int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, vo
  * the tables (computed here on the device).  The two spectral planes and the tables live in
  * a static device array the library holds on each GPU it runs on until the process ends
  * (about 2.1 MB): nx * ny may not exceed 512 * 512 (FFTLB_EINVAL, with the reason in
- * fftlb_last_error).  It calls no allocating routine.  Every call on a GPU shares that GPU's
+ * fftlb_last_error); filter_order 6 (the NPS stencils) is not available here (FFTLB_EINVAL).
+ * It calls no allocating routine.  Every call on a GPU shares that GPU's
  * array: calls that overlap on one GPU (other streams, other host threads) race and must be
  * serialised by the caller; calls on one stream are ordered. */
 int fftlb_derivative_static(const fftlb_config* cfg, const float* g, float* out, int32_t op, void* stream);

@@ -27,7 +27,12 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   R7  moments are taken of f (they equal those of f^eq by construction);
   R8  EOS constants are parameters: P^w = rho T/(1 - b rho) - a rho^2 and the
       9/8 of Eqs. (17) and (22) becomes a (the paper's a = 9/8, b = 1/3);
-  R10 the initial distribution is f^eq(rho0, u0, T0).
+  R10 the initial distribution is f^eq(rho0, u0, T0);
+  R23 the one-dimensional finite-difference schemes of Sec. 3.1 (LW, MLW1, MLW2) act along
+      x with c = v_x dt/dx and along y with c = v_y dt/dy, and their updates add;
+  R24 with the NPS stencils the Laplacian of the pressure tensor is the nine-point one, the
+      derivatives of theta are compositions of first derivatives, and the convection term is
+      v_x D_x f + v_y D_y f with the nine-point first derivatives.
 
 Array layout: fields are [ny, nx] (x fastest); distributions are [33, ny, nx]
 with q = 0 the rest particle and q = 1 + 8(k-1) + (i-1) for speed group k and
@@ -173,6 +178,17 @@ def wavenumbers(n: int, delta: float) -> np.ndarray:
 # the paper's Fig. 2); the oracle applies it as that stencil in real space.
 CENTRAL_DIFFERENCE = 5
 
+# Derivative order m = NPS selects the nine-point stencils of Sec. 3.1 (the NPS scheme) for every
+# derivative and for the convection term: the first derivative with weights A (the row through
+# the node) and B (the two rows beside it), 2A + 4B = 1, B = 1/12; the Laplacian with weights E
+# (edges) and F (corners), E + 2F = 1, F = 1/6.  Second derivatives other than the Laplacian
+# are compositions of the first ones (R2).  The paper uses dx = dy with these stencils.
+NPS = 6
+NPS_B = 1.0 / 12.0
+NPS_A = (1.0 - 4.0 * NPS_B) / 2.0
+NPS_F = 1.0 / 6.0
+NPS_E = 1.0 - 2.0 * NPS_F
+
 
 def kappa(n: int, delta: float, m: int) -> np.ndarray:
     """Windowed wavenumber k_m of Eqs. (44)-(47); m = 0 is the exact k.
@@ -220,9 +236,14 @@ class Deriv:
 
     def __init__(self, ny: int, nx: int, p: Params, workers=None):
         self.cd = p.m == CENTRAL_DIFFERENCE
+        self.nps = p.m == NPS
+        self.stencil = self.cd or self.nps
+        if self.nps and p.dx != p.dy:
+            raise ValueError("the NPS stencils need dx = dy")
         self.dx, self.dy = p.dx, p.dy
-        self.kx = kappa(nx, p.dx, p.m)[None, :]
-        self.ky = kappa(ny, p.dy, p.m)[:, None]
+        if not self.stencil:
+            self.kx = kappa(nx, p.dx, p.m)[None, :]
+            self.ky = kappa(ny, p.dy, p.m)[:, None]
         self.workers = workers
 
     def spectrum(self, g):
@@ -234,12 +255,38 @@ class Deriv:
     def x(self, g):
         if self.cd:
             return (np.roll(g, -1, axis=1) - np.roll(g, 1, axis=1)) / (2.0 * self.dx)
+        if self.nps:
+            return _nps_first(g, 1, 0) / self.dx
         return self.from_spectrum(1j * self.kx * self.spectrum(g))
 
     def y(self, g):
         if self.cd:
             return (np.roll(g, -1, axis=0) - np.roll(g, 1, axis=0)) / (2.0 * self.dy)
+        if self.nps:
+            return _nps_first(g, 0, 1) / self.dy
         return self.from_spectrum(1j * self.ky * self.spectrum(g))
+
+    def laplacian(self, g):
+        """The nine-point Laplacian with the NPS stencils; otherwise D_x D_x g + D_y D_y g (R2)."""
+        if self.nps:
+            return _nps_laplacian(g) / (self.dx * self.dx)
+        return self.x(self.x(g)) + self.y(self.y(g))
+
+
+def _nps_first(g, along, across):
+    """Nine-point first difference (times the spacing) along axis `along`: A times the
+    difference of the two neighbours on the node's own line, plus B times the differences on
+    the two lines beside it (offset by one node along `across`)."""
+    diff = np.roll(g, -1, axis=along) - np.roll(g, 1, axis=along)
+    return NPS_A * diff + NPS_B * (np.roll(diff, -1, axis=across) + np.roll(diff, 1, axis=across))
+
+
+def _nps_laplacian(g):
+    """Nine-point Laplacian (times the spacing squared): E times the four edge neighbours, F
+    times the four corner neighbours, -4 (E + F) times the node."""
+    edges = np.roll(g, 1, 0) + np.roll(g, -1, 0) + np.roll(g, 1, 1) + np.roll(g, -1, 1)
+    corners = sum(np.roll(np.roll(g, a, 0), b, 1) for a in (1, -1) for b in (1, -1))
+    return NPS_E * edges + NPS_F * corners - 4.0 * (NPS_E + NPS_F) * g
 
 
 # Sec. 3.1: finite-difference schemes of the convection term, compared in the paper's
@@ -275,7 +322,7 @@ def convection(f, v, D: Deriv, p: Params | None = None):
 
     By linearity of Eq. (42), FT[v.grad f] = i (v_x k_x + v_y k_y) FT[f]; one
     forward and one inverse transform per moving population.  C_0 = 0.  With the central
-    difference: v_x D_x f + v_y D_y f by the stencil (the conservative form of Sec. 3.1).
+    difference or the NPS stencils: v_x D_x f + v_y D_y f by the stencil (Sec. 3.1).
     With a finite-difference scheme (p.conv): the updates of fd_convection_update along x
     (c = v_x dt/dx) and along y (c = v_y dt/dy) added (reading R23), returned as the term C
     that the step subtracts times dt: C = -(du_x + du_y) / dt.
@@ -288,7 +335,7 @@ def convection(f, v, D: Deriv, p: Params | None = None):
                   + fd_convection_update(f[q], v[q, 1] * p.dt / p.dy, 0, scheme))
             out[q] = -du / p.dt
             continue
-        if D.cd:
+        if D.stencil:
             out[q] = v[q, 0] * D.x(f[q]) + v[q, 1] * D.y(f[q])
             continue
         mult = 1j * (v[q, 0] * D.kx + v[q, 1] * D.ky)
@@ -337,7 +384,7 @@ def force_coefficients(rho, ux, uy, T, p: Params, D: Deriv) -> Force:
     A    = -2 (C + C_q) T                                                  (Eq. (20))
     """
     rx, ry = D.x(rho), D.y(rho)
-    lap = D.x(rx) + D.y(ry)                       # R2
+    lap = D.laplacian(rho) if D.nps else D.x(rx) + D.y(ry)   # R2 (NPS: the nine-point Laplacian)
     dxux, dyux = D.x(ux), D.y(ux)
     dxuy, dyuy = D.x(uy), D.y(uy)
     theta = dxux + dyuy

@@ -90,7 +90,9 @@ bool config_ok(const fftlb_config* c) {
   if (!(c->tau > 0.0) || std::isnan(c->tau)) return false;
   if (!nonneg(c->K) || !nonneg(c->H) || !nonneg(c->a) || !nonneg(c->b)) return false;
   if (!std::isfinite(c->zeta) || !std::isfinite(c->q)) return false;
-  if (c->filter_order < 0 || c->filter_order > 5) return false;
+  if (c->filter_order < 0 || c->filter_order > 6) return false;
+  // the nine-point Laplacian of the NPS stencils is defined on a square lattice
+  if (c->filter_order == 6 && c->dx != c->dy) return false;
   if (c->precision != 0 && c->precision != 1) return false;
   if (c->convection < 0 || c->convection > 3) return false;
   return true;
@@ -102,6 +104,9 @@ struct Layout {
 
 // Planes of the spectral block (contiguous, so that a column pass addresses them by index).
 enum : int { SB_SM = 0, SB_S1 = 4, SB_S2I = 10, SB_S2O = 15, SB_PLANES = 18 };
+// With the NPS stencils every stage-1 derivative comes from the column pass: 5 more planes
+// after the block (dyux, thx, thy, Tx, Ty follow s1 = rx, ry, lap, dxux, dyux, dxuy).
+constexpr int SB_NPS = SB_PLANES, SB_NPS_EXTRA = 5;
 
 size_t align_up(size_t v) { return (v + FFTLB_WORKSPACE_ALIGN - 1) / FFTLB_WORKSPACE_ALIGN * FFTLB_WORKSPACE_ALIGN; }
 
@@ -120,7 +125,7 @@ Layout make_layout(const fftlb_config& c) {
   L.f = take(33 * plane);
   L.flo = take(c.precision == 1 ? 33 * plane : 0);
   L.sf = take(32 * plane);
-  L.spec = take(SB_PLANES * plane);
+  L.spec = take((SB_PLANES + (c.filter_order == 6 ? SB_NPS_EXTRA : 0)) * plane);
   L.macro = take(4 * plane);
   L.cpl = take(plane);
   L.twx = take((size_t)nx * sizeof(float2));
@@ -144,7 +149,8 @@ __host__ __device__ double windowed_k(int n, int N, double d, int m) {
   if (2 * n == -N || 2 * n == N) return 0.0;
   const double k = 2.0 * M_PI * n / (N * d);
   if (m == 0) return k;
-  if (m == 5) return sin(2.0 * M_PI * (double)n / N) / d;
+  // m = 6 (the NPS stencils) never reads these tables; it gets the central-difference values
+  if (m == 5 || m == 6) return sin(2.0 * M_PI * (double)n / N) / d;
   const double c[4] = {1.0, 1.0 / 6.0, 3.0 / 40.0, 5.0 / 112.0};
   const double s = sin(M_PI * (double)n / N);
   double acc = 0.0, sp = s;
@@ -160,7 +166,7 @@ ColGroup group(std::initializer_list<int> in, std::initializer_list<int> out,
   ColGroup g{};
   g.nin = (int)in.size();
   g.nout = (int)out.size();
-  if (!multi_shape_ok(g.nin, g.nout)) throw std::logic_error("derivative group shape without a column-pass body");
+  if (!nps_shape_ok(g.nin, g.nout)) throw std::logic_error("derivative group shape without a column-pass body");
   int i = 0;
   for (int p : in) g.in[i++] = p;
   i = 0;
@@ -183,6 +189,20 @@ ColLaunch stage1_groups() {
   a.g[0] = group({sm}, {s1, s1 + 1}, {{MK_IKY}, {MK_KYY}});
   a.g[1] = group({sm + 1, sm + 2}, {s1 + 2, s1 + 3, s1 + 4}, {{MK_IKY, MK_NONE}, {MK_NONE, MK_IKY}, {MK_KXY, MK_KYY}});
   a.g[2] = group({sm + 3}, {s1 + 5}, {{MK_IKY}});
+  return a;
+}
+
+// Stage 1 with the NPS stencils (filter_order 6): every derivative in the column pass, since the
+// nine-point stencils couple the axes.  s1 = [rx, ry, lap, dxux, dyux, dxuy] and, after the
+// block, [dyuy, thx, thy, Tx, Ty]; lap is the nine-point Laplacian, thx and thy are
+// compositions of the first derivatives (D_x theta = D_x D_x ux + D_x D_y uy).
+ColLaunch stage1_nps_groups() {
+  ColLaunch a{};
+  const int sm = SB_SM, s1 = SB_S1, sn = SB_NPS;
+  a.g[0] = group({sm}, {s1, s1 + 1, s1 + 2}, {{MK_IKX}, {MK_IKY}, {MK_LAP}});
+  a.g[1] = group({sm + 1, sm + 2}, {s1 + 3, s1 + 4, s1 + 5}, {{MK_IKX, MK_NONE}, {MK_IKY, MK_NONE}, {MK_NONE, MK_IKX}});
+  a.g[2] = group({sm + 1, sm + 2}, {sn, sn + 1, sn + 2}, {{MK_NONE, MK_IKY}, {MK_KXX, MK_KXY}, {MK_KXY, MK_KYY}});
+  a.g[3] = group({sm + 3}, {sn + 3, sn + 4}, {{MK_IKX}, {MK_IKY}});
   return a;
 }
 
@@ -211,6 +231,7 @@ ColLaunch divergence_group() {
 }
 
 const ColLaunch kStage1 = stage1_groups();
+const ColLaunch kStage1Nps = stage1_nps_groups();
 const ColLaunch kStage2 = stage2_groups();
 const ColLaunch kDivJ = divergence_group();
 
@@ -271,6 +292,15 @@ int rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s) {
 }
 
 int col_multi(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+  if (L.nps) {
+    switch (L.ny) {
+#define X(n) \
+  case n: return launch_col_nps<n>(L, groups, ngroups, s);
+      FFTLB_FOR_COL_SIZES(X)
+#undef X
+    }
+    return FFTLB_EINVAL;
+  }
   switch (L.ny) {
 #define X(n) \
   case n: return launch_col_multi<n>(L, groups, ngroups, s);
@@ -324,7 +354,7 @@ int rows_inverse_real(const Inst& I, int nx, const float2* sa, float* a, hipStre
 StepLaunch single_launch(const fftlb_handle* h, const ColPlan& plan) {
   return StepLaunch{&h->self, nullptr, 1,    nullptr,
                     h->nx,    h->ny,   h->tw, h->I.nblk,
-                    plan,     h->cfg.precision == 1, h->cfg.convection};
+                    plan,     h->cfg.precision == 1, h->I.scheme, h->cfg.filter_order == 6};
 }
 
 // ---------------------------------------------------------------------------
@@ -343,12 +373,18 @@ enum : int { ST_CONV_S1 = 0, ST_S2_ROWS = 1, ST_S2_COLS = 2, ST_COLLIDE = 3, ST_
 // best, and 16..20 are within 1 us of each other.
 constexpr int kConvSplit = 16;
 
+// The stage-1 derivative column pass by itself: the windowed groups, or with the NPS
+// stencils all 11 derivatives.
+int stage1_columns(const StepLaunch& L, hipStream_t s) {
+  return L.nps ? col_multi(L, kStage1Nps, 4, s) : col_multi(L, kStage1, 3, s);
+}
+
 // With a finite-difference convection scheme the derivative column passes run by themselves
 // and the scheme's column pass of all 32 moving populations follows the stage-1 pass.
 int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
   if (L.scheme) {
     switch (stage) {
-      case ST_CONV_S1: RC_TRY(col_multi(L, kStage1, 3, s)); return col_conv_scheme(L, s);
+      case ST_CONV_S1: RC_TRY(stage1_columns(L, s)); return col_conv_scheme(L, s);
       case ST_S2_COLS: return col_multi(L, kStage2, 2, s);
     }
   }
@@ -357,7 +393,7 @@ int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
     case ST_S2_ROWS: return rows(L, RK_STAGE2, Inputs{}, s);
     case ST_S2_COLS: return col_conv_multi(L, kStage2, 2, kConvSplit, 24 - kConvSplit, s);
     case ST_COLLIDE: return rows(L, RK_COLLIDE, Inputs{}, s);
-    case ST_S1_COLS: return col_multi(L, kStage1, 3, s);
+    case ST_S1_COLS: return stage1_columns(L, s);
   }
   return FFTLB_EINVAL;
 }
@@ -624,6 +660,7 @@ struct fftlb_batch {
     int nx, ny, tw, nblk;
     bool comp;
     int scheme;
+    bool nps;
     ColPlan plan;
     std::vector<int> members;  // all instances of this size
   };
@@ -687,7 +724,7 @@ void batch_launches(fftlb_batch* b, std::vector<std::vector<int>>* ids, std::vec
     const auto& g = b->groups[k];
     if ((*ids)[k].empty()) continue;
     out->push_back(StepLaunch{(*ptrs)[k].data(), (*ids)[k].data(), (int)(*ids)[k].size(), b->st.state, g.nx, g.ny,
-                              g.tw, g.nblk, g.plan, g.comp, g.scheme});
+                              g.tw, g.nblk, g.plan, g.comp, g.scheme, g.nps});
   }
 }
 
@@ -818,8 +855,9 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   M.b = (float)cfg->b;
   M.scale = (float)(1.0 / ((double)h->nx * h->ny));
 
-  // convection by a finite-difference scheme: LW (1), MLW1 = LW + R3 (2), MLW2 = LW + R3 + R4 (3)
-  I.scheme = cfg->convection;
+  // convection by a finite-difference scheme: LW (1), MLW1 = LW + R3 (2), MLW2 = LW + R3 + R4 (3),
+  // or with the NPS stencils (filter_order 6 and convection 0) the NPS first derivatives (4)
+  I.scheme = cfg->convection ? cfg->convection : cfg->filter_order == 6 ? 4 : 0;
   SchemeInst& S = I.sch;
   S.spec = P.sf;
   S.twy = I.twy;
@@ -833,6 +871,18 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   S.r3 = cfg->convection >= 2 ? 1.0f : 0.0f;
   S.r4 = cfg->convection >= 3 ? 1.0f : 0.0f;
   S.sdt = (float)(1.0 / ((double)h->nx * h->ny * cfg->dt));
+  S.nps = I.scheme == 4 ? 1 : 0;
+  NpsInst& N = I.nps;
+  N.spec = I.spec;
+  N.twy = I.twy;
+  N.scx = S.scx;
+  N.scy = S.scy;
+  N.nx = h->nx;
+  N.tw = h->tw;
+  N.id = 0;
+  N.rdx = (float)(1.0 / cfg->dx);
+  N.rdy = (float)(1.0 / cfg->dy);
+  N.scale = M.scale;
 
   // Twiddles exp(-2 pi i j/N) and windowed wavenumbers, in FP64, stored FP32.
   std::vector<float2> twx(h->nx), twy(h->ny);
@@ -1067,6 +1117,11 @@ int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, vo
 
 int fftlb_derivative_static(const fftlb_config* cfg, const float* g, float* out, int32_t op, void* stream) {
   if (!config_ok(cfg) || !g || !out || g == out || op < 0 || op > 2) return FFTLB_EINVAL;
+  if (cfg->filter_order == 6) {
+    std::snprintf(g_last_error, sizeof g_last_error,
+                  "fftlb_derivative_static: the NPS stencils (filter_order 6) are not available here");
+    return FFTLB_EINVAL;
+  }
   const int nx = cfg->nx, ny = cfg->ny;
   if ((long)nx * ny > kStaticMaxSites) {
     std::snprintf(g_last_error, sizeof g_last_error,
@@ -1195,11 +1250,12 @@ int fftlb_batch_create(int32_t n, const fftlb_config* cfgs, void* workspace, siz
     auto g = std::find_if(b->groups.begin(), b->groups.end(),
                           [&](const fftlb_batch::Group& gg) {
                             return gg.nx == c.nx && gg.ny == c.ny && gg.comp == (c.precision == 1) &&
-                                   gg.scheme == c.convection;
+                                   gg.scheme == h->I.scheme && gg.nps == (c.filter_order == 6);
                           });
     if (g == b->groups.end()) {
       b->groups.push_back(
-          fftlb_batch::Group{c.nx, c.ny, h->tw, h->I.nblk, c.precision == 1, c.convection, h->plan, {}});
+          fftlb_batch::Group{c.nx, c.ny, h->tw, h->I.nblk, c.precision == 1, h->I.scheme, c.filter_order == 6,
+                             h->plan, {}});
       g = b->groups.end() - 1;
     }
     g->members.push_back(i);

@@ -168,7 +168,7 @@ struct ColGroup {
 };
 
 struct ColLaunch {
-  ColGroup g[3];
+  ColGroup g[4];
 };
 
 // Kernel arguments are passed by value: pointers inside kernel arguments are known to
@@ -638,7 +638,10 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
 //   -i c s [1 - r3 (1 - c^2) e / 3] + c^2 e [1 + r4 (1 - c^2) e / 2]
 // of each mode (the CD term -i c s, the LW term c^2 e, R3 = i c (1 - c^2) s e / 3 and
 // R4 = c^2 (1 - c^2) e^2 / 2), i.e. the convection term D = -(that) / dt, which the collide
-// multiplies by -dt as for the spectral derivative.
+// multiplies by -dt as for the spectral derivative.  The nine-point stencils of the NPS scheme
+// (Sec. 3.1, A = 1/3, B = 1/12) have the cross-axis symbols
+//   D_x = i s_x (2 + cos theta_y) / (3 dx),  D_y = i s_y (2 + cos theta_x) / (3 dy),
+// so their convection term times dt is i [c_x s_x (3 + e_y) + c_y s_y (3 + e_x)] / 3.
 struct SchemeInst {
   float2* spec;            // the 32 population spectra (in place)
   const float2* twy;       // column twiddles, ny entries
@@ -648,6 +651,7 @@ struct SchemeInst {
   float cfx, cfy;          // dt / dx, dt / dy
   float r3, r4;            // 1 where the R3 / R4 terms are on, else 0
   float sdt;               // 1 / (nx ny dt)
+  int nps;                 // 1: the NPS stencils instead of the LW family
 };
 
 constexpr int kSchemeSlots = 8;
@@ -664,12 +668,32 @@ __device__ __forceinline__ float2 scheme_axis(float c, float2 se, float r3, floa
   return make_float2(re, im);
 }
 
+// dt D at (s, e) of k_x and of k_y: (real, imaginary).
+__device__ __forceinline__ float2 scheme_symbol(const SchemeInst& In, float cx, float cy, float2 sx, float2 sy) {
+  if (In.nps) return make_float2(0.0f, (cx * sx.x * (3.0f + sy.y) + cy * sy.x * (3.0f + sx.y)) * (1.0f / 3.0f));
+  const float2 a = scheme_axis(cx, sx, In.r3, In.r4), b = scheme_axis(cy, sy, In.r3, In.r4);
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+
+// (s, e) of the x Nyquist wavenumber, theta = pi
+__device__ __forceinline__ float2 nyquist_se() { return make_float2(0.0f, -2.0f); }
+
+// Product of a packed column's spectrum with two multipliers.  Column 0 of the row spectra
+// holds Z = A + i B with A, B the (real) DC and Nyquist columns of the x transform; their y
+// spectra are A^ = (Z^(ky) + conj Z^(-ky)) / 2 and i B^ = (Z^(ky) - conj Z^(-ky)) / 2, and the
+// result is m_a A^ + i m_b B^ (m_a at k_x = 0, m_b at the x Nyquist wavenumber).  z = Z^(ky),
+// w = Z^(-ky).
+__device__ __forceinline__ float2 packed_product(float2 ma, float2 mb, float2 z, float2 w) {
+  const float2 wc = make_float2(w.x, -w.y);
+  const float2 a = cmul(ma, cadd(z, wc)), b = cmul(mb, csub(z, wc));
+  return make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
+}
+
 // Tile b of nblocks (all 32 moving populations, (nx/2)/CW column tiles each): forward
-// column FFT, multiplication by D_x(kx) + D_y(ky) (scaled by 1/(nx ny)), inverse column FFT.
-// The packed column 0 holds (DC, Nyquist) of the x transform: D_x is 0 at the DC and the
-// real number D_x(pi) at the Nyquist wavenumber, so that column is multiplied by D_y alone
-// and D_x(pi) times its Nyquist part (unchanged by the column transforms, whose product
-// with the scale is 1/nx) is added to the imaginary part afterwards.
+// column FFT, multiplication by D(kx, ky) (scaled by 1/(nx ny)), inverse column FFT.  The
+// packed column 0 takes packed_product (the scheme's multipliers differ between its DC and
+// Nyquist halves), which reads the mirror element -ky: every product is formed in
+// registers before any is written back.
 template <int NY, int CW, int NT, int R>
 __device__ __forceinline__ void col_scheme_body(const SchemeInst& In, float2* lds, int b, int nblocks) {
   const float2* twy = In.twy;
@@ -686,8 +710,10 @@ __device__ __forceinline__ void col_scheme_body(const SchemeInst& In, float2* ld
   float2* g = In.spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
   const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
   const float cx = vx * In.cfx, cy = vy * In.cfy;
+  static_assert(NT % CW == 0, "a thread keeps one column");
   const unsigned col = c0 + ut % CW;
-  const float2 dx = scheme_axis(cx, elem(In.scx, col), In.r3, In.r4);
+  const float2 sx = elem(In.scx, col);
+  const bool packed = col == 0;
   for_strided<NY * CW, NT>(ut, [&](unsigned e) {
     const unsigned y = e / CW, c = e % CW;
     lds[padu(e)] = elem(g, y * tw + c);
@@ -695,21 +721,35 @@ __device__ __forceinline__ void col_scheme_body(const SchemeInst& In, float2* ld
   __syncthreads();
   fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
   const float sdt = In.sdt;
-  for_strided<NY * CW, NT>(ut, [&](unsigned e) {
-    const float2 dy = scheme_axis(cy, elem(In.scy, e / CW), In.r3, In.r4);
-    const float mr = (dx.x + dy.x) * sdt, mi = (dx.y + dy.y) * sdt;
-    const float2 v = lds[padu(e)];
-    lds[padu(e)] = make_float2(mr * v.x - mi * v.y, mr * v.y + mi * v.x);
-  });
+  constexpr int IT = (NY * CW + NT - 1) / NT;
+  constexpr bool FULL = (NY * CW) % NT == 0;
+  float2 res[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned e = ut + i * NT;
+    if (!(FULL || e < static_cast<unsigned>(NY * CW))) continue;
+    const unsigned y = e / CW, c = e % CW;
+    const float2 sy = elem(In.scy, y);
+    const float2 m = scheme_symbol(In, cx, cy, sx, sy);
+    const float2 z = lds[padu(e)];
+    float2 r = cmul(m, z);
+    if (packed) {
+      const float2 w = lds[padu(((NY - y) % NY) * CW + c)];
+      r = packed_product(m, scheme_symbol(In, cx, cy, nyquist_se(), sy), z, w);
+    }
+    res[i] = make_float2(r.x * sdt, r.y * sdt);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned e = ut + i * NT;
+    if (FULL || e < static_cast<unsigned>(NY * CW)) lds[padu(e)] = res[i];
+  }
   __syncthreads();
   fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
-  // D_x(pi) / nx: twice c^2 (1 - r4 (1 - c^2)) / dt (s = 0, e = -2), times 1/nx
-  const float nyq = 2.0f * cx * cx * (1.0f - In.r4 * (1.0f - cx * cx)) * (sdt * NY);
   for_strided<NY * CW, NT>(ut, [&](unsigned e) {
     const unsigned y = e / CW, c = e % CW;
-    float2 v = lds[padu(e)];
-    if (c0 + c == 0) v.y += nyq * elem(g, y * tw + c).y;
-    elem(g, y * tw + c) = v;
+    elem(g, y * tw + c) = lds[padu(e)];
   });
 }
 
@@ -845,6 +885,137 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
   col_multi_tile<NY, CW, NT, R>(In, L.g[blockIdx.y], lds, blockIdx.x, gridDim.x);
 }
 
+// Derivative groups with the nine-point stencils of the NPS scheme (Sec. 3.1): A = 1/3,
+// B = 1/12 for the first derivative, E = 2/3, F = 1/6 for the Laplacian.  On the periodic grid
+// each stencil is a multiplication of the spectrum; with s = sin(theta), e = cos(theta) - 1 of
+// each axis (theta = k d, dx = dy = d):
+//   D_x = i s_x (3 + e_y) / (3 dx),   D_y = i s_y (3 + e_x) / (3 dy),
+//   Lap = [2 (e_x + e_y) + (2/3) e_x e_y] / d^2,
+// and the group kinds map onto them: i k_x -> D_x, i k_y -> D_y, -k_x^2 -> D_x D_x,
+// -k_y^2 -> D_y D_y, -k_x k_y -> D_x D_y, -(k_x^2 + k_y^2) -> Lap.  One column per block:
+// these groups run by themselves (not inside the convection launches).
+struct NpsInst {
+  float2* spec;            // the spectral block
+  const float2* twy;       // column twiddles, ny entries
+  const float2* scx;       // (sin theta, cos theta - 1) of k_x = 0..nx/2-1
+  const float2* scy;       // the same of k_y = 0..ny-1
+  int nx, tw, id;
+  float rdx, rdy;          // 1 / dx, 1 / dy
+  float scale;             // 1 / (nx ny)
+};
+
+struct NpsArgs {
+  NpsInst c[kSchemeSlots];
+  const int* state;
+};
+
+__device__ __forceinline__ float2 nps_multiplier(int kd, float2 sx, float2 sy, float rdx, float rdy) {
+  const float dx = sx.x * (3.0f + sy.y) * (1.0f / 3.0f) * rdx;  // D_x = i dx
+  const float dy = sy.x * (3.0f + sx.y) * (1.0f / 3.0f) * rdy;  // D_y = i dy
+  const float lap = (2.0f * (sx.y + sy.y) + (2.0f / 3.0f) * sx.y * sy.y) * (rdx * rdy);
+  const float ai = kd == MK_IKX ? dx : kd == MK_IKY ? dy : 0.0f;
+  const float ar = kd == MK_KXX   ? -dx * dx
+                 : kd == MK_KYY   ? -dy * dy
+                 : kd == MK_KXY   ? -dx * dy
+                 : kd == MK_LAP   ? lap
+                                  : 0.0f;
+  return make_float2(ar, ai);
+}
+
+template <int NY, int NT, int R, int NIN, int NOUT>
+__device__ __forceinline__ void col_nps_body(const NpsInst& In, const ColGroup& G, float2* lds, const float2* twy,
+                                             unsigned ut, int tid, unsigned col) {
+  static_assert(NIN <= kMultiSlots && NOUT <= kMultiSlots, "group shape");
+  constexpr bool AL = is_pow2(NY) && NY % 32 == 0;
+  const unsigned tw = In.tw;
+  const long hp = (long)(In.nx / 2) * NY;
+  const long off = (long)(col / tw) * NY * tw + (col % tw);
+#pragma unroll
+  for (int p = 0; p < NIN; ++p) {
+    const float2* g = In.spec + G.in[p] * hp + off;
+    for_strided<NY, NT>(ut, [&](unsigned y) { lds[padu(p * NY + y)] = elem(g, y * tw); });
+  }
+  __syncthreads();
+  fft_lds<NY, -1, NT, NIN, false, 1, AL, R>(lds, 0, NY, twy, tid);
+  int kd[NOUT][NIN];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+    for (int p = 0; p < NIN; ++p) kd[o][p] = G.kind[o][p];
+  const float2 sx = elem(In.scx, col);
+  const bool packed = col == 0;  // the block's column: (DC, Nyquist) of the x transform
+  constexpr int IT = (NY + NT - 1) / NT;
+  constexpr bool FULL = NY % NT == 0;
+  // products into registers first: the packed column reads the mirror element -ky
+  float2 res[IT][NOUT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned y = ut + i * NT;
+    if (!(FULL || y < static_cast<unsigned>(NY))) continue;
+    const float2 sy = elem(In.scy, y);
+    float2 x[NIN], w[NIN];
+#pragma unroll
+    for (int p = 0; p < NIN; ++p) {
+      x[p] = lds[padu(p * NY + y)];
+      w[p] = packed ? lds[padu(p * NY + (NY - y) % NY)] : x[p];
+    }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int p = 0; p < NIN; ++p) {
+        const float2 m = nps_multiplier(kd[o][p], sx, sy, In.rdx, In.rdy);
+        acc = cadd(acc, packed ? packed_product(m, nps_multiplier(kd[o][p], nyquist_se(), sy, In.rdx, In.rdy), x[p],
+                                                w[p])
+                               : cmul(m, x[p]));
+      }
+      res[i][o] = make_float2(acc.x * In.scale, acc.y * In.scale);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const unsigned y = ut + i * NT;
+    if (!(FULL || y < static_cast<unsigned>(NY))) continue;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) lds[padu(o * NY + y)] = res[i][o];
+  }
+  __syncthreads();
+  fft_lds<NY, +1, NT, NOUT, false, 1, AL, R>(lds, 0, NY, twy, tid);
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    float2* g = In.spec + G.out[o] * hp + off;
+    for_strided<NY, NT>(ut, [&](unsigned y) { elem(g, y * tw) = lds[padu(o * NY + y)]; });
+  }
+}
+
+// Group shapes of the NPS groups: those of the windowed groups and (1, 3).
+__host__ __device__ constexpr bool nps_shape_ok(int nin, int nout) {
+  return multi_shape_ok(nin, nout) || (nin == 1 && nout == 3);
+}
+
+template <int NY, int NT, int R>
+__global__ __launch_bounds__(NT) void k_col_nps(NpsArgs A, ColLaunch L) {
+  const NpsInst& In = A.c[blockIdx.z];
+  if (retired(A.state, In.id)) return;
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const unsigned ut = static_cast<unsigned>(tid);
+  __builtin_assume(ut < static_cast<unsigned>(NT));
+  const float2* twy = col_twiddles<NY, R>(lds + lds_alloc(kMultiSlots * NY), In.twy, tid, NT);
+  const unsigned col = xcd_remap(blockIdx.x, In.nx / 2);
+  const ColGroup& G = L.g[blockIdx.y];
+  switch (G.nin * 4 + G.nout) {
+    case 1 * 4 + 1: col_nps_body<NY, NT, R, 1, 1>(In, G, lds, twy, ut, tid, col); break;
+    case 1 * 4 + 2: col_nps_body<NY, NT, R, 1, 2>(In, G, lds, twy, ut, tid, col); break;
+    case 1 * 4 + 3: col_nps_body<NY, NT, R, 1, 3>(In, G, lds, twy, ut, tid, col); break;
+    case 2 * 4 + 1: col_nps_body<NY, NT, R, 2, 1>(In, G, lds, twy, ut, tid, col); break;
+    case 2 * 4 + 3: col_nps_body<NY, NT, R, 2, 3>(In, G, lds, twy, ut, tid, col); break;
+    case 3 * 4 + 2: col_nps_body<NY, NT, R, 3, 2>(In, G, lds, twy, ut, tid, col); break;
+    default: break;  // not built by the host (nps_shape_ok)
+  }
+}
+
 // Convection tiles of planes pfirst.. and a derivative pass (of ngroups groups) in one
 // launch: the first nc blocks of a slot run the convection tiles, the ngroups nt blocks
 // after them the derivative tiles (CWM columns each, nt = (nx/2)/CWM tiles per group) with the
@@ -879,7 +1050,10 @@ __global__ __launch_bounds__(NT, 4) void k_col_conv_multi(ConvMultiArgs A, ColLa
 
 // Stage 2: derivatives at the sites, closure of Eqs. (18)-(23), forward row transforms of
 // P1 = S + Lxx, P2 = Lxy, P3 = S + Lyy, gx, gy; C to its plane; diagnostics partials.
-template <int NX>
+// NPS: all 11 derivatives come from the column pass (the nine-point stencils couple the
+// axes), s1 = [rx, ry, lap, dxux, dyux, dxuy] and the five planes after the spectral block's
+// 18, [dyuy, thx, thy, Tx, Ty].
+template <int NX, bool NPS = false>
 __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int blk) {
   extern __shared__ float2 lds[];
   using G = RowGeom<NX>;
@@ -913,20 +1087,35 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
     const float2 *R = P.sm, *Ux = P.sm + hp, *Uy = P.sm + 2 * hp, *Th = P.sm + 3 * hp;
     const float2* s1 = P.s1;
     PairBatch<4> b = empty_batch<4>();
-    set_term(b, 0, 0, 0, R, inx, TERM_IKX);                 // rx
-    set_term(b, 0, 1, 0, s1, 1.0f, TERM_ONE);               // ry
-    set_term(b, 1, 0, 0, R, inx, TERM_KXX);                 // lap = D_xx rho + D_yy rho
-    set_term(b, 1, 0, 1, s1 + hp, 1.0f, TERM_ONE);
-    set_term(b, 1, 1, 0, Ux, inx, TERM_IKX);                // dxux
-    set_term(b, 2, 0, 0, s1 + 2 * hp, 1.0f, TERM_ONE);      // dyux
-    set_term(b, 2, 1, 0, Ux, inx, TERM_KXX);                // thx = D_x(D_x ux + D_y uy)
-    set_term(b, 2, 1, 1, s1 + 3 * hp, 1.0f, TERM_IKX);
-    set_term(b, 3, 0, 0, Uy, inx, TERM_IKX);                // dxuy
-    set_term(b, 3, 1, 0, s1 + 3 * hp, 1.0f, TERM_ONE);      // dyuy
     PairBatch<2> b2 = empty_batch<2>();
-    set_term(b2, 0, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);     // thy
-    set_term(b2, 0, 1, 0, Th, inx, TERM_IKX);               // Tx
-    set_term(b2, 1, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);     // Ty
+    if constexpr (NPS) {
+      const float2* sn = s1 + 14 * hp;  // plane 18 of the spectral block
+      set_term(b, 0, 0, 0, s1, 1.0f, TERM_ONE);               // rx
+      set_term(b, 0, 1, 0, s1 + hp, 1.0f, TERM_ONE);          // ry
+      set_term(b, 1, 0, 0, s1 + 2 * hp, 1.0f, TERM_ONE);      // lap
+      set_term(b, 1, 1, 0, s1 + 3 * hp, 1.0f, TERM_ONE);      // dxux
+      set_term(b, 2, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);      // dyux
+      set_term(b, 2, 1, 0, sn + hp, 1.0f, TERM_ONE);          // thx
+      set_term(b, 3, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);      // dxuy
+      set_term(b, 3, 1, 0, sn, 1.0f, TERM_ONE);               // dyuy
+      set_term(b2, 0, 0, 0, sn + 2 * hp, 1.0f, TERM_ONE);     // thy
+      set_term(b2, 0, 1, 0, sn + 3 * hp, 1.0f, TERM_ONE);     // Tx
+      set_term(b2, 1, 0, 0, sn + 4 * hp, 1.0f, TERM_ONE);     // Ty
+    } else {
+      set_term(b, 0, 0, 0, R, inx, TERM_IKX);                 // rx
+      set_term(b, 0, 1, 0, s1, 1.0f, TERM_ONE);               // ry
+      set_term(b, 1, 0, 0, R, inx, TERM_KXX);                 // lap = D_xx rho + D_yy rho
+      set_term(b, 1, 0, 1, s1 + hp, 1.0f, TERM_ONE);
+      set_term(b, 1, 1, 0, Ux, inx, TERM_IKX);                // dxux
+      set_term(b, 2, 0, 0, s1 + 2 * hp, 1.0f, TERM_ONE);      // dyux
+      set_term(b, 2, 1, 0, Ux, inx, TERM_KXX);                // thx = D_x(D_x ux + D_y uy)
+      set_term(b, 2, 1, 1, s1 + 3 * hp, 1.0f, TERM_IKX);
+      set_term(b, 3, 0, 0, Uy, inx, TERM_IKX);                // dxuy
+      set_term(b, 3, 1, 0, s1 + 3 * hp, 1.0f, TERM_ONE);      // dyuy
+      set_term(b2, 0, 0, 0, s1 + 4 * hp, 1.0f, TERM_ONE);     // thy
+      set_term(b2, 0, 1, 0, Th, inx, TERM_IKX);               // Tx
+      set_term(b2, 1, 0, 0, s1 + 5 * hp, 1.0f, TERM_ONE);     // Ty
+    }
     // both batches are read at once; the second waits in registers during the first's
     // transforms
     const BatchFetch<NX, 4> f1 = rows_fetch_batch<NX, 4>(b, P.sg, P.kapx, row0, tid);
@@ -1035,12 +1224,12 @@ __device__ __forceinline__ void rows_stage2(const Planes& P, const Model& M, int
   }
 }
 
-template <int NX>
+template <int NX, bool NPS = false>
 __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_stage2(RowArgs A) {
   const int s = blockIdx.y;
   if (retired(A.state, A.id[s])) return;
   assume_planes(A.P[s]);
-  rows_stage2<NX>(A.P[s], A.M[s], blockIdx.x);
+  rows_stage2<NX, NPS>(A.P[s], A.M[s], blockIdx.x);
 }
 
 enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };

@@ -24,7 +24,8 @@ struct Inst {
   const float* kapy;   // windowed k_y
   int nblk;            // row blocks
   SchemeInst sch;      // convection by a finite-difference scheme (used when scheme != 0)
-  int scheme;          // 0: spectral convection; 1, 2, 3: LW, MLW1, MLW2
+  int scheme;          // 0: spectral convection; 1, 2, 3: LW, MLW1, MLW2; 4: NPS
+  NpsInst nps;         // derivatives by the NPS stencils (used when the launch's nps is set)
 };
 
 // One launch of a step kernel over `ninst` instances of one grid size (split into launches
@@ -38,6 +39,7 @@ struct StepLaunch {
   ColPlan plan;
   bool comp;                // compensated state (every instance of the launch)
   int scheme;               // convection scheme of every instance of the launch (Inst::scheme)
+  bool nps;                 // derivatives by the NPS stencils (filter_order 6) in every instance
 };
 
 // Block buffers of the column kernels are kept within 64 KB (in float2 elements).
@@ -57,6 +59,9 @@ int launch_col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngro
 // the finite-difference convection pass of all 32 moving populations (StepLaunch::scheme != 0)
 template <int NY>
 int launch_col_conv_scheme(const StepLaunch& L, hipStream_t s);
+// derivative groups with the NPS stencils (StepLaunch::nps)
+template <int NY>
+int launch_col_nps(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s);
 
 enum : int { RK_STAGE2 = 0, RK_COLLIDE = 1, RK_INIT = 2, RK_SET = 3, RK_MOMENTUM = 4, RK_RESIDUAL = 5 };
 template <int NX>

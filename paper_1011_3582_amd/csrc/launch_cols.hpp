@@ -128,9 +128,31 @@ int launch_col_conv_scheme(const StepLaunch& L, hipStream_t s) {
   return FFTLB_OK;
 }
 
+template <int NY>
+int launch_col_nps(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s) {
+  constexpr int R = 16;
+  static_assert(kMultiSlots * NY <= kColLdsElems, "NPS column tile exceeds the LDS budget");
+  constexpr int NT = col_threads(NY, 1, R);
+  for (int g = 0; g < ngroups; ++g)
+    if (!nps_shape_ok(groups.g[g].nin, groups.g[g].nout)) return FFTLB_EINVAL;
+  const size_t lds = (lds_alloc(kMultiSlots * NY) + NY) * sizeof(float2);
+  for (int first = 0; first < L.ninst; first += kSchemeSlots) {
+    const int count = cmin(kSchemeSlots, L.ninst - first);
+    NpsArgs a{};
+    a.state = L.state;
+    for (int k = 0; k < count; ++k) {
+      a.c[k] = L.inst[first + k]->nps;
+      a.c[k].id = L.id ? L.id[first + k] : 0;
+    }
+    hipLaunchKernelGGL((k_col_nps<NY, NT, R>), dim3(L.nx / 2, ngroups, count), dim3(NT), lds, s, a, groups);
+  }
+  return FFTLB_OK;
+}
+
 #define FFTLB_INSTANTIATE_COLS(NY)                                    \
   template int launch_col_multi<NY>(const StepLaunch&, const ColLaunch&, int, hipStream_t); \
   template int launch_col_conv_multi<NY>(const StepLaunch&, const ColLaunch&, int, int, int, hipStream_t); \
-  template int launch_col_conv_scheme<NY>(const StepLaunch&, hipStream_t);
+  template int launch_col_conv_scheme<NY>(const StepLaunch&, hipStream_t); \
+  template int launch_col_nps<NY>(const StepLaunch&, const ColLaunch&, int, hipStream_t);
 
 }  // namespace fftlb

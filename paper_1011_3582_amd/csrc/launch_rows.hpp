@@ -26,7 +26,12 @@ int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s
     const dim3 grid(L.nblk, count), block(G::NT);
     const RowArgs a = row_args(L, first, count);
     switch (kernel) {
-      case RK_STAGE2: hipLaunchKernelGGL(k_rows_stage2<NX>, grid, block, G::LDS * sizeof(float2), s, a); break;
+      case RK_STAGE2:
+        if (L.nps)
+          hipLaunchKernelGGL((k_rows_stage2<NX, true>), grid, block, G::LDS * sizeof(float2), s, a);
+        else
+          hipLaunchKernelGGL((k_rows_stage2<NX, false>), grid, block, G::LDS * sizeof(float2), s, a);
+        break;
       case RK_COLLIDE:
         if (L.scheme && L.comp)
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, true, true>), grid, block, lds, s, a, in);

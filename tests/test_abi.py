@@ -38,7 +38,7 @@ def test_workspace_bytes_valid(nx, ny):
     dict(nx=80), dict(nx=24), dict(ny=1536), dict(nx=4), dict(ny=2), dict(nx=4096), dict(ny=3000),
     dict(nx=8, ny=8), dict(nx=48, ny=9),
     dict(dt=0.0), dict(dx=-1.0), dict(tau=0.0), dict(tau=math.nan), dict(K=-1.0), dict(b=-0.1),
-    dict(filter_order=6), dict(filter_order=-1), dict(precision=2), dict(precision=-1), dict(q=math.inf),
+    dict(filter_order=7), dict(filter_order=-1), dict(filter_order=6, dy=1.0 / 200.0), dict(precision=2), dict(precision=-1), dict(q=math.inf),
     dict(convection=4), dict(convection=-1),
 ])
 def test_invalid_configs_rejected(change):
@@ -100,3 +100,6 @@ def test_static_derivative_rejects_sizes_beyond_its_scratch():
     cfg = F.Params().config(64, 64)
     assert lib.fftlb_derivative_static(ctypes.byref(cfg), fake, fake, 0, None) == F.FFTLB_EINVAL   # aliasing
     assert lib.fftlb_derivative_static(ctypes.byref(cfg), fake, fake2, 3, None) == F.FFTLB_EINVAL  # bad op
+    cfg = F.Params(m=6).config(64, 64)   # the NPS stencils: not in the static path
+    assert lib.fftlb_derivative_static(ctypes.byref(cfg), fake, fake2, 0, None) == F.FFTLB_EINVAL
+    assert "NPS" in lib.fftlb_last_error().decode()

@@ -126,8 +126,29 @@ def equimolar_radius(rho):
 
 
 def window_name(m):
-    """Name of a derivative order: exact, k1..k4, CD (the central difference, order 5)."""
-    return "exact" if m == 0 else ("CD" if m == 5 else f"k{m}")
+    """Name of a derivative order: exact, k1..k4, CD (the central difference, order 5), NPS
+    (the nine-point stencils, order 6)."""
+    return {0: "exact", 5: "CD", 6: "NPS"}.get(m, f"k{m}")
+
+
+# Discretisations of the comparisons by name: (derivative order, convection scheme), with the
+# paper's legend 'convection' + 'force' for the finite-difference schemes of Sec. 3.1.
+SCHEMES = {"CD+CD": (5, F.CONV_SPECTRAL), "LW+CD": (5, F.CONV_LW), "MLW1+CD": (5, F.CONV_MLW1),
+           "MLW2+CD": (5, F.CONV_MLW2), "NPS+NPS": (6, F.CONV_SPECTRAL)}
+
+
+def scheme(spec):
+    """(derivative order, convection scheme) of a window order (int) or a SCHEMES name."""
+    return (int(spec), F.CONV_SPECTRAL) if isinstance(spec, (int, np.integer)) else SCHEMES[spec]
+
+
+def scheme_name(spec):
+    return window_name(int(spec)) if isinstance(spec, (int, np.integer)) else spec
+
+
+def parse_specs(text):
+    """Comma-separated window orders and scheme names, e.g. "4,CD+CD,LW+CD,NPS+NPS"."""
+    return tuple(int(v) if v.strip().isdigit() else v.strip() for v in text.split(","))
 
 
 def _chunked(b, n_inst, cap, every, record):
@@ -151,7 +172,8 @@ def energy(n=128, orders=(1, 2, 3, 4, 0), cap=200_000, every=2000, seed=0, dt=1e
     rho = (1.0 + 1e-3 * rng.uniform(-1.0, 1.0, (n, n))).astype(np.float32)
     z = np.zeros_like(rho)
     T = np.full_like(rho, 0.85)
-    params = [F.Params(a=A_PAPER, b=B_PAPER, m=m, dt=dt, precision=1) for m in orders]
+    params = [F.Params(a=A_PAPER, b=B_PAPER, m=scheme(m)[0], convection=scheme(m)[1], dt=dt, precision=1)
+              for m in orders]
     b = F.Batch([_tensors(rho, z, z, T) for _ in orders], params)
     area = n * n * params[0].dx * params[0].dy
     series = {m: [] for m in orders}
@@ -170,7 +192,7 @@ def energy(n=128, orders=(1, 2, 3, 4, 0), cap=200_000, every=2000, seed=0, dt=1e
             series[m].append({"t": steps * params[i].dt, "de_T": e - e0[m], "umax": g["umax"]})
         if steps % (10 * every) == 0:
             log(f"energy {time.perf_counter() - t0:.0f} s, {steps} steps: " + ", ".join(
-                f"{window_name(m)}: {series[m][-1]['de_T']}" for m in orders))
+                f"{scheme_name(m)}: {series[m][-1]['de_T']}" for m in orders))
 
     _chunked(b, len(orders), cap, every, record)
     kept = None
@@ -178,12 +200,12 @@ def energy(n=128, orders=(1, 2, 3, 4, 0), cap=200_000, every=2000, seed=0, dt=1e
         kept = {"initial": tuple(a.astype(np.float64) for a in (rho, z, z, T))}
         for i, m in enumerate(orders):
             outs, _ = b.instance(i).moments(globals_=False)
-            kept[window_name(m)] = tuple(o.cpu().numpy().astype(np.float64) for o in outs)
+            kept[scheme_name(m)] = tuple(o.cpu().numpy().astype(np.float64) for o in outs)
     b.close()
-    final = {window_name(m): series[m][-1]["de_T"] for m in orders}
+    final = {scheme_name(m): series[m][-1]["de_T"] for m in orders}
     return {"n": n, "T": 0.85, "a": A_PAPER, "b": B_PAPER, "noise": 1e-3, "seed": seed, "steps": cap, "dt": dt,
             "e_T0": e0, "final_de_T": final,
-            "series": {(window_name(m)): series[m] for m in orders},
+            "series": {(scheme_name(m)): series[m] for m in orders},
             **({"fields": kept} if keep_fields else {})}
 
 
@@ -199,7 +221,8 @@ def triangle(n=128, side=64.0, orders=(1, 2, 3, 4), cap=3_000_000, every=20_000,
     rho = np.where(inside, 1.46, 0.58)
     z = np.zeros_like(rho)
     T = np.full_like(rho, 0.95)
-    params = [F.Params(a=A_PAPER, b=B_PAPER, K=1e-5, m=m, precision=precision) for m in orders]
+    params = [F.Params(a=A_PAPER, b=B_PAPER, K=1e-5, m=scheme(m)[0], convection=scheme(m)[1], precision=precision)
+              for m in orders]
     b = F.Batch([_tensors(rho, z, z, T) for _ in orders], params)
     series = {m: [] for m in orders}
     t0 = time.perf_counter()
@@ -213,7 +236,7 @@ def triangle(n=128, side=64.0, orders=(1, 2, 3, 4), cap=3_000_000, every=20_000,
                 series[m].append({"t": steps * params[i].dt, "umax": None, "residual": None})
         if steps % (10 * every) == 0:
             log(f"triangle {time.perf_counter() - t0:.0f} s, {steps} steps: " + ", ".join(
-                f"k{m}: {series[m][-1]['umax']}" for m in orders))
+                f"{scheme_name(m)}: {series[m][-1]['umax']}" for m in orders))
 
     _chunked(b, len(orders), cap, every, record)
     shapes = {}
@@ -223,11 +246,11 @@ def triangle(n=128, side=64.0, orders=(1, 2, 3, 4), cap=3_000_000, every=20_000,
         rr = _periodic_radius(n, cx, cy)
         mid = 0.5 * (1.46 + 0.58)
         ring = np.abs(r - mid) < 0.15
-        shapes[window_name(m)] = {"radius_mean": float(rr[ring].mean()), "radius_std": float(rr[ring].std())}
+        shapes[scheme_name(m)] = {"radius_mean": float(rr[ring].mean()), "radius_std": float(rr[ring].std())}
     b.close()
     return {"n": n, "side": side, "T": 0.95, "K": 1e-5, "precision": precision, "steps": cap,
-            "final_umax": {window_name(m): series[m][-1]["umax"] for m in orders}, "shape": shapes,
-            "series": {window_name(m): series[m] for m in orders}}
+            "final_umax": {scheme_name(m): series[m][-1]["umax"] for m in orders}, "shape": shapes,
+            "series": {scheme_name(m): series[m] for m in orders}}
 
 
 def sod(nx=768, ny=4, orders=(0, 1, 2, 3, 4), steps=20_000, every=2000):
@@ -278,15 +301,16 @@ def main():
     ap.add_argument("study", choices=["energy", "triangle", "sod"])
     ap.add_argument("--cap", type=int, default=1_000_000)
     ap.add_argument("--dt", type=float, default=1e-5, help="time step of the energy study")
-    ap.add_argument("--orders", default="1,2,3,4,0", help="window orders of the energy study (0: exact k)")
+    ap.add_argument("--orders", default=None,
+                    help="window orders (0: exact k) and scheme names (CD+CD, LW+CD, MLW1+CD, MLW2+CD, NPS+NPS)")
     args = ap.parse_args()
     if args.study == "energy":
-        out = energy(cap=args.cap, dt=args.dt, orders=tuple(int(v) for v in args.orders.split(",")),
+        out = energy(cap=args.cap, dt=args.dt, orders=parse_specs(args.orders or "1,2,3,4,0"),
                      every=max(1000, int(round(2000 * 1e-5 / args.dt))))
     elif args.study == "sod":
         out = sod()
     else:
-        out = triangle(cap=args.cap)
+        out = triangle(cap=args.cap, orders=parse_specs(args.orders or "1,2,3,4"))
     print(json.dumps(out))
 
 

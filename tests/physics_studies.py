@@ -14,10 +14,15 @@ under profiles/.
   coexistence(): slabs started with the densities of a temperature 0.02 T_c higher than
       their own relax to the coexistence curve of the Maxwell construction (Sec. 4.1, the
       temperature steps of the coexistence-curve study);
-  energy(): Delta e_T of the phase separation for k1..k4 and exact k, also measured with one
-      common (exact-gradient) energy definition.
+  energy(): Delta e_T of the phase separation for k1..k4 and exact k (or any window orders and
+      finite-difference schemes), also measured with one common (exact-gradient) energy
+      definition;
+  spurious(): the spurious velocities of planar interfaces (Sec. 4.1, the paper's Figs. 10, 12
+      and 14) for the k4 window and the finite-difference schemes (NPS, MLW2, LW, CD), with the
+      bulk densities against the Maxwell construction.
 
-Usage (one MI355X): python tests/physics_studies.py laplace|profile|coexistence|energy [--cap N]
+Usage (one MI355X):
+  python tests/physics_studies.py laplace|profile|coexistence|energy|spurious [--cap N] [--orders ...]
 """
 import argparse
 import json
@@ -186,6 +191,65 @@ def energy(cap=500_000, orders=(1, 2, 3, 4, 0)):
     return res
 
 
+def spurious(cases=((0.93, 0.0), (0.93, 5e-6), (0.85, 5e-6)), orders=(4, "NPS+NPS", "MLW2+CD", "LW+CD", "CD+CD"),
+             nx=512, ny=4, cap=1_000_000, every=50_000):
+    """Planar interfaces (Sec. 4.1): slabs with liquid in nx/4 < x <= 3nx/4 at each (T/T_c, K) of
+    `cases`, started at the Maxwell coexistence densities of T with the equilibrium profile
+    (K > 0) or a tanh of width 1.5 grid units (K = 0, where the equilibrium interface is sharp),
+    u = 0; every case with every discretisation in one batch for cap steps.  u^s = max |u|
+    against time, the final u_x(x) (mean over y) and the bulk densities against Maxwell's."""
+    t_c = 8 * A / (27 * B)
+    x = np.arange(nx, dtype=np.float64)
+    dist = np.minimum(x - nx / 4.0, 3.0 * nx / 4.0 - x)   # grid units, > 0 in the liquid
+    fields, params, keys = [], [], []
+    for tr, K in cases:
+        T = tr * t_c
+        mv, ml = thermo.maxwell(T, A, B)
+        dx = F.Params().dx
+        prof = (thermo.planar_profile(dist * dx, T, A, B, K) if K > 0
+                else 0.5 * (ml + mv) + 0.5 * (ml - mv) * np.tanh(dist / 1.5))
+        for spec in orders:
+            m, conv = V.scheme(spec)
+            fields.append(V.slab_start(nx, ny, prof, T))
+            params.append(F.Params(a=A, b=B, K=K, m=m, convection=conv, precision=1))
+            keys.append((tr, K, V.scheme_name(spec)))
+    b = F.Batch([tuple(torch_from(a) for a in f) for f in fields], params)
+    series = [[] for _ in keys]
+
+    def record(steps):
+        for i in range(len(keys)):
+            try:
+                series[i].append((steps * params[i].dt, b.instance(i).poll()["umax"]))
+            except F.FFTLBError:
+                series[i].append((steps * params[i].dt, None))
+        if steps % (4 * every) == 0:
+            log(f"spurious {steps} steps: " + ", ".join(f"{k[2]}@{k[0]},{k[1]:g}: {s[-1][1]}" for k, s in
+                                                        zip(keys, series)))
+
+    V._chunked(b, len(keys), cap, every, record)
+    rows = []
+    for i, (tr, K, name) in enumerate(keys):
+        row = {"T/Tc": tr, "K": K, "scheme": name, "umax": series[i][-1][1],
+               "umax_series": series[i]}
+        if row["umax"] is not None:
+            (rho, ux, _, T), _ = b.instance(i).moments(globals_=False)
+            rho = rho.cpu().numpy().astype(np.float64)
+            ux = ux.cpu().numpy().astype(np.float64).mean(axis=0)
+            t_end = float(T.cpu().numpy().astype(np.float64).mean())
+            rv, rl = V.bulk_densities(rho)
+            mv, ml = thermo.maxwell(t_end, A, B)
+            row.update({"T_end": t_end, "rho_v": rv, "rho_l": rl, "maxwell_v": mv, "maxwell_l": ml,
+                        "ux_profile": ux.tolist(), "ux_argmax": int(np.argmax(np.abs(ux)))})
+        rows.append(row)
+    b.close()
+    return {"nx": nx, "ny": ny, "steps": cap, "cases": rows}
+
+
+def torch_from(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+
+
 def sod():
     """The modified Sod tube (paper_1011_3582_amd.validation.sod) against the exact Riemann
     solution of the gamma = 2 ideal gas at t = 0.2: for each window, the L1 errors of rho, u,
@@ -226,11 +290,19 @@ def sod():
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod"])
+    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod", "spurious"])
     ap.add_argument("--cap", type=int, default=1_000_000)
+    ap.add_argument("--orders", default=None, help="window orders and scheme names (energy, spurious)")
     args = ap.parse_args()
     if args.study == "sod":
         print(json.dumps(sod()))
+        return
+    if args.orders and args.study in ("energy", "spurious"):
+        fn = energy if args.study == "energy" else spurious
+        print(json.dumps(fn(cap=args.cap, orders=V.parse_specs(args.orders))))
+        return
+    if args.study == "spurious":
+        print(json.dumps(spurious(cap=args.cap)))
         return
     fn = {"laplace": laplace, "coexistence": coexistence, "profile": profile, "energy": energy}[args.study]
     print(json.dumps(fn(cap=args.cap)))

@@ -19,7 +19,9 @@ under profiles/.
       definition;
   spurious(): the spurious velocities of planar interfaces (Sec. 4.1, the paper's Figs. 10, 12
       and 14) for the k4 window and the finite-difference schemes (NPS, MLW2, LW, CD), with the
-      bulk densities against the Maxwell construction.
+      bulk densities against the Maxwell construction;
+  droplet_currents(): the spurious currents of a circular droplet started at equilibrium
+      (Sec. 4.2, Fig. 19) for k1..k4, NPS and CD.
 
 Usage (one MI355X):
   python tests/physics_studies.py laplace|profile|coexistence|energy|spurious [--cap N] [--orders ...]
@@ -245,6 +247,39 @@ def spurious(cases=((0.93, 0.0), (0.93, 5e-6), (0.85, 5e-6)), orders=(4, "NPS+NP
     return {"nx": nx, "ny": ny, "steps": cap, "cases": rows}
 
 
+def droplet_currents(n=128, R=24.0, t_ratio=0.95, K=1e-5, orders=(1, 2, 3, 4, "NPS+NPS", "CD+CD"),
+                     cap=3_000_000, every=100_000):
+    """The spurious currents of a circular interface (Sec. 4.2, Figs. 18-19) without the relaxation
+    flow of a deformed start: a droplet of radius R (grid units) started from the planar
+    equilibrium profile at T (rho = 1.46 / 0.58 is the paper's triangle at T = 0.95), u = 0, run
+    for cap steps with each discretisation; u^s_max against time."""
+    T = t_ratio * 8 * A / (27 * B)
+    dx = F.Params().dx
+    prof = lambda s_, K=K: thermo.planar_profile(s_, T, A, B, K)
+    fields, params = [], []
+    for spec in orders:
+        m, conv = V.scheme(spec)
+        fields.append(V.droplet_from_profile(n, R, prof, T, dx))
+        params.append(F.Params(a=A, b=B, K=K, m=m, convection=conv, precision=1))
+    b = F.Batch([tuple(torch_from(a) for a in f) for f in fields], params)
+    series = [[] for _ in orders]
+
+    def record(steps):
+        for i in range(len(orders)):
+            try:
+                series[i].append((steps * params[i].dt, b.instance(i).poll()["umax"]))
+            except F.FFTLBError:
+                series[i].append((steps * params[i].dt, None))
+        if steps % (5 * every) == 0:
+            log(f"droplet {steps} steps: " + ", ".join(f"{V.scheme_name(o)}: {s_[-1][1]}" for o, s_ in
+                                                       zip(orders, series)))
+
+    V._chunked(b, len(orders), cap, every, record)
+    b.close()
+    return {"n": n, "R": R, "T/Tc": t_ratio, "K": K, "steps": cap,
+            "umax": {V.scheme_name(o): s_ for o, s_ in zip(orders, series)}}
+
+
 def torch_from(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
@@ -290,7 +325,7 @@ def sod():
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod", "spurious"])
+    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod", "spurious", "droplet"])
     ap.add_argument("--cap", type=int, default=1_000_000)
     ap.add_argument("--orders", default=None, help="window orders and scheme names (energy, spurious)")
     args = ap.parse_args()
@@ -303,6 +338,9 @@ def main():
         return
     if args.study == "spurious":
         print(json.dumps(spurious(cap=args.cap)))
+        return
+    if args.study == "droplet":
+        print(json.dumps(droplet_currents(cap=args.cap)))
         return
     fn = {"laplace": laplace, "coexistence": coexistence, "profile": profile, "energy": energy}[args.study]
     print(json.dumps(fn(cap=args.cap)))

@@ -80,7 +80,10 @@ extern "C" {
  *  convection    scheme of the convection term v.grad f: 0 = the derivative operator of
  *                filter_order (windowed FFT, or CD with filter_order 5); 1 = Lax-Wendroff
  *                (Sec. 3.1, Eq. (ML-)); 2 = MLW1, LW plus the dispersion correction R3 (Eq. (R3));
- *                3 = MLW2, LW plus R3 and the dissipation correction R4 (Eq. (R4=)).  The
+ *                3 = MLW2, LW plus R3 and the dissipation correction R4 (Eq. (R4=)); 4 = the flux
+ *                limiter with the MCD limiter along each population's characteristic line (Sec. 3.1,
+ *                Eq. (FL); dx must equal dy), computed in real space and taken to spectra by row
+ *                transforms (32 more planes of workspace).  For 1..3 the
  *                one-dimensional stencils act along x and along y and their updates add; the
  *                CFL numbers are c = v_x dt/dx and v_y dt/dy.  On the periodic grid every such
  *                stencil is a multiplication of the spectrum, applied in a column pass over all

@@ -30,6 +30,7 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   R10 the initial distribution is f^eq(rho0, u0, T0);
   R23 the one-dimensional finite-difference schemes of Sec. 3.1 (LW, MLW1, MLW2) act along
       x with c = v_x dt/dx and along y with c = v_y dt/dy, and their updates add;
+  R26 flux limiter: where g_{J+1} = g_J the limited term of the flux is zero (theta undefined);
   R24 with the NPS stencils the Laplacian of the pressure tensor is the nine-point one, the
       derivatives of theta are compositions of first derivatives, and the convection term is
       v_x D_x f + v_y D_y f with the nine-point first derivatives.
@@ -63,7 +64,7 @@ class Params:
     The paper's values are dx = dy = 1/256, dt = 1e-5, tau = 1e-2, K = 1e-5,
     H = 0, zeta = 0, q = -0.004 and the k4 window (m = 4); its EOS is a = 9/8,
     b = 1/3.  m = 0 selects the exact wavenumber k.  conv = 0 takes the convection term
-    with the derivative operator of m; LAX_WENDROFF, MLW1 or MLW2 with that
+    with the derivative operator of m; LAX_WENDROFF, MLW1, MLW2 or FLUX_LIMITER with that
     finite-difference scheme of Sec. 3.1.
     """
     dx: float = 1.0 / 256.0
@@ -293,6 +294,9 @@ def _nps_laplacian(g):
 # Fig. 2 (with the central difference for the force): Lax-Wendroff, Eq. (ML-); MLW1 adds the
 # discretised dispersion term R3, Eq. (R3); MLW2 adds R3 and the dissipation term R4, Eq. (R4=).
 LAX_WENDROFF, MLW1, MLW2 = 1, 2, 3
+# The flux-limiter scheme of Sec. 3.1: the convection of each population along its
+# characteristic line (its own lattice direction), with the MCD limiter.
+FLUX_LIMITER = 4
 
 
 def fd_convection_update(g, c, axis, scheme):
@@ -317,6 +321,43 @@ def fd_convection_update(g, c, axis, scheme):
     return du
 
 
+def mcd_limiter(theta):
+    """psi(theta) of the monotonized central-difference limiter (Sec. 3.1): 0 for theta <= 0,
+    2 theta up to 1/3, (1 + theta)/2 up to 3, 2 beyond."""
+    theta = np.asarray(theta, dtype=np.float64)
+    return np.where(theta <= 0.0, 0.0,
+                    np.where(theta <= 1.0 / 3.0, 2.0 * theta, np.where(theta <= 3.0, 0.5 * (1.0 + theta), 2.0)))
+
+
+def _along(g, e, n):
+    """g at J + n e on the periodic grid (e = (ex, ey) a lattice step; arrays are [y, x])."""
+    return np.roll(np.roll(g, -n * e[1], axis=0), -n * e[0], axis=1)
+
+
+def fl_convection_update(g, c, e, limiter=mcd_limiter):
+    """Change of g in one forward-Euler step from its convection along the characteristic line
+    through every node (Sec. 3.1, Eq. (FL)): J +- 1 are the neighbours at J +- e, c the CFL number
+    v_k dt / (A_i dr) of the line.  With theta_J = (g_J - g_{J-1}) / (g_{J+1} - g_J),
+      F_{J+1/2} = g_J + (1 - c)/2 (g_{J+1} - g_J) psi(theta_J),   F_{J-1/2} = F_{(J-1)+1/2},
+    and the change is -c (F_{J+1/2} - F_{J-1/2}).  Where g_{J+1} = g_J, theta is undefined and
+    the limited term (g_{J+1} - g_J) psi vanishes with its factor (reading R26)."""
+    def flux(gm, g0, gp):
+        den = gp - g0
+        safe = np.where(den != 0.0, den, 1.0)
+        theta = np.where(den != 0.0, (g0 - gm) / safe, 0.0)
+        return g0 + 0.5 * (1.0 - c) * den * limiter(theta)
+    gp1, gm1, gm2 = _along(g, e, 1), _along(g, e, -1), _along(g, e, -2)
+    return -c * (flux(gm1, g, gp1) - flux(gm2, gm1, g))
+
+
+def characteristic(v):
+    """Lattice step e and factor A_i of a velocity of Eq. (1): e = the signs of its components,
+    A_i = 1 along an axis, sqrt(2) along a diagonal (Sec. 3.1)."""
+    ex = int(np.sign(round(v[0], 9)))
+    ey = int(np.sign(round(v[1], 9)))
+    return (ex, ey), (math.sqrt(2.0) if ex and ey else 1.0)
+
+
 def convection(f, v, D: Deriv, p: Params | None = None):
     """Convection term v_q . grad f_q by windowed FFT (Sec. 3.6, Fig. 3 flow chart).
 
@@ -329,7 +370,14 @@ def convection(f, v, D: Deriv, p: Params | None = None):
     """
     out = np.zeros_like(f)
     scheme = p.conv if p is not None else 0
+    if scheme == FLUX_LIMITER and p.dx != p.dy:
+        raise ValueError("the flux-limiter scheme needs dx = dy")
     for q in range(1, f.shape[0]):
+        if scheme == FLUX_LIMITER:
+            e, A = characteristic(v[q])
+            speed = math.hypot(v[q, 0], v[q, 1])
+            out[q] = -fl_convection_update(f[q], speed * p.dt / (A * p.dx), e) / p.dt
+            continue
         if scheme:
             du = (fd_convection_update(f[q], v[q, 0] * p.dt / p.dx, 1, scheme)
                   + fd_convection_update(f[q], v[q, 1] * p.dt / p.dy, 0, scheme))

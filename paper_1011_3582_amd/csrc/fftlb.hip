@@ -16,6 +16,7 @@
 #include "fftlb.h"
 #include "launch.hpp"
 #include "reduce.hpp"
+#include "stencil.hpp"
 
 using namespace fftlb;
 
@@ -94,12 +95,14 @@ bool config_ok(const fftlb_config* c) {
   // the nine-point Laplacian of the NPS stencils is defined on a square lattice
   if (c->filter_order == 6 && c->dx != c->dy) return false;
   if (c->precision != 0 && c->precision != 1) return false;
-  if (c->convection < 0 || c->convection > 3) return false;
+  if (c->convection < 0 || c->convection > 4) return false;
+  // the characteristic lines of the flux limiter have steps dr and sqrt(2) dr
+  if (c->convection == 4 && c->dx != c->dy) return false;
   return true;
 }
 
 struct Layout {
-  size_t f, flo, sf, spec, macro, cpl, twx, twy, kx, ky, scx, scy, pd, pf, gl, total;
+  size_t f, flo, sf, flr, spec, macro, cpl, twx, twy, kx, ky, scx, scy, pd, pf, gl, total;
 };
 
 // Planes of the spectral block (contiguous, so that a column pass addresses them by index).
@@ -125,6 +128,7 @@ Layout make_layout(const fftlb_config& c) {
   L.f = take(33 * plane);
   L.flo = take(c.precision == 1 ? 33 * plane : 0);
   L.sf = take(32 * plane);
+  L.flr = take(c.convection == 4 ? 32 * plane : 0);
   L.spec = take((SB_PLANES + (c.filter_order == 6 ? SB_NPS_EXTRA : 0)) * plane);
   L.macro = take(4 * plane);
   L.cpl = take(plane);
@@ -331,6 +335,17 @@ int col_conv_scheme(const StepLaunch& L, hipStream_t s) {
 }
 
 // Real plane -> packed row spectra, and back, for an instance's grid, twiddles and k_x table.
+int rows_forward_real_pair(const Inst& I, int nx, const float* a, const float* b, float2* sa, float2* sb,
+                           hipStream_t s) {
+  switch (nx) {
+#define X(n) \
+  case n: return launch_rows_forward_real<n>(I.nblk, a, b, sa, sb, I.P.sg, I.P.twx, s);
+    FFTLB_FOR_ROW_SIZES(X)
+#undef X
+  }
+  return FFTLB_EINVAL;
+}
+
 int rows_forward_real(const Inst& I, int nx, const float* a, float2* sa, hipStream_t s) {
   switch (nx) {
 #define X(n) \
@@ -379,10 +394,31 @@ int stage1_columns(const StepLaunch& L, hipStream_t s) {
   return L.nps ? col_multi(L, kStage1Nps, 4, s) : col_multi(L, kStage1, 3, s);
 }
 
+// The flux-limiter convection of every instance of a launch: the real-space kernel, then the row
+// transforms of its 32 planes into the population spectra (which the collide takes as they are).
+int conv_flux_limiter(const StepLaunch& L, hipStream_t s) {
+  for (int k = 0; k < L.ninst; ++k) {
+    const Inst& I = *L.inst[k];
+    FlArgs a = I.fl;
+    a.id = L.id ? L.id[k] : 0;
+    hipLaunchKernelGGL(k_conv_fl, dim3((L.nx + 255) / 256, L.ny, 32), dim3(256), 0, s, a, L.state);
+    const long plane = (long)L.nx * L.ny, hp = plane / 2;
+    for (int p = 0; p < 32; p += 2)
+      RC_TRY(rows_forward_real_pair(I, L.nx, a.out + p * plane, a.out + (p + 1) * plane, I.P.sf + p * hp,
+                                    I.P.sf + (p + 1) * hp, s));
+  }
+  return FFTLB_OK;
+}
+
 // With a finite-difference convection scheme the derivative column passes run by themselves
-// and the scheme's column pass of all 32 moving populations follows the stage-1 pass.
+// and the scheme's convection pass of all 32 moving populations follows the stage-1 pass.
 int enqueue_stage(const StepLaunch& L, int stage, hipStream_t s) {
-  if (L.scheme) {
+  if (L.scheme == 4) {
+    switch (stage) {
+      case ST_CONV_S1: RC_TRY(stage1_columns(L, s)); return conv_flux_limiter(L, s);
+      case ST_S2_COLS: return col_multi(L, kStage2, 2, s);
+    }
+  } else if (L.scheme) {
     switch (stage) {
       case ST_CONV_S1: RC_TRY(stage1_columns(L, s)); return col_conv_scheme(L, s);
       case ST_S2_COLS: return col_multi(L, kStage2, 2, s);
@@ -856,8 +892,9 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   M.scale = (float)(1.0 / ((double)h->nx * h->ny));
 
   // convection by a finite-difference scheme: LW (1), MLW1 = LW + R3 (2), MLW2 = LW + R3 + R4 (3),
-  // or with the NPS stencils (filter_order 6 and convection 0) the NPS first derivatives (4)
-  I.scheme = cfg->convection ? cfg->convection : cfg->filter_order == 6 ? 4 : 0;
+  // the flux limiter (4), or with the NPS stencils (filter_order 6 and convection 0) the NPS
+  // first derivatives (5)
+  I.scheme = cfg->convection ? cfg->convection : cfg->filter_order == 6 ? 5 : 0;
   SchemeInst& S = I.sch;
   S.spec = P.sf;
   S.twy = I.twy;
@@ -871,7 +908,15 @@ int init_handle(const fftlb_config* cfg, void* workspace, size_t ws_bytes, const
   S.r3 = cfg->convection >= 2 ? 1.0f : 0.0f;
   S.r4 = cfg->convection >= 3 ? 1.0f : 0.0f;
   S.sdt = (float)(1.0 / ((double)h->nx * h->ny * cfg->dt));
-  S.nps = I.scheme == 4 ? 1 : 0;
+  S.nps = I.scheme == 5 ? 1 : 0;
+  FlArgs& FA = I.fl;
+  FA.f = P.f;
+  FA.out = cfg->convection == 4 ? reinterpret_cast<float*>(ws + L.flr) : nullptr;
+  FA.nx = h->nx;
+  FA.ny = h->ny;
+  FA.id = 0;
+  FA.cf = (float)(cfg->dt / cfg->dx);
+  FA.rdr = (float)(1.0 / cfg->dx);
   NpsInst& N = I.nps;
   N.spec = I.spec;
   N.twy = I.twy;

@@ -885,6 +885,32 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
   col_multi_tile<NY, CW, NT, R>(In, L.g[blockIdx.y], lds, blockIdx.x, gridDim.x);
 }
 
+// Convection by the flux-limiter scheme of Sec. 3.1: each population is convected along its
+// own lattice direction e (the characteristic line; A = 1 along an axis, sqrt(2) along a
+// diagonal) with CFL number c = v_k dt / (A dr):
+//   C = v_k / (A dr) [F_{J+1/2} - F_{J-1/2}],  F_{J+1/2} = f_J + (1 - c)/2 psi(theta_J) (f_{J+1} - f_J),
+// theta_J = (f_J - f_{J-1}) / (f_{J+1} - f_J), J +- 1 the nodes at J +- e.  The MCD limiter
+// (0 for theta <= 0, 2 theta up to 1/3, (1 + theta)/2 up to 3, 2 beyond) times the difference
+// it multiplies is, with a = f_J - f_{J-1}, b = f_{J+1} - f_J: 0 when a b <= 0, otherwise
+// sign(b) min(2|a|, |a + b|/2, 2|b|) (the same values without the division; zero when b = 0).
+// The limiter makes the scheme nonlinear, so it runs in real space (k_conv_fl, stencil.hpp):
+// one thread per site and population, writing the real convection planes that row transforms
+// then take to spectra.
+struct FlArgs {
+  const float* f;          // [33][ny][nx] f^n (the high part of a compensated state)
+  float* out;              // [32][ny][nx] convection terms of the moving populations
+  int nx, ny, id;
+  float cf;                // dt / dr
+  float rdr;               // 1 / dr
+};
+
+__device__ __forceinline__ float mcd_limited(float a, float b) {
+  if (!(a * b > 0.0f)) return 0.0f;
+  const float m = fminf(fminf(2.0f * fabsf(a), 0.5f * fabsf(a + b)), 2.0f * fabsf(b));
+  return copysignf(m, b);
+}
+
+
 // Derivative groups with the nine-point stencils of the NPS scheme (Sec. 3.1): A = 1/3,
 // B = 1/12 for the first derivative, E = 2/3, F = 1/6 for the Laplacian.  On the periodic grid
 // each stencil is a multiplication of the spectrum; with s = sin(theta), e = cos(theta) - 1 of

@@ -24,8 +24,9 @@ struct Inst {
   const float* kapy;   // windowed k_y
   int nblk;            // row blocks
   SchemeInst sch;      // convection by a finite-difference scheme (used when scheme != 0)
-  int scheme;          // 0: spectral convection; 1, 2, 3: LW, MLW1, MLW2; 4: NPS
+  int scheme;          // 0: spectral convection; 1, 2, 3: LW, MLW1, MLW2; 4: flux limiter; 5: NPS
   NpsInst nps;         // derivatives by the NPS stencils (used when the launch's nps is set)
+  FlArgs fl;           // the flux-limiter convection (scheme 4)
 };
 
 // One launch of a step kernel over `ninst` instances of one grid size (split into launches

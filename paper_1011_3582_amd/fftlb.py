@@ -44,7 +44,7 @@ class Config(ctypes.Structure):
 
 
 # convection schemes (fftlb_config.convection)
-CONV_SPECTRAL, CONV_LW, CONV_MLW1, CONV_MLW2 = 0, 1, 2, 3
+CONV_SPECTRAL, CONV_LW, CONV_MLW1, CONV_MLW2, CONV_FL = 0, 1, 2, 3, 4
 
 
 class Plan(ctypes.Structure):
@@ -72,7 +72,7 @@ class Params:
     b: float = 0.4
     m: int = 4
     precision: int = 0   # 0: f stored in FP32; 1: compensated hi + lo (see fftlb_config)
-    convection: int = 0  # CONV_SPECTRAL, or the finite-difference scheme CONV_LW / CONV_MLW1 / CONV_MLW2
+    convection: int = 0  # CONV_SPECTRAL, or the finite-difference scheme CONV_LW / CONV_MLW1 / CONV_MLW2 / CONV_FL
 
     def config(self, nx: int, ny: int) -> Config:
         return Config(nx, ny, self.dx, self.dy, self.dt, self.tau, self.K, self.H, self.zeta, self.q,

@@ -134,7 +134,7 @@ def window_name(m):
 # Discretisations of the comparisons by name: (derivative order, convection scheme), with the
 # paper's legend 'convection' + 'force' for the finite-difference schemes of Sec. 3.1.
 SCHEMES = {"CD+CD": (5, F.CONV_SPECTRAL), "LW+CD": (5, F.CONV_LW), "MLW1+CD": (5, F.CONV_MLW1),
-           "MLW2+CD": (5, F.CONV_MLW2), "NPS+NPS": (6, F.CONV_SPECTRAL)}
+           "MLW2+CD": (5, F.CONV_MLW2), "FL+CD": (5, F.CONV_FL), "NPS+NPS": (6, F.CONV_SPECTRAL)}
 
 
 def scheme(spec):

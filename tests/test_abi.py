@@ -39,7 +39,7 @@ def test_workspace_bytes_valid(nx, ny):
     dict(nx=8, ny=8), dict(nx=48, ny=9),
     dict(dt=0.0), dict(dx=-1.0), dict(tau=0.0), dict(tau=math.nan), dict(K=-1.0), dict(b=-0.1),
     dict(filter_order=7), dict(filter_order=-1), dict(filter_order=6, dy=1.0 / 200.0), dict(precision=2), dict(precision=-1), dict(q=math.inf),
-    dict(convection=4), dict(convection=-1),
+    dict(convection=5), dict(convection=-1), dict(convection=4, dy=1.0 / 200.0),
 ])
 def test_invalid_configs_rejected(change):
     cfg = F.Params().config(64, 64)

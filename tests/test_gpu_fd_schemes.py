@@ -1,7 +1,8 @@
 """The finite-difference convection schemes of Sec. 3.1 (fftlb_config.convection: LW, MLW1,
-MLW2, with the central difference for the force, filter_order 5) against the FP64 oracle, which
-applies them as the printed stencils in real space; the HIP path applies each as its Fourier
-symbol in a column pass over all 32 moving populations."""
+MLW2, FL, with the central difference for the force, filter_order 5) against the FP64 oracle,
+which applies them as the printed stencils in real space; the HIP path applies LW, MLW1 and
+MLW2 as their Fourier symbols in a column pass over all 32 moving populations, and the flux
+limiter (nonlinear) in a real-space kernel along each population's characteristic line."""
 import math
 import sys
 
@@ -15,7 +16,7 @@ from paper_1011_3582_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 F = None
-SCHEMES = (1, 2, 3)   # LW, MLW1, MLW2
+SCHEMES = (1, 2, 3, 4)   # LW, MLW1, MLW2, FL
 
 
 @pytest.fixture(autouse=True, scope="module")
@@ -75,13 +76,13 @@ def test_one_step_from_shared_state(scheme, ny, nx):
 
 
 def test_each_scheme_term_matches():
-    """The differences LW - CD, MLW1 - LW (the R3 term) and MLW2 - MLW1 (the R4 term) of one step
-    from the same state: a sharp slab and dt = 4e-4 (CFL numbers up to 0.44), where each term is
-    1e-4..1e-3 of the state, far above FP32 rounding."""
+    """The differences LW - CD, MLW1 - LW (the R3 term), MLW2 - MLW1 (the R4 term) and FL - CD of
+    one step from the same state: a sharp slab and dt = 4e-4 (CFL numbers up to 0.44), where each
+    term is 1e-4..1e-3 of the state, far above FP32 rounding."""
     fld = W.slab(64, 64, t_ratio=0.9, width=2.0, noise=1e-3, seed=2)
     out, ref = {}, {}
     f0 = None
-    for conv in (0, 1, 2, 3):
+    for conv in (0, 1, 2, 3, 4):
         p = F.Params(m=5, dt=4e-4, convection=conv)
         with solver(fld, p) as s:
             g0 = state64(s)
@@ -92,7 +93,7 @@ def test_each_scheme_term_matches():
             out[conv] = state64(s)
         ref[conv] = O.step(f0, oparams(p))
     scale = np.abs(ref[0]).max()
-    for a, b, name in ((1, 0, "LW - CD"), (2, 1, "R3"), (3, 2, "R4")):
+    for a, b, name in ((1, 0, "LW - CD"), (2, 1, "R3"), (3, 2, "R4"), (4, 0, "FL - CD")):
         dg, do = out[a] - out[b], ref[a] - ref[b]
         err = np.abs(dg - do).max()
         sys.stderr.write(f"[{name}] max {np.abs(do).max() / scale:.2e}, err {err / scale:.2e} of the state\n")
@@ -128,7 +129,7 @@ def test_batch_of_mixed_schemes_is_bitwise_solo():
     """Instances of one grid size with different convection schemes share a batch (grouped by
     scheme): each evolves bitwise as it does alone."""
     flds = [W.smooth_random(64, 64, seed=40 + k, T0=1.2) for k in range(4)]
-    schemes = [0, 1, 3, 1]
+    schemes = [0, 1, 3, 4]
     params = [F.Params(m=5, convection=c) for c in schemes]
     b = F.Batch([tuple(torch.from_numpy(a) for a in (f.rho, f.ux, f.uy, f.T)) for f in flds], params=params)
     try:

@@ -15,6 +15,8 @@ outside their formulas:
     MLW2's to the fourth-order one (-g[J+2] + 8 g[J+1] - 8 g[J-1] + g[J-2]) / 12;
   * in a full step, populations moving along y only are changed only by the y stencil.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -128,3 +130,90 @@ def test_step_convection_acts_per_axis(scheme):
 def test_unknown_scheme_rejected():
     with pytest.raises(ValueError):
         O.fd_convection_update(np.zeros(8), 0.1, 0, 4)
+
+
+# ---------------------------------------------------------------------------
+# Flux limiter (Sec. 3.1, MCD limiter along characteristic lines)
+# ---------------------------------------------------------------------------
+
+AXES = [(1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+
+
+def _field(ny=12, nx=16, seed=7):
+    return np.random.default_rng(seed).standard_normal((ny, nx))
+
+
+@pytest.mark.parametrize("e", AXES)
+def test_fl_unit_cfl_is_an_exact_shift(e):
+    # c = 1: F_{J+1/2} = g_J whatever psi, so g moves one node along e
+    g = _field()
+    out = g + O.fl_convection_update(g, 1.0, e)
+    assert np.allclose(out, O._along(g, e, -1), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("e", [(1, 0), (0, 1), (-1, 0), (0, -1)])
+def test_fl_limiter_one_is_lax_wendroff_and_zero_is_upwind(e):
+    # the paper: psi = 1 gives the LW scheme, psi = 0 the first-order upwind scheme
+    g = _field()
+    c = 0.37
+    axis = 1 if e[0] else 0
+    cs = c * (e[0] or e[1])     # signed CFL number along the axis
+    lw = O.fl_convection_update(g, c, e, limiter=lambda t: np.ones_like(t))
+    assert np.allclose(lw, O.fd_convection_update(g, cs, axis, O.LAX_WENDROFF), rtol=0, atol=1e-13)
+    up = O.fl_convection_update(g, c, e, limiter=lambda t: np.zeros_like(t))
+    assert np.allclose(up, -c * (g - O._along(g, e, -1)), rtol=0, atol=1e-13)
+
+
+def test_mcd_limiter_values():
+    th = np.array([-1.0, 0.0, 0.1, 1.0 / 3.0, 0.5, 1.0, 3.0, 5.0])
+    want = np.array([0.0, 0.0, 0.2, 2.0 / 3.0, 0.75, 1.0, 2.0, 2.0])
+    assert np.allclose(O.mcd_limiter(th), want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("e", [(1, 0), (1, 1)])
+def test_fl_is_total_variation_diminishing(e):
+    # a square pulse advected 200 steps at c = 0.6: no new extrema, variation does not grow
+    ny, nx = 8, 64
+    g = np.zeros((ny, nx))
+    g[:, 20:30] = 1.0
+    g[2:5, :] += 0.5 * (e[1] != 0)
+    tv0 = np.abs(np.diff(g, axis=1)).sum()
+    lo, hi = g.min(), g.max()
+    for _ in range(200):
+        g = g + O.fl_convection_update(g, 0.6, e)
+        assert g.min() >= lo - 1e-12 and g.max() <= hi + 1e-12
+    if e == (1, 0):
+        assert np.abs(np.diff(g, axis=1)).sum() <= tv0 + 1e-12
+
+
+def test_fl_conserves_the_sum_and_is_second_order_on_smooth_data():
+    for e in AXES:
+        g = _field(seed=11)
+        assert abs(O.fl_convection_update(g, 0.4, e).sum()) < 1e-12
+    # one step of a smooth wave along x: error against exact translation falls ~ 4x per halving
+    errs = []
+    for n in (64, 128, 256):
+        x = np.arange(n) / n
+        g = np.tile(np.sin(2 * np.pi * x) + 2.0, (4, 1))
+        c = 0.5
+        steps = n // 8                      # the same physical time
+        for _ in range(steps):
+            g = g + O.fl_convection_update(g, c, (1, 0))
+        exact = np.sin(2 * np.pi * (x - c * steps / n)) + 2.0
+        errs.append(np.abs(g[0] - exact).mean())
+    order = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    assert min(order) > 1.5, order
+
+
+def test_fl_step_uses_each_population_s_line():
+    ny, nx = 8, 16
+    rng = np.random.default_rng(3)
+    f = 1.0 + 0.01 * rng.standard_normal((O.Q, ny, nx))
+    p = O.Params(conv=O.FLUX_LIMITER, m=O.CENTRAL_DIFFERENCE)
+    v = O.velocities()
+    C = O.convection(f, v, O.Deriv(ny, nx, p), p)
+    for q in (1, 2, 4, 10):
+        e, A = O.characteristic(v[q])
+        c = math.hypot(*v[q]) * p.dt / (A * p.dx)
+        assert np.allclose(-p.dt * C[q], O.fl_convection_update(f[q], c, e), rtol=0, atol=1e-15)
+    assert O.characteristic(v[2]) == ((1, 1), math.sqrt(2.0))

@@ -898,7 +898,9 @@ __global__ __launch_bounds__(NT, 4) void k_col_multi(ColArgs A, ColLaunch L) {
 // then take to spectra.
 struct FlArgs {
   const float* f;          // [33][ny][nx] f^n (the high part of a compensated state)
-  float* out;              // [32][ny][nx] convection terms of the moving populations
+  float* out;              // [32][ny][nx] convection terms of the moving populations, times 1/nx
+                           // (the unnormalised forward and inverse row transforms they pass
+                           // through on the way to the collide multiply by nx)
   int nx, ny, id;
   float cf;                // dt / dr
   float rdr;               // 1 / dr

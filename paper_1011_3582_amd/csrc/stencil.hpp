@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_conv_fl(FlArgs A, const int* state) {
   const float f0 = at(0), fp1 = at(1), fm1 = at(-1), fm2 = at(-2);
   const float fp = f0 + 0.5f * (1.0f - c) * mcd_limited(f0 - fm1, fp1 - f0);
   const float fm = fm1 + 0.5f * (1.0f - c) * mcd_limited(fm1 - fm2, f0 - fm1);
-  A.out[(long)(q - 1) * nx * ny + (long)y * nx + x] = speed * A.rdr / a_i * (fp - fm);
+  A.out[(long)(q - 1) * nx * ny + (long)y * nx + x] = speed * A.rdr / (a_i * nx) * (fp - fm);
 }
 
 }  // namespace fftlb

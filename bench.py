@@ -96,7 +96,8 @@ def write_traffic(fetch_csv, write_csv, calib_mib, nx, ny):
                 vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
         return vals
 
-    want = f"{STAGE_KERNELS[DOMINANT]}<{nx}, 0, false>"
+    # the step's collide: MODE_STEP, FP32 state, population spectra of the windowed path
+    want = f"{STAGE_KERNELS[DOMINANT]}<{nx}, 0, false, false>"
     rec = {"source_hash": kernel_source_hash(), "nx": nx, "ny": ny, "kernel": want,
            "calib_copy_kib": calib_mib * 1024}
     total = 0.0

@@ -141,3 +141,27 @@ def test_batch_of_mixed_schemes_is_bitwise_solo():
         with solver(fld, p) as s:
             s.step(30)
             assert np.array_equal(s.get_state().cpu().numpy(), g)
+
+
+@pytest.mark.parametrize("m,scheme", [(5, 1), (5, 4), (6, 0)])
+def test_compensated_state_with_schemes(m, scheme):
+    """The comparison schemes with the compensated state (precision 1; the collide variant that
+    takes every convection spectrum from a pass and keeps the low parts): one step from a shared
+    state against the oracle, and 20 steps against the FP32 run of the same scheme."""
+    fld = _fields(64, 64, seed=60 + scheme)
+    p = F.Params(m=m, convection=scheme, precision=1)
+    with solver(fld, p) as s:
+        s.step(2)
+        f0 = state64(s)
+        s.step(1)
+        f1 = state64(s)
+        s.step(17)
+        f20 = state64(s)
+    ref = O.step(f0, oparams(p))
+    scale = np.abs(ref).max()
+    assert np.abs(f1 - ref).max() < 3e-7 * scale, np.abs(f1 - ref).max() / scale
+    p32 = F.Params(m=m, convection=scheme)
+    with solver(fld, p32) as s:
+        s.step(20)
+        g20 = state64(s)
+    assert np.abs(f20 - g20).max() < 2e-6 * scale

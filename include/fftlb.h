@@ -184,7 +184,11 @@ int fftlb_derivative_static(const fftlb_config* cfg, const float* g, float* out,
  * pass of the other 8, 3 = collide row kernel (Eqs. (3), (11) and the update).  Running stages
  * 0..3 once, in order, is exactly one fftlb_step; repeating a stage is for timing and
  * leaves the state meaningless until the next fftlb_set_state or fftlb_init (each
- * stage-3 launch counts as a step).  Other stage numbers: FFTLB_EINVAL. */
+ * stage-3 launch counts as a step).  With a finite-difference convection scheme or the NPS
+ * stencils (fftlb_config.convection != 0 or filter_order 6) stage 0 is the stage-1 derivative
+ * pass followed by the scheme's convection pass (two launches; with the flux limiter the
+ * stencil kernel and the row transforms of its 32 planes) and stage 2 the divergence pass
+ * alone.  Other stage numbers: FFTLB_EINVAL. */
 int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream);
 
 /* Column-pass plan of a handle: spectral columns per block of the convection pass and of

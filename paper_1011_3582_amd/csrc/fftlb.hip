@@ -335,17 +335,6 @@ int col_conv_scheme(const StepLaunch& L, hipStream_t s) {
 }
 
 // Real plane -> packed row spectra, and back, for an instance's grid, twiddles and k_x table.
-int rows_forward_real_pair(const Inst& I, int nx, const float* a, const float* b, float2* sa, float2* sb,
-                           hipStream_t s) {
-  switch (nx) {
-#define X(n) \
-  case n: return launch_rows_forward_real<n>(I.nblk, a, b, sa, sb, I.P.sg, I.P.twx, s);
-    FFTLB_FOR_ROW_SIZES(X)
-#undef X
-  }
-  return FFTLB_EINVAL;
-}
-
 int rows_forward_real(const Inst& I, int nx, const float* a, float2* sa, hipStream_t s) {
   switch (nx) {
 #define X(n) \
@@ -394,18 +383,31 @@ int stage1_columns(const StepLaunch& L, hipStream_t s) {
   return L.nps ? col_multi(L, kStage1Nps, 4, s) : col_multi(L, kStage1, 3, s);
 }
 
-// The flux-limiter convection of every instance of a launch: the real-space kernel, then the row
-// transforms of its 32 planes into the population spectra (which the collide takes as they are).
+// The flux-limiter convection of every instance of a launch, kSchemeSlots instances per pair of
+// launches: the real-space stencil kernel, then the row transforms of its 32 planes into the
+// population spectra (which the collide takes as they are).  Two launches per step and group,
+// whatever the number of instances, so that batch graphs stay as small as with the other schemes.
 int conv_flux_limiter(const StepLaunch& L, hipStream_t s) {
-  for (int k = 0; k < L.ninst; ++k) {
-    const Inst& I = *L.inst[k];
-    FlArgs a = I.fl;
-    a.id = L.id ? L.id[k] : 0;
-    hipLaunchKernelGGL(k_conv_fl, dim3((L.nx + 255) / 256, L.ny, 32), dim3(256), 0, s, a, L.state);
-    const long plane = (long)L.nx * L.ny, hp = plane / 2;
-    for (int p = 0; p < 32; p += 2)
-      RC_TRY(rows_forward_real_pair(I, L.nx, a.out + p * plane, a.out + (p + 1) * plane, I.P.sf + p * hp,
-                                    I.P.sf + (p + 1) * hp, s));
+  for (int first = 0; first < L.ninst; first += kSchemeSlots) {
+    const int count = std::min(kSchemeSlots, L.ninst - first);
+    FlBatch fb{};
+    PlaneFwdArgs pf{};
+    fb.state = pf.state = L.state;
+    for (int k = 0; k < count; ++k) {
+      const Inst& I = *L.inst[first + k];
+      const int id = L.id ? L.id[first + k] : 0;
+      fb.c[k] = I.fl;
+      fb.c[k].id = id;
+      pf.c[k] = PlaneFwdInst{I.fl.out, I.P.sf, I.P.twx, I.P.sg, (long)L.nx * L.ny, id};
+    }
+    hipLaunchKernelGGL(k_conv_fl, dim3((L.nx + 255) / 256, L.ny, 32 * count), dim3(256), 0, s, fb);
+    switch (L.nx) {
+#define X(n) \
+  case n: RC_TRY(launch_rows_forward_planes<n>(pf, count, L.nblk, s)); break;
+      FFTLB_FOR_ROW_SIZES(X)
+#undef X
+      default: return FFTLB_EINVAL;
+    }
   }
   return FFTLB_OK;
 }

@@ -906,6 +906,11 @@ struct FlArgs {
   float rdr;               // 1 / dr
 };
 
+struct FlBatch {
+  FlArgs c[kSchemeSlots];
+  const int* state;
+};
+
 __device__ __forceinline__ float mcd_limited(float a, float b) {
   if (!(a * b > 0.0f)) return 0.0f;
   const float m = fminf(fminf(2.0f * fabsf(a), 0.5f * fabsf(a + b)), 2.0f * fabsf(b));
@@ -1630,6 +1635,45 @@ __global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_real(const flo
   twx = row_twiddles<NX>(lds, twx, tid);
   PairBatchOut<1> o{{sa}, {sb}, {sb != nullptr}};
   rows_forward_batch<NX, 1>(lds, o, sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
+}
+
+// The 32 real convection planes of the flux-limiter scheme -> the population spectra (packed row
+// spectra, plane pair p -> spectra 2p and 2p + 1), for up to kSchemeSlots instances of one grid
+// size: blockIdx.y = pair, blockIdx.z = slot.
+struct PlaneFwdInst {
+  const float* src;        // [32][ny][nx]
+  float2* dst;             // [32] population spectra
+  const float2* twx;       // row twiddles
+  SpecGeom sg;
+  long plane;              // nx * ny
+  int id;
+};
+
+struct PlaneFwdArgs {
+  PlaneFwdInst c[kSchemeSlots];
+  const int* state;
+};
+
+template <int NX>
+__global__ __launch_bounds__(RowGeom<NX>::NT) void k_rows_forward_planes(PlaneFwdArgs A) {
+  const PlaneFwdInst& I = A.c[blockIdx.z];
+  if (retired(A.state, I.id)) return;
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const RowThread<NX> rt(tid);
+  const long rb = (long)blockIdx.x * RowGeom<NX>::RB * NX;
+  const long p2 = 2 * (long)blockIdx.y;
+  const float* a = I.src + p2 * I.plane;
+  const float* b = a + I.plane;
+#pragma unroll
+  for (int j = 0; j < RowGeom<NX>::J; ++j) {
+    const unsigned s = rt.site(j);
+    lds[rt.at(0, j)] = make_float2(elem(a + rb, s), elem(b + rb, s));
+  }
+  const float2* twx = row_twiddles<NX>(lds, I.twx, tid);
+  const long hp = I.plane / 2;
+  PairBatchOut<1> o{{I.dst + p2 * hp}, {I.dst + (p2 + 1) * hp}, {true}};
+  rows_forward_batch<NX, 1>(lds, o, I.sg, twx, blockIdx.x * RowGeom<NX>::RB, tid);
 }
 
 // Packed row spectra -> real plane(s) (b may be null).

@@ -60,6 +60,9 @@ int launch_col_conv_multi(const StepLaunch& L, const ColLaunch& groups, int ngro
 // the finite-difference convection pass of all 32 moving populations (StepLaunch::scheme != 0)
 template <int NY>
 int launch_col_conv_scheme(const StepLaunch& L, hipStream_t s);
+// the 32 flux-limiter convection planes of up to kSchemeSlots instances -> their population spectra
+template <int NX>
+int launch_rows_forward_planes(const PlaneFwdArgs& a, int count, int nblk, hipStream_t s);
 // derivative groups with the NPS stencils (StepLaunch::nps)
 template <int NY>
 int launch_col_nps(const StepLaunch& L, const ColLaunch& groups, int ngroups, hipStream_t s);

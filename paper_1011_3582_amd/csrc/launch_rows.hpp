@@ -77,11 +77,19 @@ int launch_rows_inverse_real(int nblk, const float2* sa, const float2* sb, float
   return FFTLB_OK;
 }
 
+template <int NX>
+int launch_rows_forward_planes(const PlaneFwdArgs& a, int count, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_rows_forward_planes<NX>, dim3(nblk, 16, count), dim3(RowGeom<NX>::NT),
+                     RowGeom<NX>::LDS_TOTAL * sizeof(float2), s, a);
+  return FFTLB_OK;
+}
+
 #define FFTLB_INSTANTIATE_ROWS(NX)                                                                       \
   template int launch_rows<NX>(const StepLaunch&, int, const Inputs&, hipStream_t);                    \
   template int launch_rows_forward_real<NX>(int, const float*, const float*, float2*, float2*, SpecGeom, \
                                             const float2*, hipStream_t);                                 \
   template int launch_rows_inverse_real<NX>(int, const float2*, const float2*, float*, float*, SpecGeom, \
-                                            const float2*, const float*, hipStream_t);
+                                            const float2*, const float*, hipStream_t);           \
+  template int launch_rows_forward_planes<NX>(const PlaneFwdArgs&, int, int, hipStream_t);
 
 }  // namespace fftlb

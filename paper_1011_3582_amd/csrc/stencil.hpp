@@ -5,9 +5,11 @@
 
 namespace fftlb {
 
-__global__ __launch_bounds__(256) void k_conv_fl(FlArgs A, const int* state) {
-  if (retired(state, A.id)) return;
-  const int q = blockIdx.z + 1;  // moving population 1..32
+// Grid: (ceil(nx / 256), ny, 32 x instances); blockIdx.z = 32 slot + (q - 1).
+__global__ __launch_bounds__(256) void k_conv_fl(FlBatch B) {
+  const FlArgs& A = B.c[blockIdx.z / 32];
+  if (retired(B.state, A.id)) return;
+  const int q = blockIdx.z % 32 + 1;  // moving population 1..32
   const int y = blockIdx.y;
   const int x = blockIdx.x * 256 + threadIdx.x;
   if (x >= A.nx) return;

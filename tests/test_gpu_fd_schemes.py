@@ -165,3 +165,20 @@ def test_compensated_state_with_schemes(m, scheme):
         s.step(20)
         g20 = state64(s)
     assert np.abs(f20 - g20).max() < 2e-6 * scale
+
+
+def test_batch_of_many_flux_limiter_instances_is_bitwise_solo():
+    """Nine flux-limiter instances in one batch (two launches of the stencil and the row transforms
+    per step, eight instances in the first): each evolves bitwise as it does alone."""
+    flds = [W.smooth_random(64, 64, seed=70 + k, T0=1.2) for k in range(9)]
+    p = F.Params(m=5, convection=4)
+    b = F.Batch([tuple(torch.from_numpy(a) for a in (f.rho, f.ux, f.uy, f.T)) for f in flds], params=p)
+    try:
+        b.run(tol=0.0, consecutive=3, poll_every=10, max_steps=20)
+        got = [b.instance(i).get_state().cpu().numpy() for i in range(9)]
+    finally:
+        b.close()
+    for k in (0, 7, 8):
+        with solver(flds[k], p) as s:
+            s.step(20)
+            assert np.array_equal(s.get_state().cpu().numpy(), got[k])

@@ -21,7 +21,9 @@ under profiles/.
       and 14) for the k4 window and the finite-difference schemes (NPS, MLW2, LW, CD), with the
       bulk densities against the Maxwell construction;
   droplet_currents(): the spurious currents of a circular droplet started at equilibrium
-      (Sec. 4.2, Fig. 19) for k1..k4, NPS and CD.
+      (Sec. 4.2, Fig. 19) for k1..k4, NPS and CD;
+  slab_floor(): the spurious velocity of an equilibrium slab at K = 1e-5 with f in FP32, with the
+      compensated state and (optionally) in the FP64 oracle.
 
 Usage (one MI355X):
   python tests/physics_studies.py laplace|profile|coexistence|energy|spurious [--cap N] [--orders ...]
@@ -280,6 +282,45 @@ def droplet_currents(n=128, R=24.0, t_ratio=0.95, K=1e-5, orders=(1, 2, 3, 4, "N
             "umax": {V.scheme_name(o): s_ for o, s_ in zip(orders, series)}}
 
 
+def slab_floor(nx=256, ny=4, t_ratio=0.93, K=1e-5, steps=150_000, every=2500, oracle=False):
+    """The spurious velocity of a planar interface started from the equilibrium profile (K = 1e-5:
+    the paper prints 1e-12 for it, Sec. 4.1) with the k4 window: the GPU with f in FP32 and with the
+    compensated state, and with oracle=True the FP64 oracle on the CPU from the same (FP32-rounded)
+    start (slow: tens of milliseconds per step).  max |u| every `every` steps."""
+    from oracle import fftlb_oracle as O
+    t_c = 8 * A / (27 * B)
+    T = t_ratio * t_c
+    dx = F.Params().dx
+    x = np.arange(nx, dtype=np.float64)
+    dist = np.minimum(x - nx / 4.0, 3.0 * nx / 4.0 - x) * dx
+    fields = V.slab_start(nx, ny, thermo.planar_profile(dist, T, A, B, K), T)
+    fields = tuple(np.asarray(a, dtype=np.float32) for a in fields)
+    params = [F.Params(a=A, b=B, K=K, precision=pr) for pr in (0, 1)]
+    b = F.Batch([tuple(torch_from(a) for a in fields) for _ in params], params)
+    series = {"fp32": [], "compensated": []}
+
+    def record(n):
+        for i, k in enumerate(series):
+            series[k].append((n, b.instance(i).poll()["umax"]))
+
+    V._chunked(b, 2, steps, every, record)
+    b.close()
+    out = {"nx": nx, "T/Tc": t_ratio, "K": K, "steps": steps, "gpu": series}
+    if oracle:
+        op = O.Params(a=A, b=B, K=K, m=4)
+        f = O.init_distribution(*(a.astype(np.float64) for a in fields))
+        ser = []
+        for n in range(steps + 1):
+            if n % every == 0:
+                _, ux, uy, _ = O.moments(f)
+                ser.append((n, float(np.sqrt(ux * ux + uy * uy).max())))
+                log(f"oracle {n} steps: {ser[-1][1]:.3e}")
+            if n < steps:
+                f = O.step(f, op)
+        out["oracle"] = ser
+    return out
+
+
 def torch_from(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
@@ -325,7 +366,8 @@ def sod():
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod", "spurious", "droplet"])
+    ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod", "spurious", "droplet",
+                                      "floor"])
     ap.add_argument("--cap", type=int, default=1_000_000)
     ap.add_argument("--orders", default=None, help="window orders and scheme names (energy, spurious)")
     args = ap.parse_args()
@@ -341,6 +383,9 @@ def main():
         return
     if args.study == "droplet":
         print(json.dumps(droplet_currents(cap=args.cap)))
+        return
+    if args.study == "floor":
+        print(json.dumps(slab_floor(steps=args.cap)))
         return
     fn = {"laplace": laplace, "coexistence": coexistence, "profile": profile, "energy": energy}[args.study]
     print(json.dumps(fn(cap=args.cap)))

@@ -23,7 +23,9 @@ under profiles/.
   droplet_currents(): the spurious currents of a circular droplet started at equilibrium
       (Sec. 4.2, Fig. 19) for k1..k4, NPS and CD;
   slab_floor(): the spurious velocity of an equilibrium slab at K = 1e-5 with f in FP32, with the
-      compensated state and (optionally) in the FP64 oracle.
+      compensated state and (optionally) in the FP64 oracle;
+  cooling(): the paper's coexistence protocol, a slab cooled from 0.97 T_c in steps of 0.02, per
+      discretisation.
 
 Usage (one MI355X):
   python tests/physics_studies.py laplace|profile|coexistence|energy|spurious [--cap N] [--orders ...]
@@ -282,6 +284,60 @@ def droplet_currents(n=128, R=24.0, t_ratio=0.95, K=1e-5, orders=(1, 2, 3, 4, "N
             "umax": {V.scheme_name(o): s_ for o, s_ in zip(orders, series)}}
 
 
+def cooling(temps=(0.97, 0.95, 0.93, 0.91, 0.89, 0.87, 0.85), K=0.0, orders=(4, "NPS+NPS", "MLW2+CD", "FL+CD"),
+            nx=512, ny=4, stage_steps=500_000, every=100_000):
+    """The coexistence protocol of Sec. 4.1: one slab per discretisation (liquid in
+    nx/4 < x <= 3nx/4), started at T = temps[0] T_c with the densities 0.80 / 1.20 the paper takes
+    from T = 0.99 and a tanh of width 1.5 grid units, run stage_steps; then cooled by the next
+    step of `temps` at a time (a uniform shift of T, which changes the total energy of Eq. (17) by
+    the shift times the mass: fftlb_match_energy) and run again.  After each stage: bulk
+    densities, mean T and u^s against the Maxwell densities at the mean T; an instance that goes
+    non-finite is reported unstable from then on."""
+    t_c = 8 * A / (27 * B)
+    x = np.arange(nx, dtype=np.float64)
+    dist = np.minimum(x - nx / 4.0, 3.0 * nx / 4.0 - x)
+    prof = 1.0 + 0.2 * np.tanh(dist / 1.5)
+    fields, params = [], []
+    for spec in orders:
+        m, conv = V.scheme(spec)
+        fields.append(V.slab_start(nx, ny, prof, temps[0] * t_c))
+        params.append(F.Params(a=A, b=B, K=K, m=m, convection=conv, precision=1))
+    b = F.Batch([tuple(torch_from(a) for a in f) for f in fields], params)
+    stages = []
+    alive = [True] * len(orders)
+    for k, tr in enumerate(temps):
+        if k > 0:
+            shift = (temps[k] - temps[k - 1]) * t_c
+            for i in range(len(orders)):
+                if alive[i]:
+                    g = b.instance(i).poll()
+                    b.instance(i).match_energy(g["energy"] + shift * g["mass"])
+        V._chunked(b, len(orders), stage_steps, every, lambda n: None)
+        row = {"T/Tc": tr, "schemes": {}}
+        for i, spec in enumerate(orders):
+            name = V.scheme_name(spec)
+            try:
+                g = b.instance(i).poll()
+            except F.FFTLBError:
+                alive[i] = False
+            if not alive[i]:
+                row["schemes"][name] = None
+                continue
+            (rho, _, _, T), _ = b.instance(i).moments(globals_=False)
+            rho = rho.cpu().numpy().astype(np.float64)
+            t_end = float(T.cpu().numpy().astype(np.float64).mean())
+            rv, rl = V.bulk_densities(rho)
+            mv, ml = thermo.maxwell(t_end, A, B)
+            row["schemes"][name] = {"T_end": t_end, "rho_v": rv, "rho_l": rl, "maxwell_v": mv, "maxwell_l": ml,
+                                    "umax": g["umax"]}
+        log(f"cooling T/Tc {tr}: " + ", ".join(
+            f"{n}: " + ("unstable" if v is None else f"{v['rho_v']:.4f}/{v['rho_l']:.4f} u {v['umax']:.1e}")
+            for n, v in row["schemes"].items()))
+        stages.append(row)
+    b.close()
+    return {"nx": nx, "ny": ny, "K": K, "stage_steps": stage_steps, "stages": stages}
+
+
 def slab_floor(nx=256, ny=4, t_ratio=0.93, K=1e-5, steps=150_000, every=2500, oracle=False):
     """The spurious velocity of a planar interface started from the equilibrium profile (K = 1e-5:
     the paper prints 1e-12 for it, Sec. 4.1) with the k4 window: the GPU with f in FP32 and with the
@@ -367,7 +423,7 @@ def sod():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["laplace", "coexistence", "profile", "energy", "sod", "spurious", "droplet",
-                                      "floor"])
+                                      "floor", "cooling"])
     ap.add_argument("--cap", type=int, default=1_000_000)
     ap.add_argument("--orders", default=None, help="window orders and scheme names (energy, spurious)")
     args = ap.parse_args()
@@ -386,6 +442,9 @@ def main():
         return
     if args.study == "floor":
         print(json.dumps(slab_floor(steps=args.cap)))
+        return
+    if args.study == "cooling":
+        print(json.dumps(cooling(stage_steps=args.cap)))
         return
     fn = {"laplace": laplace, "coexistence": coexistence, "profile": profile, "energy": energy}[args.study]
     print(json.dumps(fn(cap=args.cap)))

@@ -338,11 +338,11 @@ def cooling(temps=(0.97, 0.95, 0.93, 0.91, 0.89, 0.87, 0.85), K=0.0, orders=(4, 
     return {"nx": nx, "ny": ny, "K": K, "stage_steps": stage_steps, "stages": stages}
 
 
-def slab_floor(nx=256, ny=4, t_ratio=0.93, K=1e-5, steps=150_000, every=2500, oracle=False):
+def slab_floor(nx=256, ny=4, t_ratio=0.93, K=1e-5, steps=150_000, every=2500, gpu=True, oracle=False):
     """The spurious velocity of a planar interface started from the equilibrium profile (K = 1e-5:
-    the paper prints 1e-12 for it, Sec. 4.1) with the k4 window: the GPU with f in FP32 and with the
-    compensated state, and with oracle=True the FP64 oracle on the CPU from the same (FP32-rounded)
-    start (slow: tens of milliseconds per step).  max |u| every `every` steps."""
+    the paper prints 1e-12 for it, Sec. 4.1) with the k4 window: with gpu=True the GPU with f in
+    FP32 and with the compensated state, with oracle=True the FP64 oracle on the CPU from the same
+    (FP32-rounded) start (slow: tens of milliseconds per step).  max |u| every `every` steps."""
     from oracle import fftlb_oracle as O
     t_c = 8 * A / (27 * B)
     T = t_ratio * t_c
@@ -351,17 +351,19 @@ def slab_floor(nx=256, ny=4, t_ratio=0.93, K=1e-5, steps=150_000, every=2500, or
     dist = np.minimum(x - nx / 4.0, 3.0 * nx / 4.0 - x) * dx
     fields = V.slab_start(nx, ny, thermo.planar_profile(dist, T, A, B, K), T)
     fields = tuple(np.asarray(a, dtype=np.float32) for a in fields)
-    params = [F.Params(a=A, b=B, K=K, precision=pr) for pr in (0, 1)]
-    b = F.Batch([tuple(torch_from(a) for a in fields) for _ in params], params)
-    series = {"fp32": [], "compensated": []}
+    out = {"nx": nx, "T/Tc": t_ratio, "K": K, "steps": steps}
+    if gpu:
+        params = [F.Params(a=A, b=B, K=K, precision=pr) for pr in (0, 1)]
+        b = F.Batch([tuple(torch_from(a) for a in fields) for _ in params], params)
+        series = {"fp32": [], "compensated": []}
 
-    def record(n):
-        for i, k in enumerate(series):
-            series[k].append((n, b.instance(i).poll()["umax"]))
+        def record(n):
+            for i, k in enumerate(series):
+                series[k].append((n, b.instance(i).poll()["umax"]))
 
-    V._chunked(b, 2, steps, every, record)
-    b.close()
-    out = {"nx": nx, "T/Tc": t_ratio, "K": K, "steps": steps, "gpu": series}
+        V._chunked(b, 2, steps, every, record)
+        b.close()
+        out["gpu"] = series
     if oracle:
         op = O.Params(a=A, b=B, K=K, m=4)
         f = O.init_distribution(*(a.astype(np.float64) for a in fields))
@@ -372,7 +374,7 @@ def slab_floor(nx=256, ny=4, t_ratio=0.93, K=1e-5, steps=150_000, every=2500, or
                 ser.append((n, float(np.sqrt(ux * ux + uy * uy).max())))
                 log(f"oracle {n} steps: {ser[-1][1]:.3e}")
             if n < steps:
-                f = O.step(f, op)
+                f = O.step(f, op, workers=os.cpu_count())
         out["oracle"] = ser
     return out
 

@@ -38,14 +38,15 @@ def _tensors(fl):
     return tuple(torch.from_numpy(np.ascontiguousarray(a)) for a in fl)
 
 
-def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0, energy_from=None, trace=False):
+def run_batch(fields, tol, cap, chunk=20000, poll=100, probe=0, energy_from=None, trace=False, precision=0):
     """Run instances (list of (rho, ux, uy, T) arrays) until each has retired or `cap` steps.
     Returns (status dict, [(rho, T) numpy of every instance], wall seconds); with probe > 0
     the status also holds "probe_residual", every instance's residual after `probe` steps.
     energy_from {i: j}: before the run, instance i takes the total energy of instance j's
     initial state (fftlb_match_energy).  trace: the status also holds "trace", the steps and
-    every instance's residual after each chunk."""
-    b = F.Batch([_tensors(f) for f in fields])
+    every instance's residual after each chunk.  precision: the state of every instance
+    (0: FP32, 1: compensated, for tolerances below the FP32 floor)."""
+    b = F.Batch([_tensors(f) for f in fields], params=F.Params(precision=precision))
     for i, j in (energy_from or {}).items():
         b.instance(i).match_energy(b.instance(j).poll()["energy"])
     b.autotune(reps=3)
@@ -139,7 +140,7 @@ def decay_fit(steps, resid, lo, hi):
     return float(np.exp(icpt)), float(-slope)
 
 
-def evaluate(net, n, seed, size, tol, cap, probe=1000, chunk=5000):
+def evaluate(net, n, seed, size, tol, cap, probe=1000, chunk=5000, precision=0):
     """Cold and warm runs of n held-out instances in one batch; steps to tolerance, and the
     best-of-two start decided by the residuals after `probe` steps.  Also, per instance: the
     RMS distance of each start from the relaxed cold field (normalised by rho_c) and the
@@ -158,7 +159,7 @@ def evaluate(net, n, seed, size, tol, cap, probe=1000, chunk=5000):
         warm.append((r, np.zeros_like(r), np.zeros_like(r), Tn))
     # the warm starts take the total energy of their cold starts (mass is kept by the transform)
     st, relaxed, wall = run_batch(cold + warm, tol, cap, chunk=chunk, probe=probe,
-                                  energy_from={n + k: k for k in range(n)}, trace=True)
+                                  energy_from={n + k: k for k in range(n)}, trace=True, precision=precision)
     s = st["steps_to_tol"]
     sc, sw = s[:n], s[n:]
     ok = (sc > 0) & (sw > 0)
@@ -176,7 +177,7 @@ def evaluate(net, n, seed, size, tol, cap, probe=1000, chunk=5000):
     tsteps = [h[0] for h in st["trace"]]
     fits = [decay_fit(tsteps, [h[1][i] for h in st["trace"]], 10 * tol, 1e-5) for i in range(2 * n)]
     kinds = [(k, float(t), float(R)) for k, _, t, R, _ in inst]
-    return {"instances": n, "tol": tol, "cap": cap, "both_converged": int(ok.sum()),
+    return {"instances": n, "tol": tol, "cap": cap, "precision": precision, "both_converged": int(ok.sum()),
             "cold_capped": int((sc < 0).sum()), "warm_capped": int((sw < 0).sum()),
             "steps_cold_median": float(np.median(np.where(sc > 0, sc, cap))),
             "steps_warm_median": float(np.median(np.where(sw > 0, sw, cap))),
@@ -201,6 +202,7 @@ def main():
     ap.add_argument("--data-cap", type=int, default=100000)
     ap.add_argument("--tol", type=float, default=3e-7)
     ap.add_argument("--cap", type=int, default=200000)
+    ap.add_argument("--precision", type=int, default=0, help="state of the evaluation runs (1: compensated)")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -225,7 +227,7 @@ def main():
                     "data_steps_median": float(np.median(steps)), "data_seconds": t_data, "epochs": args.epochs,
                     "batch": args.batch, "lr": args.lr, "train_seconds": t_train, "loss_first": hist[0],
                     "loss_last": hist[-1]})
-    out["evaluation"] = evaluate(net, args.eval, 20000, args.size, args.tol, args.cap)
+    out["evaluation"] = evaluate(net, args.eval, 20000, args.size, args.tol, args.cap, precision=args.precision)
     print(json.dumps(out))
 
 

@@ -27,7 +27,7 @@ struct CnnLayout {
 
 // Pixels per K chunk of the weight-gradient GEMM (each chunk of each sample writes one
 // partial gradient).
-constexpr int kWChunk = 4096;
+constexpr int kWChunk = 1024;
 
 // Output size of layer l for an h x w input.
 void layer_out(int l, int h, int w, int* ho, int* wo) {
@@ -82,7 +82,7 @@ bool shape_ok(int h, int w, int nmax) {
 
 template <class Pb>
 int launch_gemm(const Pb& pb, int M, int N, int Z, hipStream_t s) {
-  hipLaunchKernelGGL(k_gemm<Pb>, dim3((N + 255) / 256, (M + 15) / 16, Z), dim3(256), 0, s, pb);
+  hipLaunchKernelGGL(k_gemm<Pb>, dim3((N + 255) / 256, (M + 31) / 32, Z), dim3(256), 0, s, pb);
   return hipGetLastError() == hipSuccess ? FFTLB_OK : FFTLB_EHIP;
 }
 
@@ -167,7 +167,7 @@ int backward(fftlb_cnn* c, const float* x, const float* target, int n, hipStream
     const int ncol = g.cin * 9 + 1;
     if (launch_gemm(wg, g.cout, ncol, n * wg.nchunks, s)) return FFTLB_EHIP;
     float* dW = c->grad + param_offset(l);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((g.cout * ncol + 255) / 256), dim3(256), 0, s, c->wpart,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((g.cout * ncol + 63) / 64), dim3(256), 0, s, c->wpart,
                        n * wg.nchunks, g.cout, ncol, dW, dW + (long)g.cout * g.cin * 9);
     if (l == 0) break;
     BwdDataProblem bd{};

@@ -1,8 +1,8 @@
 // Warm-start network on gfx950: every convolution (forward, input gradient, weight gradient)
 // is one implicit GEMM on the bf16 matrix cores with FP32 accumulation.
 //
-// A block of four waves computes a 16 x 256 block of C = A B (each wave 16 x 64: four
-// v_mfma_f32_16x16x32_bf16 per 32-deep slice of K).  The A tile of a slice is gathered once
+// A block of four waves computes a 32 x 256 block of C = A B (each wave 32 x 64: eight
+// v_mfma_f32_16x16x32_bf16 per 32-deep slice of K, two row tiles sharing each B fragment).  The A tile of a slice is gathered once
 // per block into LDS as bf16; B elements are gathered straight from the FP32 tensors by the
 // problem's accessors and rounded to bf16 on the way into the matrix core.  Operand layouts
 // of the 16x16x32 instruction (lane l of the wave):
@@ -79,8 +79,28 @@ __device__ __forceinline__ float fwd_gather(const float* __restrict__ X, const G
   return X[((long)ci * g.hin + iy) * g.win + ix];
 }
 
-// Forward: Z[co][p] = b[co] + sum_k W[co][k] X-gather[k][p], k = (ci, tap); then
-// A = GELU(Z), or for the last layer Y = input channel + Z.
+// Input pixel (iy, ix) feeding tap (ky, kx) of output pixel (oy, ox).
+__device__ __forceinline__ void fwd_pos(const Geom& g, int ky, int kx, int oy, int ox, int& iy, int& ix) {
+  if (g.kind == KIND_S1) {
+    iy = wrap(oy + ky - 1, g.hin);
+    ix = wrap(ox + kx - 1, g.win);
+  } else if (g.kind == KIND_S2) {
+    iy = wrap(2 * oy + ky - 1, g.hin);
+    ix = wrap(2 * ox + kx - 1, g.win);
+  } else {
+    iy = wrap(oy + ky - 1, 2 * g.hin) >> 1;
+    ix = wrap(ox + kx - 1, 2 * g.win) >> 1;
+  }
+}
+
+// Eight consecutive K indices k .. k + 7 of one B column (n) per lane and slice: the gathers
+// below compute the pixel arithmetic once for the eight (consecutive channels at one pixel, or
+// consecutive pixels of one row) and fall back to element-wise gathers where the layer's sizes
+// are not multiples of eight.  Elements with k >= ke or n >= N are zero.
+
+// Forward: Z[co][p] = b[co] + sum_k W[co][k] X-gather[k][p], k = tap * cin + ci (the taps outer,
+// so that eight consecutive k of a 32-channel layer are eight channels at one input pixel);
+// then A = GELU(Z), or for the last layer Y = input channel + Z.
 struct FwdProblem {
   Geom g;
   const float* X;      // [n][cin][hin][win]
@@ -98,9 +118,23 @@ struct FwdProblem {
     e = g.cin * 9;
   }
   __device__ int sample(int z) const { return z; }
-  __device__ float a(int m, int k, int) const { return W[(long)m * g.cin * 9 + k]; }
+  __device__ float a(int m, int k, int) const { return W[(long)m * g.cin * 9 + (k % g.cin) * 9 + k / g.cin]; }
   __device__ float b(int k, int n, int z) const {
-    return fwd_gather(X + z * xs, g, k / 9, k % 9, n / g.wout, n % g.wout);
+    return fwd_gather(X + z * xs, g, k % g.cin, k / g.cin, n / g.wout, n % g.wout);
+  }
+  __device__ void b8(int k, int n, int z, int ke, float* v) const {
+    if (n >= N() || k >= ke || (g.cin & 7) || k + 8 > ke) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (k + i < ke && n < N()) ? b(k + i, n, z) : 0.0f;
+      return;
+    }
+    const int tap = k / g.cin, ci = k % g.cin;
+    int iy, ix;
+    fwd_pos(g, tap / 3, tap % 3, n / g.wout, n % g.wout, iy, ix);
+    const long plane = (long)g.hin * g.win;
+    const float* x = X + z * xs + ci * plane + (long)iy * g.win + ix;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = x[i * plane];
   }
   __device__ void store(int m, int n, float v, int z) const {
     const long i = z * zs + (long)m * N() + n;
@@ -112,8 +146,9 @@ struct FwdProblem {
 };
 
 // Input gradient of a layer whose input is the GELU output of the layer before:
-// dZprev[ci][p] = GELU'(Zprev[ci][p]) sum_k W^T[ci][k] dZ-gather[k][p], k = (co, tap, r),
-// r over the 2 x 2 output pixels an upsampled input pixel feeds.
+// dZprev[ci][p] = GELU'(Zprev[ci][p]) sum_k W^T[ci][k] dZ-gather[k][p],
+// k = (tap R + r) cout + co (r over the 2 x 2 output pixels an upsampled input pixel feeds; the
+// output channels inner, so that eight consecutive k are eight channels at one output pixel).
 struct BwdDataProblem {
   Geom g;
   const float* W;      // [cout][cin][9]
@@ -130,26 +165,48 @@ struct BwdDataProblem {
   }
   __device__ int sample(int z) const { return z; }
   __device__ float a(int m, int k, int) const {
-    const int r = R(), co = k / (9 * r), tap = (k / r) % 9;
+    const int co = k % g.cout, tap = (k / g.cout) / R();
     return W[((long)co * g.cin + m) * 9 + tap];
   }
-  __device__ float b(int k, int n, int z) const {
-    const int r = R(), co = k / (9 * r), tap = (k / r) % 9, q = k % r;
+  // Output pixel (y, x) that reads input pixel n through tap and sub-pixel q; false if none.
+  __device__ bool out_pos(int tq, int n, int& y, int& x) const {
+    const int r = R(), tap = tq / r, q = tq % r;
     const int ky = tap / 3, kx = tap % 3, iy = n / g.win, ix = n % g.win;
-    int y, x;
     if (g.kind == KIND_S1) {
       y = wrap(iy - ky + 1, g.hout);
       x = wrap(ix - kx + 1, g.wout);
     } else if (g.kind == KIND_S2) {
       const int ty = wrap(iy - ky + 1, g.hin), tx = wrap(ix - kx + 1, g.win);
-      if ((ty | tx) & 1) return 0.0f;  // no output pixel reads this input through this tap
+      if ((ty | tx) & 1) return false;  // no output pixel reads this input through this tap
       y = ty >> 1;
       x = tx >> 1;
     } else {
       y = wrap(2 * iy + (q >> 1) - ky + 1, g.hout);
       x = wrap(2 * ix + (q & 1) - kx + 1, g.wout);
     }
-    return dZ[z * zs + ((long)co * g.hout + y) * g.wout + x];
+    return true;
+  }
+  __device__ float b(int k, int n, int z) const {
+    int y, x;
+    if (!out_pos(k / g.cout, n, y, x)) return 0.0f;
+    return dZ[z * zs + ((long)(k % g.cout) * g.hout + y) * g.wout + x];
+  }
+  __device__ void b8(int k, int n, int z, int ke, float* v) const {
+    if (n >= N() || k >= ke || (g.cout & 7) || k + 8 > ke) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (k + i < ke && n < N()) ? b(k + i, n, z) : 0.0f;
+      return;
+    }
+    int y, x;
+    if (!out_pos(k / g.cout, n, y, x)) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.0f;
+      return;
+    }
+    const long plane = (long)g.hout * g.wout;
+    const float* d = dZ + z * zs + (k % g.cout) * plane + (long)y * g.wout + x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = d[i * plane];
   }
   __device__ void store(int m, int n, float v, int z) const {
     const long i = z * ps + (long)m * N() + n;
@@ -182,36 +239,81 @@ struct WGradProblem {
     if (n == g.cin * 9) return 1.0f;
     return fwd_gather(X + sample(z) * xs, g, n / 9, n % 9, k / g.wout, k % g.wout);
   }
+  __device__ void b8(int k, int n, int z, int ke, float* v) const {
+    if (n >= N() || k >= ke || (g.wout & 7) || k + 8 > ke || n == g.cin * 9) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (k + i < ke && n < N()) ? b(k + i, n, z) : 0.0f;
+      return;
+    }
+    // pixels k .. k + 7 lie in one output row (k and wout are multiples of 8)
+    const int ci = n / 9, tap = n % 9, ky = tap / 3, kx = tap % 3, oy = k / g.wout, ox = k % g.wout;
+    const float* x = X + sample(z) * xs + (long)ci * g.hin * g.win;
+    int iy, ix0;
+    fwd_pos(g, ky, kx, oy, ox, iy, ix0);
+    const float* row = x + (long)iy * g.win;
+    if (g.kind == KIND_S1) {
+      const int b0 = ox + kx - 1;  // ix of pixel i is b0 + i, wrapped
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int c = b0 + i;
+        v[i] = row[c < 0 ? c + g.win : (c >= g.win ? c - g.win : c)];
+      }
+    } else if (g.kind == KIND_S2) {
+      const int b0 = 2 * ox + kx - 1;  // ix of pixel i is b0 + 2 i, wrapped
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int c = b0 + 2 * i;
+        v[i] = row[c < 0 ? c + g.win : (c >= g.win ? c - g.win : c)];
+      }
+    } else {
+      const int b0 = ox + kx - 1, w2 = 2 * g.win;  // ix of pixel i is wrap(b0 + i, 2 win) / 2
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int c = b0 + i;
+        v[i] = row[(c < 0 ? c + w2 : (c >= w2 ? c - w2 : c)) >> 1];
+      }
+    }
+  }
   __device__ void store(int m, int n, float v, int z) const { part[((long)z * M() + m) * N() + n] = v; }
 };
 
 // dW[co][k] (k < cin * 9) and db[co] (k = cin * 9) = the sum over z = 0..nz-1 of
-// part[z][co][k], in order of z, accumulated in FP64.
+// part[z][co][k], accumulated in FP64 in a fixed order: a block of 256 threads takes 64
+// consecutive outputs (consecutive lanes read consecutive addresses); its four thread groups
+// sum the z = g, g + 4, g + 8, ... partials in order, and the four group sums are added in
+// order g = 0..3.  Grid: ceil(cout * ncol / 64) blocks.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nz, int cout, int ncol,
                                                       float* __restrict__ dW, float* __restrict__ db) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double grp[4][64];
+  const int c = threadIdx.x & 63, gz = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + c;
   const int mn = cout * ncol;
-  if (i >= mn) return;
   double acc = 0.0;
-  for (int z = 0; z < nz; ++z) acc += part[(long)z * mn + i];
+  if (i < mn)
+    for (int z = gz; z < nz; z += 4) acc += part[(long)z * mn + i];
+  grp[gz][c] = acc;
+  __syncthreads();
+  if (gz != 0 || i >= mn) return;
+  const double sum = ((grp[0][c] + grp[1][c]) + grp[2][c]) + grp[3][c];
   const int m = i / ncol, k = i % ncol;
   if (k < ncol - 1)
-    dW[(long)m * (ncol - 1) + k] = (float)acc;
+    dW[(long)m * (ncol - 1) + k] = (float)sum;
   else
-    db[m] = (float)acc;
+    db[m] = (float)sum;
 }
 
-// One wave: a 16 x 64 block of C; a block of 256 threads (four waves): 16 x 256.  Grid: x
-// over N / 256, y over M / 16, z over the problem's samples (and K chunks).  Per 32-deep
-// slice of K the block stages the 16 x 32 A tile, shared by its four waves, in LDS as bf16
-// (each element gathered once per block instead of once per wave), then every wave gathers
-// its B columns and issues four v_mfma_f32_16x16x32_bf16.
+// One wave: a 32 x 64 block of C (two 16-row tiles sharing each B fragment); a block of 256
+// threads (four waves): 32 x 256.  Grid: x over N / 256, y over M / 32, z over the problem's
+// samples (and K chunks).  Per 32-deep slice of K the block stages the 32 x 32 A tile, shared by
+// its four waves, in LDS as bf16 (each element gathered once per block), then every wave gathers
+// its B columns once (eight consecutive k per lane, pb.b8) and issues eight
+// v_mfma_f32_16x16x32_bf16.  Every M of the network is 32 or 2, so one block row covers it.
 template <class Pb>
 __global__ __launch_bounds__(256) void k_gemm(Pb pb) {
   // A tile rows padded to 40 bf16 (80 bytes): the 8 values of a lane are one aligned 16-byte read
-  __shared__ __attribute__((aligned(16))) short As[16][40];
+  __shared__ __attribute__((aligned(16))) short As[32][40];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 16;
+  const int m0 = blockIdx.y * 32;
   const int n0 = (blockIdx.x * 4 + wave) * 64;
   const int z = blockIdx.z;
   const int M = pb.M(), N = pb.N();
@@ -219,44 +321,50 @@ __global__ __launch_bounds__(256) void k_gemm(Pb pb) {
   int kb, ke;
   pb.krange(z, kb, ke);
   const int row = lane & 15, kq = (lane >> 4) * 8, crow = (lane >> 4) * 4;
-  const int sr = threadIdx.x >> 4, sk = (threadIdx.x & 15) * 2;  // this thread's two staged A elements
-  f32x4 acc[4];
+  const int sr = threadIdx.x >> 3, sk = (threadIdx.x & 7) * 4;  // this thread's four staged A elements
+  f32x4 acc[2][4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[t][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = kb; k0 < ke; k0 += 32) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < 4; ++e) {
       const int k = k0 + sk + e, m = m0 + sr;
       As[sr][sk + e] = bf16_bits(k < ke && m < M ? pb.a(m, k, z) : 0.0f);
     }
     __syncthreads();
     if (active) {
-      const s16x8 av = *reinterpret_cast<const s16x8*>(&As[row][kq]);
+      const s16x8 av0 = *reinterpret_cast<const s16x8*>(&As[row][kq]);
+      const s16x8 av1 = *reinterpret_cast<const s16x8*>(&As[16 + row][kq]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         s16x8 bv;
         const int n = n0 + 16 * j + row;
+        float bf[8];
+        pb.b8(k0 + kq, n, z, ke, bf);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = k0 + kq + i;
-          bv[i] = bf16_bits(k < ke && n < N ? pb.b(k, n, z) : 0.0f);
-        }
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
-                                                         acc[j], 0, 0, 0);
+        for (int i = 0; i < 8; ++i) bv[i] = bf16_bits(bf[i]);
+        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av0),
+                                                            __builtin_bit_cast(bf16x8, bv), acc[0][j], 0, 0, 0);
+        acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av1),
+                                                            __builtin_bit_cast(bf16x8, bv), acc[1][j], 0, 0, 0);
       }
     }
     __syncthreads();
   }
   if (!active) return;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int n = n0 + 16 * j + row;
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = m0 + crow + i;
-      if (m < M && n < N) pb.store(m, n, acc[j][i], z);
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + 16 * j + row;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = m0 + 16 * t + crow + i;
+        if (m < M && n < N) pb.store(m, n, acc[t][j][i], z);
+      }
     }
-  }
 }
 
 // Mean squared error of y against t over `count` values: dL/dy into dy, and the block

@@ -79,9 +79,9 @@ def test_derivatives(ny, nx):
 
 
 @pytest.mark.parametrize("ny,nx", SHAPES[:-1])
-@pytest.mark.parametrize("convection", [0, 1])
+@pytest.mark.parametrize("convection", [0, 1, 4])
 def test_one_step_from_shared_state(convection, ny, nx):
-    """NPS + NPS (convection 0) and LW + NPS (convection 1)."""
+    """NPS + NPS (convection 0), LW + NPS (convection 1) and FL + NPS (convection 4)."""
     p = F.Params(m=NPS, convection=convection)
     with solver(_fields(ny, nx, seed=31 + convection), p) as s:
         s.step(2)

@@ -32,18 +32,19 @@ METRIC = "site·velocity updates/s per FFT-LB step; % HBM roofline; time-to-equi
 
 # Algorithmic bytes per site of each kernel of the step (FP32 values; a packed half
 # spectrum of a real plane is nx*ny/2 complex = one float per site):
-# (the convection columns of the 24 populations with v_y != 0, read and written in place,
-# are split 16 / 8 over the two derivative column launches):
+# (the convection columns of the 24 populations with v_y != 0 are split 16 / 8 over the two
+# derivative column launches; each reads one plane and writes one: the row spectrum in
+# place, or for the 8 along +-y f and the real convection term):
 #   0 stage-1 + convection columns: read 4 moment spectra, write 6 y-derivatives,
-#                         read and write 16 population spectra            ->  42 floats
+#                         read and write 16 population planes             ->  42 floats
 #   1 stage-2 rows:       read 4 + 6 spectra + 4 fields, write 5 spectra + C -> 20
 #   2 stage-2 + convection columns: read 5 spectra, write 3,
-#                         read and write 8 population spectra             ->  24
-#   3 collide rows:       read f (33) + 32 spectra + 3 + C + 4 fields,
-#                         write f (33) + 32 spectra + 4 spectra + 4 fields -> 146
+#                         read and write 8 population planes              ->  24
+#   3 collide rows:       read f (33) + 32 convection planes + 3 + C + 4 fields,
+#                         write f (33) + 24 spectra + 4 spectra + 4 fields -> 138
 STAGES = ("stage1_conv_columns", "stage2_rows", "stage2_conv_columns", "collide_rows")
 STAGE_KERNELS = ("k_col_conv_multi", "k_rows_stage2", "k_col_conv_multi", "k_rows_collide")
-STAGE_FLOATS_PER_SITE = (42, 20, 24, 146)
+STAGE_FLOATS_PER_SITE = (42, 20, 24, 138)
 DOMINANT = 3
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_spinodal1024.json")

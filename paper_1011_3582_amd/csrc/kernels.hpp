@@ -11,7 +11,9 @@
 // Per time step (all derivatives by windowed FFT, Sec. 3.6):
 //   k_col_conv_multi  one launch of two independent column passes: column FFT of the
 //                   row spectra of some of the 24 populations with v_y != 0, multiply by
-//                   i (v_x k_m(kx) + v_y k_m(ky)) / (nx ny), inverse column FFT (in place);
+//                   i (v_x k_m(kx) + v_y k_m(ky)) / (nx ny), inverse column FFT (in place;
+//                   for the 8 moving along +-y, v_x = 0, from f itself to v_y D_y f in real
+//                   space, with no row transforms);
 //                   and a derivative pass of the macroscopic fields: 4 moment spectra -> 6
 //                   y-derivative spectra (stage 1; launched with 16 of the populations),
 //                   5 -> 3 divergence spectra (stage 2; with the other 8);
@@ -19,9 +21,10 @@
 //   k_rows_stage2   inverse row FFTs of the 11 derivatives, the pointwise closure of
 //                   Eqs. (18)-(23), forward row FFTs of the 5 fields whose divergences the
 //                   force needs, FP64 partial sums for the global diagnostics;
-//   k_rows_collide  inverse row FFTs of the convection terms and of the force
-//                   divergences, equilibrium, force, explicit update, moments of f^{n+1},
-//                   forward row FFTs of f^{n+1} and of its moments (inputs of the next step).
+//   k_rows_collide  inverse row FFTs of the convection terms (those of the 8 populations
+//                   along +-y read in real space) and of the force divergences, equilibrium,
+//                   force, explicit update, moments of f^{n+1}, forward row FFTs of f^{n+1}
+//                   (but those along +-y) and of its moments (inputs of the next step).
 // Two real rows are transformed as one complex row (z = a + i b) and separated by
 // Hermitian symmetry.
 #pragma once
@@ -194,6 +197,8 @@ struct ColInst {
   const float* kapy;   // windowed k_y, ny entries
   int nx, tw, id;
   float scale;         // 1 / (nx ny)
+  const float2* freal; // f_0..f_32 in real space, each plane read as [ny][nx/2] pairs of sites
+  float yscale;        // 1 / ny
 };
 
 struct ColArgs {
@@ -565,10 +570,23 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
 // Convection: for each of the 24 moving populations with v_y != 0 (directions i != 1, 5),
 // column FFT, multiply by i (v_x k_m(kx) + v_y k_m(ky)) * scale, inverse column FFT, in
 // place.  The 8 populations moving along +-x need no column transform (see k_rows_collide).
+// The 8 moving along +-y (directions i = 3, 7: v_x = 0) need no row transform: their term
+// v_y D_y f is formed from f itself, two real columns at a time as one complex column (the
+// multiplier is odd in k_y and zero at the Nyquist row, so the two stay apart), and left in
+// real space, row-major, in the population's spectral plane.
 __device__ __forceinline__ int conv_column_plane(int j) {
   // j = 0..23 -> population q - 1 = 8 k + i - 1 with i - 1 in {1, 2, 3, 5, 6, 7}
   const int k = j / 6, r = j % 6;
   return 8 * k + (r < 3 ? r + 1 : r + 2);
+}
+// plane q - 1 of a population moving along +-y (i - 1 = 2 or 6)
+__device__ __forceinline__ bool conv_direct(int p) { return (p & 3) == 2; }
+
+// Row-transform pairs of a speed group in the collide: direction offset (i - 1) of side h
+// (0 = a, 1 = b) of pair p.  All eight directions: (0,1) (2,3) (4,5) (6,7); without the two
+// along +-y (offsets 2, 6; direct): (0,1) (4,5) (3,7).
+constexpr int pair_dir(bool direct, int p, int h) {
+  return direct ? (p == 0 ? h : p == 1 ? 4 + h : 3 + 4 * h) : 2 * p + h;
 }
 
 // Tile b of nblocks (planes pfirst.. of the 24, (nx/2)/CW column tiles each) of one
@@ -581,7 +599,6 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
   const float* __restrict__ kapy = In.kapy;
   const int nx = In.nx;
   const unsigned tw = In.tw;
-  const float scale = In.scale;
   const int tid = threadIdx.x;
   const unsigned ut = static_cast<unsigned>(tid);
   __builtin_assume(ut < static_cast<unsigned>(NT));
@@ -590,7 +607,13 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
   b = xcd_remap(b, nblocks);
   const int p = conv_column_plane(pfirst + b / nsub), sub = b % nsub;
   const unsigned c0 = sub * CW;
-  float2* g = spec + (long)p * (nx / 2) * NY + (long)(c0 / tw) * NY * tw + (c0 % tw);
+  // source and destination: the spectral plane in place (tiles of tw columns), or for a
+  // population along +-y its f plane and, row-major, its spectral plane
+  const bool direct = conv_direct(p);
+  const unsigned stride = direct ? static_cast<unsigned>(nx / 2) : tw;
+  float2* g = spec + (long)p * (nx / 2) * NY + (direct ? (long)c0 : (long)(c0 / tw) * NY * tw + (c0 % tw));
+  const float2* src = direct ? In.freal + (long)(p + 1) * (nx / 2) * NY + c0 : g;
+  const float scale = direct ? In.yscale : In.scale;
   // element e of the block is (y, c) = (e / CW, e % CW); NT is a multiple of CW, so c and
   // the k_x multiplier are fixed per thread.  The k_y of the thread's elements are read
   // with the data, so that their latency is not added after the forward transform.
@@ -606,11 +629,11 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
   const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
   for_strided<NY * CW, NT>(ut, [&](unsigned e) {
     const unsigned y = e / CW, c = e % CW;
-    lds[padu(e)] = elem(g, y * tw + c);
+    lds[padu(e)] = elem(src, y * stride + c);
   });
   __syncthreads();
   fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
-  const float mx = vx * kxv;
+  const float mx = vx * kxv;  // v_x = 0 exactly for the direct planes
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const unsigned e = ut + i * NT;
@@ -624,7 +647,7 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
   fft_lds<NY, +1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
   for_strided<NY * CW, NT>(ut, [&](unsigned e) {
     const unsigned y = e / CW, c = e % CW;
-    elem(g, y * tw + c) = lds[padu(e)];
+    elem(g, y * stride + c) = lds[padu(e)];
   });
 }
 
@@ -1270,7 +1293,8 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 // Collision, force and update (MODE_STEP), or f := f^eq(inputs) (MODE_INIT), or f := input
 // (MODE_SET); then moments of the new f and forward row transforms of f_1..f_32 and of
 // rho, ux, uy, T for the next step.  The 32 moving populations go in four rounds of one
-// speed group (8 populations, 4 complex row transforms) each.
+// speed group (8 populations) each: 4 complex row transforms per round, or 3 when the two
+// along +-y take none (the spectral derivative, not XCOL).
 //
 // COMP: the state is compensated, f = hi + lo with the low parts in P.flo: the update adds
 // every increment exactly (relax_update_comp), the moments add the sums of the low parts,
@@ -1278,7 +1302,7 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 //
 // XCOL: the convection spectra of all 32 moving populations come from a column pass (the
 // finite-difference schemes, k_col_conv_scheme); otherwise the 8 populations moving along
-// +-x take theirs here from their row spectra.
+// +-x take theirs here from their row spectra and the 8 along +-y theirs in real space.
 template <int NX, int MODE, bool COMP = false, bool XCOL = false>
 __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, const Inputs& in, int blk) {
   extern __shared__ float2 lds[];
@@ -1293,28 +1317,32 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   float* mac = P.macro + rb;
   const long hp = P.plane / 2;
 
-  // moving populations: each round covers GPR speed groups (8 GPR populations, 4 GPR
-  // complex row transforms); q = 1 + 8k .. 8 + 8k for group k, transformed as pairs (q, q+1).
-  // The convection spectra of a round are the consecutive planes q0 - 1 .. q0 + 8 GPR - 2;
-  // directions i = 1 and 5 (v along +-x) skipped the column pass: their convection term
-  // v_x D_x f is the row-spectral product i v_x k_x S / nx.
+  // Moving populations: each round covers one speed group (q = 1 + 8k .. 8 + 8k for group
+  // k, directions i = 1..8), transformed as pairs of planes (pair_dir).  The convection
+  // spectra of a round are the consecutive planes q0 - 1 .. q0 + 6.  With the spectral
+  // derivative (DIRECT) directions i = 1 and 5 (v along +-x) skipped the column pass: their
+  // convection term v_x D_x f is the row-spectral product i v_x k_x S / nx; directions i = 3
+  // and 7 (v along +-y) take no row transforms: the column pass forms v_y D_y f from f and
+  // leaves it in real space.  With XCOL all eight directions are transformed and every
+  // convection spectrum comes from a column pass.  The init and set modes pair the planes as
+  // the step does, so that the spectra they write are bitwise those a step would write.
+  static_assert(GPR == 1, "one speed group per round");
+  constexpr bool DIRECT = !XCOL;
+  constexpr int NPR = DIRECT ? 3 : G::NPB;  // pair transforms per round
   auto conv_batch = [&](int rd) {
-    const int q0 = 1 + 8 * GPR * rd;
+    const int q0 = 1 + 8 * rd;
     const float2* S = P.sf + (long)(q0 - 1) * hp;
-    PairBatch<G::NPB> in = empty_batch<G::NPB>();
+    PairBatch<NPR> in = empty_batch<NPR>();
 #pragma unroll
-    for (int p = 0; p < G::NPB; ++p) {
-      set_term(in, p, 0, 0, S + 2 * p * hp, 1.0f, TERM_ONE);
-      set_term(in, p, 1, 0, S + (2 * p + 1) * hp, 1.0f, TERM_ONE);
-    }
-    if constexpr (!XCOL) {
+    for (int p = 0; p < NPR; ++p)
 #pragma unroll
-    for (int g = 0; g < GPR; ++g) {
-      const int qx0 = q0 + 8 * g, qx4 = qx0 + 4;
-      set_term(in, 4 * g + 0, 0, 0, S + (8 * g + 0) * hp, c_vel.vx[qx0] / P.nx, TERM_IKX);
-      set_term(in, 4 * g + 2, 0, 0, S + (8 * g + 4) * hp, c_vel.vx[qx4] / P.nx, TERM_IKX);
-    }
-    }
+      for (int h = 0; h < 2; ++h) {
+        const int d = pair_dir(DIRECT, p, h);
+        if (DIRECT && (d == 0 || d == 4))
+          set_term(in, p, h, 0, S + d * hp, c_vel.vx[q0 + d] / P.nx, TERM_IKX);
+        else
+          set_term(in, p, h, 0, S + d * hp, 1.0f, TERM_ONE);
+      }
     return in;
   };
   // With J = 2 the loads of a round are issued ahead: the next round's convection spectra
@@ -1323,7 +1351,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // registers each).
   constexpr bool PREF = MODE == MODE_STEP && J == 2;
   if constexpr (COMP) __builtin_assume(P.flo != nullptr);
-  BatchFetch<NX, G::NPB> cf;
+  BatchFetch<NX, NPR> cf;
   Site st[J];
   if constexpr (MODE == MODE_STEP) {
     PairBatch<2> b2 = empty_batch<2>();
@@ -1342,7 +1370,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       mt[j] = elem(mac + 3 * P.plane, s);
       mc[j] = elem(P.cpl + rb, s);
     }
-    if constexpr (PREF) cf = rows_fetch_batch<NX, G::NPB>(conv_batch(0), P.sg, P.kapx, row0, tid);
+    if constexpr (PREF) cf = rows_fetch_batch<NX, NPR>(conv_batch(0), P.sg, P.kapx, row0, tid);
     rows_put_batch<NX, 2>(lds, b2, f2, tid);
     __syncthreads();
     rows_inverse_fft<NX, 2>(lds, twx, tid);
@@ -1397,41 +1425,48 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     mx[j] = my[j] = me[j] = 0.0f;
   }
 #pragma unroll 1
-  for (int rd = 0; rd < 4 / GPR; ++rd) {
+  for (int rd = 0; rd < 4; ++rd) {
     const RowThread<NX> rt(opaque(tid));
-    const int q0 = 1 + 8 * GPR * rd;
-    float2* S = P.sf + (long)(q0 - 1) * hp;  // spectra of q0 .. q0 + 8 GPR - 1 are consecutive planes
-    PairBatchOut<G::NPB> io;
+    const int q0 = 1 + 8 * rd;
+    float2* S = P.sf + (long)(q0 - 1) * hp;  // spectra of q0 .. q0 + 7 are consecutive planes
+    PairBatchOut<NPR> io;
 #pragma unroll
-    for (int p = 0; p < G::NPB; ++p) {
-      io.a[p] = S + 2 * p * hp;
-      io.b[p] = S + (2 * p + 1) * hp;
+    for (int p = 0; p < NPR; ++p) {
+      io.a[p] = S + pair_dir(DIRECT, p, 0) * hp;
+      io.b[p] = S + pair_dir(DIRECT, p, 1) * hp;
       io.hb[p] = true;
     }
-    float fpre[PREF ? 2 * G::NPB : 1][J];
+    float fpre[PREF ? 8 : 1][J];
+    float cpre[PREF && DIRECT ? 2 : 1][J];  // convection terms of directions 3 and 7 (real)
     if constexpr (PREF) {
       // the prefetches of a round are issued at a raised wave priority (measured faster:
       // their loads are not held up behind the transform work of the CU's other waves)
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-      for (int i = 0; i < 2 * G::NPB; ++i)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < J; ++j) fpre[i][j] = elem(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
+      if constexpr (DIRECT) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int j = 0; j < J; ++j)
+            cpre[k][j] = elem(reinterpret_cast<const float*>(S + (2 + 4 * k) * hp) + rb, rt.site(j));
+      }
       __builtin_amdgcn_s_setprio(0);
     }
     if constexpr (MODE == MODE_STEP) {
-      const PairBatch<G::NPB> in = conv_batch(rd);
+      const PairBatch<NPR> in = conv_batch(rd);
       if constexpr (PREF) {
-        rows_put_batch<NX, G::NPB>(lds, in, cf, tid);
+        rows_put_batch<NX, NPR>(lds, in, cf, tid);
         __syncthreads();
-        rows_inverse_fft<NX, G::NPB>(lds, twx, tid);
+        rows_inverse_fft<NX, NPR>(lds, twx, tid);
       } else {
-        rows_inverse_batch<NX, G::NPB>(lds, in, P.sg, twx, P.kapx, row0, tid);
+        rows_inverse_batch<NX, NPR>(lds, in, P.sg, twx, P.kapx, row0, tid);
       }
     }
-#pragma unroll
-    for (int g = 0; g < GPR; ++g) {
-      const int k = GPR * rd + g;
+    {
+      const int k = rd;
       const float v2 = c_vel.v2[1 + 8 * k];
       GroupEq ge[J];
       float k0[J];
@@ -1443,9 +1478,10 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         }
       }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int slot = 4 * g + p;
-        const int qa = q0 + 2 * slot, qb = qa + 1;
+      for (int p = 0; p < NPR; ++p) {
+        const int slot = p;
+        const int da = pair_dir(DIRECT, p, 0), db = pair_dir(DIRECT, p, 1);
+        const int qa = q0 + da, qb = q0 + db;
         const float vxa = c_vel.vx[qa], vya = c_vel.vy[qa];
         const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
         float* fA = P.f + (long)qa * P.plane + rb;
@@ -1465,8 +1501,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
             const float eb = feq_moving(st[j], ge[j], vxb, vyb);
             if constexpr (MODE == MODE_STEP) {
               const float2 c = lds[li];
-              const float f0a = PREF ? fpre[2 * slot][j] : elem(fA, x);
-              const float f0b = PREF ? fpre[2 * slot + 1][j] : elem(fB, x);
+              const float f0a = PREF ? fpre[da][j] : elem(fA, x);
+              const float f0b = PREF ? fpre[db][j] : elem(fB, x);
               if constexpr (COMP) {
                 const float2 ha = relax_update_comp(st[j], M, f0a, elem(lA, x), ea, c.x, vxa, vya, k0[j]);
                 const float2 hb = relax_update_comp(st[j], M, f0b, elem(lB, x), eb, c.y, vxb, vyb, k0[j]);
@@ -1503,13 +1539,60 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         // registers)
         if constexpr (!PREF) __builtin_amdgcn_sched_barrier(0);
       }
+      if constexpr (DIRECT) {
+        // directions 3 and 7: the convection term is read in real space; no row transform
+#pragma unroll
+        for (int kd = 0; kd < 2; ++kd) {
+          const int d = 2 + 4 * kd, q = q0 + d;
+          const float vx = c_vel.vx[q], vy = c_vel.vy[q];
+          float* fQ = P.f + (long)q * P.plane + rb;
+          float* lQ = COMP ? P.flo + (long)q * P.plane + rb : nullptr;
+          const float* cQ = reinterpret_cast<const float*>(S + d * hp) + rb;
+#pragma unroll
+          for (int j = 0; j < J; ++j) {
+            const unsigned x = rt.site(j);
+            float fn, ln = 0.0f;
+            if constexpr (MODE == MODE_SET) {
+              fn = elem(in.a[0] + (long)q * P.plane + rb, x);
+            } else {
+              const float e = feq_moving(st[j], ge[j], vx, vy);
+              if constexpr (MODE == MODE_STEP) {
+                const float f0 = PREF ? fpre[d][j] : elem(fQ, x);
+                const float c = PREF ? cpre[kd][j] : elem(cQ, x);
+                if constexpr (COMP) {
+                  const float2 h = relax_update_comp(st[j], M, f0, elem(lQ, x), e, c, vx, vy, k0[j]);
+                  fn = h.x;
+                  ln = h.y;
+                } else {
+                  fn = relax_update(st[j], M, f0, e, c, vx, vy, k0[j]);
+                }
+              } else {
+                fn = rounded(e);
+              }
+            }
+            elem(fQ, x) = fn;
+            if constexpr (COMP) {
+              elem(lQ, x) = ln;
+              l0[j] += ln;
+              lx[j] += vx * ln;
+              ly[j] += vy * ln;
+              le[j] += v2 * ln;
+            }
+            m0[j] += fn;
+            mx[j] += vx * fn;
+            my[j] += vy * fn;
+            me[j] += v2 * fn;
+          }
+          if constexpr (!PREF) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
     }
     if constexpr (PREF) {
       __builtin_amdgcn_s_setprio(1);
-      if (rd + 1 < 4 / GPR) cf = rows_fetch_batch<NX, G::NPB>(conv_batch(rd + 1), P.sg, P.kapx, row0, tid);
+      if (rd + 1 < 4) cf = rows_fetch_batch<NX, NPR>(conv_batch(rd + 1), P.sg, P.kapx, row0, tid);
       __builtin_amdgcn_s_setprio(0);
     }
-    rows_forward_batch<NX, G::NPB>(lds, io, P.sg, twx, row0, tid);
+    rows_forward_batch<NX, NPR>(lds, io, P.sg, twx, row0, tid);
   }
   // moments of the new state and their row spectra
 #pragma unroll

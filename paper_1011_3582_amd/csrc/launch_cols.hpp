@@ -12,7 +12,7 @@ inline ColArgs col_args(const StepLaunch& L, int first, int count, bool conv) {
   for (int k = 0; k < count; ++k) {
     const Inst& I = *L.inst[first + k];
     a.c[k] = ColInst{conv ? I.P.sf : I.spec, I.twy, I.P.kapx, I.kapy, L.nx, L.tw, L.id ? L.id[first + k] : 0,
-                     I.M.scale};
+                     I.M.scale, reinterpret_cast<const float2*>(I.P.f), (float)(1.0 / I.P.ny)};
   }
   return a;
 }

@@ -42,14 +42,23 @@ int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s
         else
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, false>), grid, block, lds, s, a, in);
         break;
+      // init and set pair the row transforms as the step of the instance's scheme does
       case RK_INIT:
-        if (L.comp)
+        if (L.scheme && L.comp)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT, true, true>), grid, block, lds, s, a, in);
+        else if (L.scheme)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT, false, true>), grid, block, lds, s, a, in);
+        else if (L.comp)
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT, true>), grid, block, lds, s, a, in);
         else
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT, false>), grid, block, lds, s, a, in);
         break;
       case RK_SET:
-        if (L.comp)
+        if (L.scheme && L.comp)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET, true, true>), grid, block, lds, s, a, in);
+        else if (L.scheme)
+          hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET, false, true>), grid, block, lds, s, a, in);
+        else if (L.comp)
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET, true>), grid, block, lds, s, a, in);
         else
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_SET, false>), grid, block, lds, s, a, in);

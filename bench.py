@@ -40,11 +40,13 @@ METRIC = "site·velocity updates/s per FFT-LB step; % HBM roofline; time-to-equi
 #   1 stage-2 rows:       read 4 + 6 spectra + 4 fields, write 5 spectra + C -> 20
 #   2 stage-2 + convection columns: read 5 spectra, write 3,
 #                         read and write 8 population planes              ->  24
-#   3 collide rows:       read f (33) + 32 convection planes + 3 + C + 4 fields,
-#                         write f (33) + 24 spectra + 4 spectra + 4 fields -> 138
+#   3 collide rows:       read f (33) + 24 convection planes + 3 + C + 4 fields,
+#                         write f (33) + 16 spectra + 4 spectra + 4 fields -> 122
+#                         (the 8 populations along +-x take their x-derivative from f^n in
+#                         the kernel: no spectra of theirs are stored or read)
 STAGES = ("stage1_conv_columns", "stage2_rows", "stage2_conv_columns", "collide_rows")
 STAGE_KERNELS = ("k_col_conv_multi", "k_rows_stage2", "k_col_conv_multi", "k_rows_collide")
-STAGE_FLOATS_PER_SITE = (42, 20, 24, 138)
+STAGE_FLOATS_PER_SITE = (42, 20, 24, 122)
 DOMINANT = 3
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_spinodal1024.json")

@@ -21,10 +21,12 @@
 //   k_rows_stage2   inverse row FFTs of the 11 derivatives, the pointwise closure of
 //                   Eqs. (18)-(23), forward row FFTs of the 5 fields whose divergences the
 //                   force needs, FP64 partial sums for the global diagnostics;
-//   k_rows_collide  inverse row FFTs of the convection terms (those of the 8 populations
-//                   along +-y read in real space) and of the force divergences, equilibrium,
-//                   force, explicit update, moments of f^{n+1}, forward row FFTs of f^{n+1}
-//                   (but those along +-y) and of its moments (inputs of the next step).
+//   k_rows_collide  inverse row FFTs of the convection spectra of the 16 diagonal
+//                   populations and of the force divergences; the x-derivatives of the 8
+//                   along +-x formed from f^n in the kernel (forward row FFT, i k_x, inverse);
+//                   the terms of the 8 along +-y read in real space; equilibrium, force,
+//                   explicit update, moments of f^{n+1}, forward row FFTs of the diagonal
+//                   f^{n+1} and of the moments (inputs of the next step).
 // Two real rows are transformed as one complex row (z = a + i b) and separated by
 // Hermitian symmetry.
 #pragma once
@@ -556,6 +558,78 @@ __device__ __forceinline__ void rows_forward_batch(float2* lds, const PairBatchO
   __syncthreads();
 }
 
+// Windowed k_x of signed FFT bin m of a length-NX row (odd in m, zero at the Nyquist bin),
+// from kapx[0 .. NX/2 - 1].
+template <int NX>
+__device__ __forceinline__ float kx_of_bin(const float* __restrict__ kapx, unsigned m) {
+  constexpr unsigned H = NX / 2;
+  return m < H ? elem(kapx, m) : m == H ? 0.0f : -elem(kapx, NX - m);
+}
+
+// Slot `slot` of the row batch holds the forward transforms Z of complex rows z = a + i b
+// (a, b real): multiply bin m by i k_x(m) / NX, so that the inverse transform gives
+// D_x a + i D_x b (the multiplier is odd in m and zero at the Nyquist bin, so the two real
+// rows stay apart).  Each thread reads and writes its own elements (no barrier inside).
+template <int NX>
+__device__ __forceinline__ void rows_dx_multiply(float2* lds, int slot, const float* __restrict__ kapx, int tid) {
+  constexpr int RB = RowGeom<NX>::RB, NT = RowGeom<NX>::NT;
+  constexpr float s = 1.0f / NX;
+  float2* L = lds + slot * slot_stride<NX>();
+  const unsigned ut = opaque_tid<NT>(tid);
+  for_strided<RB * NX, NT>(ut, [&](unsigned e) {
+    const float k = kx_of_bin<NX>(kapx, e % NX) * s;
+    const float2 v = L[padu(e)];
+    L[padu(e)] = make_float2(-k * v.y, k * v.x);
+  });
+}
+
+// The same after all passes but the last (radix-2, span H) of pass order 1: the thread of
+// butterfly k (0 <= k < H) forms X(k) = u + w_k t and X(k + H) = u - w_k t from u = Z(k),
+// t = Z(k + H) and multiplies both.
+template <int NX>
+__device__ __forceinline__ void rows_dx_multiply_r2(float2* lds, int slot, const float2* tw_last,
+                                                    const float* __restrict__ kapx, int tid) {
+  constexpr unsigned H = NX / 2;
+  constexpr int RB = RowGeom<NX>::RB, NT = RowGeom<NX>::NT;
+  constexpr float s = 1.0f / NX;
+  float2* L = lds + slot * slot_stride<NX>();
+  const unsigned ut = opaque_tid<NT>(tid);
+  for_strided<RB * H, NT>(ut, [&](unsigned e) {
+    const unsigned rl = e / H, k = e % H;
+    const unsigned z = rl * NX;
+    const float2 u = L[padu(z + k)], t = cmul(L[padu(z + k + H)], tw_last[k]);
+    const float2 x0 = cadd(u, t), x1 = csub(u, t);
+    const float k0 = elem(kapx, k) * s;                          // bin k
+    const float k1 = k == 0 ? 0.0f : -elem(kapx, H - k) * s;      // bin k + H (Nyquist for k = 0)
+    L[padu(z + k)] = make_float2(-k0 * x0.y, k0 * x0.x);
+    L[padu(z + k + H)] = make_float2(-k1 * x1.y, k1 * x1.x);
+  });
+}
+
+// Forward row transforms of NP + 1 slots written (unsynchronised): the packed half spectra
+// of slots 0 .. NP - 1 are stored as by rows_forward_batch, slot NP stays in LDS multiplied
+// by i k_x / NX (rows_dx_multiply).  Ends with a barrier.
+template <int NX, int NP>
+__device__ __forceinline__ void rows_forward_batch_dx(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
+                                                      const float2* twx, const float* __restrict__ kapx, int row0,
+                                                      int tid) {
+  using G = RowGeom<NX>;
+  constexpr bool AL = is_pow2(NX) && (NX % 32 == 0);
+  __syncthreads();
+  if constexpr (G::FUSE_STORE) {
+    const float2* tw1 = twx + NX;
+    fft_lds_part<NX, 1, NX / 2, 1, -1, G::NT, (NP + 1) * G::RB, false, 1, AL, G::RADIX, true>(lds, 0, NX, tw1, tid);
+    const float2* tw_last = tw1 + tw_offset<NX, G::RADIX, NX / 2, 1>();
+    rows_store_batch_r2<NX, NP>(lds, out, sg, tw_last, row0, tid);
+    rows_dx_multiply_r2<NX>(lds, NP, tw_last, kapx, tid);
+  } else {
+    fft_lds<NX, -1, G::NT, (NP + 1) * G::RB, false, 1, AL, G::RADIX, true>(lds, 0, NX, twx, tid);
+    rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
+    rows_dx_multiply<NX>(lds, NP, kapx, tid);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Column kernels
 // ---------------------------------------------------------------------------
@@ -583,11 +657,11 @@ __device__ __forceinline__ int conv_column_plane(int j) {
 __device__ __forceinline__ bool conv_direct(int p) { return (p & 3) == 2; }
 
 // Row-transform pairs of a speed group in the collide: direction offset (i - 1) of side h
-// (0 = a, 1 = b) of pair p.  All eight directions: (0,1) (2,3) (4,5) (6,7); without the two
-// along +-y (offsets 2, 6; direct): (0,1) (4,5) (3,7).
-constexpr int pair_dir(bool direct, int p, int h) {
-  return direct ? (p == 0 ? h : p == 1 ? 4 + h : 3 + 4 * h) : 2 * p + h;
-}
+// (0 = a, 1 = b) of pair p.  All eight directions: (0,1) (2,3) (4,5) (6,7).  With the
+// spectral derivative (direct): the diagonal pairs (1,3) (5,7), then the pair along +-x
+// (0,4), whose x-derivative the collide forms from f^n itself; the two along +-y (2, 6) take
+// no row transforms.
+constexpr int pair_dir(bool direct, int p, int h) { return direct ? (p < 2 ? 1 + 4 * p + 2 * h : 4 * h) : 2 * p + h; }
 
 // Tile b of nblocks (planes pfirst.. of the 24, (nx/2)/CW column tiles each) of one
 // instance.
@@ -1293,8 +1367,8 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 // Collision, force and update (MODE_STEP), or f := f^eq(inputs) (MODE_INIT), or f := input
 // (MODE_SET); then moments of the new f and forward row transforms of f_1..f_32 and of
 // rho, ux, uy, T for the next step.  The 32 moving populations go in four rounds of one
-// speed group (8 populations) each: 4 complex row transforms per round, or 3 when the two
-// along +-y take none (the spectral derivative, not XCOL).
+// speed group (8 populations) each: 4 pair transforms per round (XCOL), or with the spectral
+// derivative 2 diagonal pairs and the +-x pair (see below).
 //
 // COMP: the state is compensated, f = hi + lo with the low parts in P.flo: the update adds
 // every increment exactly (relax_update_comp), the moments add the sums of the low parts,
@@ -1302,7 +1376,7 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 //
 // XCOL: the convection spectra of all 32 moving populations come from a column pass (the
 // finite-difference schemes, k_col_conv_scheme); otherwise the 8 populations moving along
-// +-x take theirs here from their row spectra and the 8 along +-y theirs in real space.
+// +-x take theirs here from f^n and the 8 along +-y theirs in real space.
 template <int NX, int MODE, bool COMP = false, bool XCOL = false>
 __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, const Inputs& in, int blk) {
   extern __shared__ float2 lds[];
@@ -1320,15 +1394,21 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // Moving populations: each round covers one speed group (q = 1 + 8k .. 8 + 8k for group
   // k, directions i = 1..8), transformed as pairs of planes (pair_dir).  The convection
   // spectra of a round are the consecutive planes q0 - 1 .. q0 + 6.  With the spectral
-  // derivative (DIRECT) directions i = 1 and 5 (v along +-x) skipped the column pass: their
-  // convection term v_x D_x f is the row-spectral product i v_x k_x S / nx; directions i = 3
-  // and 7 (v along +-y) take no row transforms: the column pass forms v_y D_y f from f and
-  // leaves it in real space.  With XCOL all eight directions are transformed and every
-  // convection spectrum comes from a column pass.  The init and set modes pair the planes as
-  // the step does, so that the spectra they write are bitwise those a step would write.
+  // derivative (DIRECT) the four diagonal directions take their convection spectra from the
+  // column pass; directions i = 1 and 5 (v along +-x) need only a row derivative: the round
+  // forms z = f_1 + i f_5 (of f^n) in LDS slot NPR, transforms it forward, multiplies by
+  // i k_x / nx and inverse-transforms it with the diagonal spectra, so that their spectra are
+  // neither stored nor read (the next group's z is transformed with the round's forward
+  // batch, the first group's on its own); directions i = 3 and 7 (v along +-y) take no row
+  // transforms: the column pass forms v_y D_y f from f and leaves it in real space.  With
+  // XCOL all eight directions are transformed and every convection spectrum comes from a
+  // column pass.  The init and set modes pair the planes as the step does, so that the
+  // spectra they write are bitwise those a step would write.
   static_assert(GPR == 1, "one speed group per round");
   constexpr bool DIRECT = !XCOL;
-  constexpr int NPR = DIRECT ? 3 : G::NPB;  // pair transforms per round
+  constexpr int NPR = DIRECT ? 2 : G::NPB;  // pairs with stored spectra per round
+  constexpr bool DX = DIRECT && MODE == MODE_STEP;  // the +-x pair in slot NPR
+  constexpr int NIN = DX ? NPR + 1 : NPR;            // slots of the inverse batch
   auto conv_batch = [&](int rd) {
     const int q0 = 1 + 8 * rd;
     const float2* S = P.sf + (long)(q0 - 1) * hp;
@@ -1338,10 +1418,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int d = pair_dir(DIRECT, p, h);
-        if (DIRECT && (d == 0 || d == 4))
-          set_term(in, p, h, 0, S + d * hp, c_vel.vx[q0 + d] / P.nx, TERM_IKX);
-        else
-          set_term(in, p, h, 0, S + d * hp, 1.0f, TERM_ONE);
+        set_term(in, p, h, 0, S + d * hp, 1.0f, TERM_ONE);
       }
     return in;
   };
@@ -1391,6 +1468,19 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       const unsigned s = rt.site(j);
       site_init(st[j], elem(in.a[0] + rb, s), elem(in.a[1] + rb, s), elem(in.a[2] + rb, s), elem(in.a[3] + rb, s));
     }
+  }
+
+  // the first group's +-x pair z = f_1 + i f_5: forward transform and i k_x / nx in slot NPR
+  if constexpr (DX) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const unsigned s = rt.site(j);
+      lds[rt.at(NPR, j)] = make_float2(elem(P.f + P.plane + rb, s), elem(P.f + 5 * P.plane + rb, s));
+    }
+    __syncthreads();
+    fft_lds<NX, -1, G::NT, G::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), G::RADIX, true>(
+        lds, NPR * G::RB * NX, NX, twx, tid);
+    rows_dx_multiply<NX>(lds, NPR, P.kapx, tid);
   }
 
   float m0[J], mx[J], my[J], me[J];
@@ -1460,9 +1550,11 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       if constexpr (PREF) {
         rows_put_batch<NX, NPR>(lds, in, cf, tid);
         __syncthreads();
-        rows_inverse_fft<NX, NPR>(lds, twx, tid);
+        rows_inverse_fft<NX, NIN>(lds, twx, tid);
       } else {
-        rows_inverse_batch<NX, NPR>(lds, in, P.sg, twx, P.kapx, row0, tid);
+        rows_load_batch<NX, NPR>(lds, in, P.sg, P.kapx, row0, tid);
+        __syncthreads();
+        rows_inverse_fft<NX, NIN>(lds, twx, tid);
       }
     }
     {
@@ -1478,7 +1570,9 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         }
       }
 #pragma unroll
-      for (int p = 0; p < NPR; ++p) {
+      for (int p = 0; p < (DIRECT ? NPR + 1 : NPR); ++p) {
+        // p = NPR (direct): the +-x pair, convection D_x f from slot NPR, no forward transform
+        const bool xp = DIRECT && p == NPR;
         const int slot = p;
         const int da = pair_dir(DIRECT, p, 0), db = pair_dir(DIRECT, p, 1);
         const int qa = q0 + da, qb = q0 + db;
@@ -1500,7 +1594,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
             const float ea = feq_moving(st[j], ge[j], vxa, vya);
             const float eb = feq_moving(st[j], ge[j], vxb, vyb);
             if constexpr (MODE == MODE_STEP) {
-              const float2 c = lds[li];
+              float2 c = lds[li];
+              if (xp) c = make_float2(vxa * c.x, vxb * c.y);
               const float f0a = PREF ? fpre[da][j] : elem(fA, x);
               const float f0b = PREF ? fpre[db][j] : elem(fB, x);
               if constexpr (COMP) {
@@ -1533,7 +1628,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
           mx[j] += vxa * fa + vxb * fb;
           my[j] += vya * fa + vyb * fb;
           me[j] += v2 * (fa + fb);
-          lds[li] = make_float2(fa, fb);
+          if (!xp) lds[li] = make_float2(fa, fb);
         }
         // without prefetch: keep one pair's loads in flight at a time (bounds the live
         // registers)
@@ -1592,7 +1687,23 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       if (rd + 1 < 4) cf = rows_fetch_batch<NX, NPR>(conv_batch(rd + 1), P.sg, P.kapx, row0, tid);
       __builtin_amdgcn_s_setprio(0);
     }
-    rows_forward_batch<NX, NPR>(lds, io, P.sg, twx, row0, tid);
+    if constexpr (DX) {
+      if (rd + 1 < 4) {
+        // z of the next group's +-x pair into slot NPR, transformed with this round's batch
+        const int qn = q0 + 8;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const unsigned x = rt.site(j);
+          lds[rt.at(NPR, j)] = make_float2(elem(P.f + (long)qn * P.plane + rb, x),
+                                           elem(P.f + (long)(qn + 4) * P.plane + rb, x));
+        }
+        rows_forward_batch_dx<NX, NPR>(lds, io, P.sg, twx, P.kapx, row0, tid);
+      } else {
+        rows_forward_batch<NX, NPR>(lds, io, P.sg, twx, row0, tid);
+      }
+    } else {
+      rows_forward_batch<NX, NPR>(lds, io, P.sg, twx, row0, tid);
+    }
   }
   // moments of the new state and their row spectra
 #pragma unroll

@@ -1470,12 +1470,18 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     }
   }
 
-  // the first group's +-x pair z = f_1 + i f_5: forward transform and i k_x / nx in slot NPR
+  // the first group's +-x pair z = f_1 + i f_5: forward transform and i k_x / nx in slot NPR.
+  // xf holds the f^n of the +-x pair of the round's group (read once, for z and the update;
+  // not with the compensated state, whose collide has no registers to spare for it).
+  constexpr bool XC = DX && !COMP;
+  float xf[2][J];
   if constexpr (DX) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const unsigned s = rt.site(j);
-      lds[rt.at(NPR, j)] = make_float2(elem(P.f + P.plane + rb, s), elem(P.f + 5 * P.plane + rb, s));
+      xf[0][j] = elem(P.f + P.plane + rb, s);
+      xf[1][j] = elem(P.f + 5 * P.plane + rb, s);
+      lds[rt.at(NPR, j)] = make_float2(xf[0][j], xf[1][j]);
     }
     __syncthreads();
     fft_lds<NX, -1, G::NT, G::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), G::RADIX, true>(
@@ -1533,9 +1539,11 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       // their loads are not held up behind the transform work of the CU's other waves)
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < 8; ++i) {
+        if (XC && (i == 0 || i == 4)) continue;  // in xf
 #pragma unroll
         for (int j = 0; j < J; ++j) fpre[i][j] = elem(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
+      }
       if constexpr (DIRECT) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -1596,8 +1604,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
             if constexpr (MODE == MODE_STEP) {
               float2 c = lds[li];
               if (xp) c = make_float2(vxa * c.x, vxb * c.y);
-              const float f0a = PREF ? fpre[da][j] : elem(fA, x);
-              const float f0b = PREF ? fpre[db][j] : elem(fB, x);
+              const float f0a = XC && xp ? xf[0][j] : PREF ? fpre[da][j] : elem(fA, x);
+              const float f0b = XC && xp ? xf[1][j] : PREF ? fpre[db][j] : elem(fB, x);
               if constexpr (COMP) {
                 const float2 ha = relax_update_comp(st[j], M, f0a, elem(lA, x), ea, c.x, vxa, vya, k0[j]);
                 const float2 hb = relax_update_comp(st[j], M, f0b, elem(lB, x), eb, c.y, vxb, vyb, k0[j]);
@@ -1694,8 +1702,9 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
 #pragma unroll
         for (int j = 0; j < J; ++j) {
           const unsigned x = rt.site(j);
-          lds[rt.at(NPR, j)] = make_float2(elem(P.f + (long)qn * P.plane + rb, x),
-                                           elem(P.f + (long)(qn + 4) * P.plane + rb, x));
+          xf[0][j] = elem(P.f + (long)qn * P.plane + rb, x);
+          xf[1][j] = elem(P.f + (long)(qn + 4) * P.plane + rb, x);
+          lds[rt.at(NPR, j)] = make_float2(xf[0][j], xf[1][j]);
         }
         rows_forward_batch_dx<NX, NPR>(lds, io, P.sg, twx, P.kapx, row0, tid);
       } else {

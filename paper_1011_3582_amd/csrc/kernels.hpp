@@ -117,6 +117,18 @@ __device__ __forceinline__ const T& elem(const T* base, unsigned i) {
   return elem(const_cast<T*>(base), i);
 }
 
+// The populations f^n and f^{n+1} (and the low parts of a compensated state) are read once
+// and written once per step by the collide: non-temporal accesses keep them from displacing,
+// in the caches, the spectra that the column passes read right after the collide (measured
+// at 1024^2: 0.2460 -> 0.2357 ms per step; making the spectra stores non-temporal as well was
+// slower, 0.2396).
+__device__ __forceinline__ float ld_stream(const float* base, unsigned i) {
+  return __builtin_nontemporal_load(&elem(base, i));
+}
+__device__ __forceinline__ void st_stream(float* base, unsigned i, float v) {
+  __builtin_nontemporal_store(v, &elem(base, i));
+}
+
 // Pointers into the workspace (and the caller's buffers for the init/set modes).
 struct Planes {
   float* f;          // [33][ny][nx]
@@ -1479,8 +1491,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const unsigned s = rt.site(j);
-      xf[0][j] = elem(P.f + P.plane + rb, s);
-      xf[1][j] = elem(P.f + 5 * P.plane + rb, s);
+      xf[0][j] = ld_stream(P.f + P.plane + rb, s);
+      xf[1][j] = ld_stream(P.f + 5 * P.plane + rb, s);
       lds[rt.at(NPR, j)] = make_float2(xf[0][j], xf[1][j]);
     }
     __syncthreads();
@@ -1499,21 +1511,21 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     float fn, ln = 0.0f;
     if constexpr (MODE == MODE_STEP) {
       if constexpr (COMP) {
-        const float2 hl = relax_update_comp(st[j], M, elem(P.f + rb, s), elem(P.flo + rb, s), feq_rest(st[j]), 0.0f,
+        const float2 hl = relax_update_comp(st[j], M, ld_stream(P.f + rb, s), ld_stream(P.flo + rb, s), feq_rest(st[j]), 0.0f,
                                             0.0f, 0.0f, force_k0(st[j], M, 0.0f));
         fn = hl.x;
         ln = hl.y;
       } else {
-        fn = relax_update(st[j], M, elem(P.f + rb, s), feq_rest(st[j]), 0.0f, 0.0f, 0.0f, force_k0(st[j], M, 0.0f));
+        fn = relax_update(st[j], M, ld_stream(P.f + rb, s), feq_rest(st[j]), 0.0f, 0.0f, 0.0f, force_k0(st[j], M, 0.0f));
       }
     } else if constexpr (MODE == MODE_INIT) {
       fn = rounded(feq_rest(st[j]));
     } else {
       fn = elem(in.a[0] + rb, s);
     }
-    elem(P.f + rb, s) = fn;
+    st_stream(P.f + rb, s, fn);
     if constexpr (COMP) {
-      elem(P.flo + rb, s) = ln;
+      st_stream(P.flo + rb, s, ln);
       l0[j] = ln;
       lx[j] = ly[j] = le[j] = 0.0f;
     }
@@ -1542,7 +1554,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       for (int i = 0; i < 8; ++i) {
         if (XC && (i == 0 || i == 4)) continue;  // in xf
 #pragma unroll
-        for (int j = 0; j < J; ++j) fpre[i][j] = elem(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
+        for (int j = 0; j < J; ++j) fpre[i][j] = ld_stream(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
       }
       if constexpr (DIRECT) {
 #pragma unroll
@@ -1604,11 +1616,11 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
             if constexpr (MODE == MODE_STEP) {
               float2 c = lds[li];
               if (xp) c = make_float2(vxa * c.x, vxb * c.y);
-              const float f0a = XC && xp ? xf[0][j] : PREF ? fpre[da][j] : elem(fA, x);
-              const float f0b = XC && xp ? xf[1][j] : PREF ? fpre[db][j] : elem(fB, x);
+              const float f0a = XC && xp ? xf[0][j] : PREF ? fpre[da][j] : ld_stream(fA, x);
+              const float f0b = XC && xp ? xf[1][j] : PREF ? fpre[db][j] : ld_stream(fB, x);
               if constexpr (COMP) {
-                const float2 ha = relax_update_comp(st[j], M, f0a, elem(lA, x), ea, c.x, vxa, vya, k0[j]);
-                const float2 hb = relax_update_comp(st[j], M, f0b, elem(lB, x), eb, c.y, vxb, vyb, k0[j]);
+                const float2 ha = relax_update_comp(st[j], M, f0a, ld_stream(lA, x), ea, c.x, vxa, vya, k0[j]);
+                const float2 hb = relax_update_comp(st[j], M, f0b, ld_stream(lB, x), eb, c.y, vxb, vyb, k0[j]);
                 fa = ha.x;
                 la = ha.y;
                 fb = hb.x;
@@ -1622,11 +1634,11 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
               fb = rounded(eb);
             }
           }
-          elem(fA, x) = fa;
-          elem(fB, x) = fb;
+          st_stream(fA, x, fa);
+          st_stream(fB, x, fb);
           if constexpr (COMP) {
-            elem(lA, x) = la;
-            elem(lB, x) = lb;
+            st_stream(lA, x, la);
+            st_stream(lB, x, lb);
             l0[j] += la + lb;
             lx[j] += vxa * la + vxb * lb;
             ly[j] += vya * la + vyb * lb;
@@ -1660,10 +1672,10 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
             } else {
               const float e = feq_moving(st[j], ge[j], vx, vy);
               if constexpr (MODE == MODE_STEP) {
-                const float f0 = PREF ? fpre[d][j] : elem(fQ, x);
+                const float f0 = PREF ? fpre[d][j] : ld_stream(fQ, x);
                 const float c = PREF ? cpre[kd][j] : elem(cQ, x);
                 if constexpr (COMP) {
-                  const float2 h = relax_update_comp(st[j], M, f0, elem(lQ, x), e, c, vx, vy, k0[j]);
+                  const float2 h = relax_update_comp(st[j], M, f0, ld_stream(lQ, x), e, c, vx, vy, k0[j]);
                   fn = h.x;
                   ln = h.y;
                 } else {
@@ -1673,9 +1685,9 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
                 fn = rounded(e);
               }
             }
-            elem(fQ, x) = fn;
+            st_stream(fQ, x, fn);
             if constexpr (COMP) {
-              elem(lQ, x) = ln;
+              st_stream(lQ, x, ln);
               l0[j] += ln;
               lx[j] += vx * ln;
               ly[j] += vy * ln;
@@ -1702,8 +1714,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
 #pragma unroll
         for (int j = 0; j < J; ++j) {
           const unsigned x = rt.site(j);
-          xf[0][j] = elem(P.f + (long)qn * P.plane + rb, x);
-          xf[1][j] = elem(P.f + (long)(qn + 4) * P.plane + rb, x);
+          xf[0][j] = ld_stream(P.f + (long)qn * P.plane + rb, x);
+          xf[1][j] = ld_stream(P.f + (long)(qn + 4) * P.plane + rb, x);
           lds[rt.at(NPR, j)] = make_float2(xf[0][j], xf[1][j]);
         }
         rows_forward_batch_dx<NX, NPR>(lds, io, P.sg, twx, P.kapx, row0, tid);

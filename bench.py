@@ -33,20 +33,19 @@ METRIC = "site·velocity updates/s per FFT-LB step; % HBM roofline; time-to-equi
 # Algorithmic bytes per site of each kernel of the step (FP32 values; a packed half
 # spectrum of a real plane is nx*ny/2 complex = one float per site):
 # (the convection columns of the 24 populations with v_y != 0 are split 16 / 8 over the two
-# derivative column launches; each reads one plane and writes one: the row spectrum in
-# place, or for the 8 along +-y f and the real convection term):
+# derivative column launches; each reads its f plane and writes the real y-part v_y D_y f):
 #   0 stage-1 + convection columns: read 4 moment spectra, write 6 y-derivatives,
 #                         read and write 16 population planes             ->  42 floats
 #   1 stage-2 rows:       read 4 + 6 spectra + 4 fields, write 5 spectra + C -> 20
 #   2 stage-2 + convection columns: read 5 spectra, write 3,
 #                         read and write 8 population planes              ->  24
-#   3 collide rows:       read f (33) + 24 convection planes + 3 + C + 4 fields,
-#                         write f (33) + 16 spectra + 4 spectra + 4 fields -> 122
-#                         (the 8 populations along +-x take their x-derivative from f^n in
-#                         the kernel: no spectra of theirs are stored or read)
+#   3 collide rows:       read f (33) + 24 y-parts + 3 + C + 4 fields,
+#                         write f (33) + 4 moment spectra + 4 fields       -> 106
+#                         (the x-parts v_x D_x f are formed from f^n in the kernel: no
+#                         population spectra are stored or read)
 STAGES = ("stage1_conv_columns", "stage2_rows", "stage2_conv_columns", "collide_rows")
 STAGE_KERNELS = ("k_col_conv_multi", "k_rows_stage2", "k_col_conv_multi", "k_rows_collide")
-STAGE_FLOATS_PER_SITE = (42, 20, 24, 122)
+STAGE_FLOATS_PER_SITE = (42, 20, 24, 106)
 DOMINANT = 3
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_spinodal1024.json")

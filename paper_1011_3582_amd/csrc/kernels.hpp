@@ -9,11 +9,10 @@
 //     (kx / TW) * ny * TW + y * TW + (kx % TW).
 //
 // Per time step (all derivatives by windowed FFT, Sec. 3.6):
-//   k_col_conv_multi  one launch of two independent column passes: column FFT of the
-//                   row spectra of some of the 24 populations with v_y != 0, multiply by
-//                   i (v_x k_m(kx) + v_y k_m(ky)) / (nx ny), inverse column FFT (in place;
-//                   for the 8 moving along +-y, v_x = 0, from f itself to v_y D_y f in real
-//                   space, with no row transforms);
+//   k_col_conv_multi  one launch of two independent column passes: the y-parts v_y D_y f of
+//                   the convection terms of some of the 24 populations with v_y != 0, formed
+//                   from f (column FFT, i v_y k_m(ky) / ny, inverse column FFT) and left in
+//                   real space;
 //                   and a derivative pass of the macroscopic fields: 4 moment spectra -> 6
 //                   y-derivative spectra (stage 1; launched with 16 of the populations),
 //                   5 -> 3 divergence spectra (stage 2; with the other 8);
@@ -21,12 +20,12 @@
 //   k_rows_stage2   inverse row FFTs of the 11 derivatives, the pointwise closure of
 //                   Eqs. (18)-(23), forward row FFTs of the 5 fields whose divergences the
 //                   force needs, FP64 partial sums for the global diagnostics;
-//   k_rows_collide  inverse row FFTs of the convection spectra of the 16 diagonal
-//                   populations and of the force divergences; the x-derivatives of the 8
-//                   along +-x formed from f^n in the kernel (forward row FFT, i k_x, inverse);
-//                   the terms of the 8 along +-y read in real space; equilibrium, force,
-//                   explicit update, moments of f^{n+1}, forward row FFTs of the diagonal
-//                   f^{n+1} and of the moments (inputs of the next step).
+//   k_rows_collide  inverse row FFTs of the force divergences; the x-parts v_x D_x f of
+//                   the 24 populations with v_x != 0 formed from f^n (forward row FFT, i k_x,
+//                   inverse); the y-parts read in real space; equilibrium, force, explicit
+//                   update, moments of f^{n+1} and their forward row FFTs (inputs of the next
+//                   step).  With the finite-difference schemes the collide instead takes every
+//                   convection spectrum from a column pass and writes the row spectra of f^{n+1}.
 // Two real rows are transformed as one complex row (z = a + i b) and separated by
 // Hermitian symmetry.
 #pragma once
@@ -618,28 +617,26 @@ __device__ __forceinline__ void rows_dx_multiply_r2(float2* lds, int slot, const
   });
 }
 
-// Forward row transforms of NP + 1 slots written (unsynchronised): the packed half spectra
-// of slots 0 .. NP - 1 are stored as by rows_forward_batch, slot NP stays in LDS multiplied
-// by i k_x / NX (rows_dx_multiply).  Ends with a barrier.
-template <int NX, int NP>
-__device__ __forceinline__ void rows_forward_batch_dx(float2* lds, const PairBatchOut<NP>& out, const SpecGeom& sg,
-                                                      const float2* twx, const float* __restrict__ kapx, int row0,
-                                                      int tid) {
+// Forward row transforms of slots 0 .. NS - 1 written (unsynchronised), each multiplied by
+// i k_x / NX in place (rows_dx_multiply): after an inverse transform they hold D_x of their
+// two real rows.  No barrier at the end (callers have one before the next transform).
+template <int NX, int NS>
+__device__ __forceinline__ void rows_dx_forward(float2* lds, const float2* twx, const float* __restrict__ kapx,
+                                                int tid) {
   using G = RowGeom<NX>;
   constexpr bool AL = is_pow2(NX) && (NX % 32 == 0);
   __syncthreads();
   if constexpr (G::FUSE_STORE) {
     const float2* tw1 = twx + NX;
-    fft_lds_part<NX, 1, NX / 2, 1, -1, G::NT, (NP + 1) * G::RB, false, 1, AL, G::RADIX, true>(lds, 0, NX, tw1, tid);
+    fft_lds_part<NX, 1, NX / 2, 1, -1, G::NT, NS * G::RB, false, 1, AL, G::RADIX, true>(lds, 0, NX, tw1, tid);
     const float2* tw_last = tw1 + tw_offset<NX, G::RADIX, NX / 2, 1>();
-    rows_store_batch_r2<NX, NP>(lds, out, sg, tw_last, row0, tid);
-    rows_dx_multiply_r2<NX>(lds, NP, tw_last, kapx, tid);
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) rows_dx_multiply_r2<NX>(lds, sl, tw_last, kapx, tid);
   } else {
-    fft_lds<NX, -1, G::NT, (NP + 1) * G::RB, false, 1, AL, G::RADIX, true>(lds, 0, NX, twx, tid);
-    rows_store_batch<NX, NP>(lds, out, sg, row0, tid);
-    rows_dx_multiply<NX>(lds, NP, kapx, tid);
+    fft_lds<NX, -1, G::NT, NS * G::RB, false, 1, AL, G::RADIX, true>(lds, 0, NX, twx, tid);
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) rows_dx_multiply<NX>(lds, sl, kapx, tid);
   }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -653,38 +650,34 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return (b % 8) * (nblocks / 8) + b / 8;
 }
 
-// Convection: for each of the 24 moving populations with v_y != 0 (directions i != 1, 5),
-// column FFT, multiply by i (v_x k_m(kx) + v_y k_m(ky)) * scale, inverse column FFT, in
-// place.  The 8 populations moving along +-x need no column transform (see k_rows_collide).
-// The 8 moving along +-y (directions i = 3, 7: v_x = 0) need no row transform: their term
-// v_y D_y f is formed from f itself, two real columns at a time as one complex column (the
-// multiplier is odd in k_y and zero at the Nyquist row, so the two stay apart), and left in
-// real space, row-major, in the population's spectral plane.
+// Convection with the spectral derivative: the term v.grad f = v_x D_x f + v_y D_y f of a
+// population splits by axis (the 2D multiplier i (v_x k_m(kx) + v_y k_m(ky)) is a sum of
+// one-axis multipliers).  The column pass forms the y-part v_y D_y f of each of the 24
+// moving populations with v_y != 0 (directions i != 1, 5) from f itself, two real columns
+// at a time as one complex column (the multiplier is odd in k_y and zero at the Nyquist row,
+// so the two stay apart), and leaves it in real space, row-major, in the population's
+// spectral plane; the collide forms the x-parts from f^n along its rows.  No population is
+// row-transformed between the kernels.
 __device__ __forceinline__ int conv_column_plane(int j) {
   // j = 0..23 -> population q - 1 = 8 k + i - 1 with i - 1 in {1, 2, 3, 5, 6, 7}
   const int k = j / 6, r = j % 6;
   return 8 * k + (r < 3 ? r + 1 : r + 2);
 }
-// plane q - 1 of a population moving along +-y (i - 1 = 2 or 6)
-__device__ __forceinline__ bool conv_direct(int p) { return (p & 3) == 2; }
 
-// Row-transform pairs of a speed group in the collide: direction offset (i - 1) of side h
-// (0 = a, 1 = b) of pair p.  All eight directions: (0,1) (2,3) (4,5) (6,7).  With the
-// spectral derivative (direct): the diagonal pairs (1,3) (5,7), then the pair along +-x
-// (0,4), whose x-derivative the collide forms from f^n itself; the two along +-y (2, 6) take
-// no row transforms.
-constexpr int pair_dir(bool direct, int p, int h) { return direct ? (p < 2 ? 1 + 4 * p + 2 * h : 4 * h) : 2 * p + h; }
+// Pairs of the collide's row transforms.  Finite-difference schemes (every convection
+// spectrum from a column pass): direction offsets (i - 1) (0,1) (2,3) (4,5) (6,7) of a speed
+// group, spectra stored and read.  Spectral derivative: the x-derivative pairs (0,4) (1,3)
+// (5,7) of the six directions with v_x != 0, formed from f^n in the collide.
+constexpr int pair_dir(bool direct, int p, int h) { return direct ? (p == 0 ? 4 * h : 4 * p - 3 + 2 * h) : 2 * p + h; }
 
 // Tile b of nblocks (planes pfirst.. of the 24, (nx/2)/CW column tiles each) of one
-// instance.
+// instance: v_y D_y f of population p + 1 (f plane p + 1 read as [ny][nx/2] pairs of sites)
+// into spectral plane p, both row-major.
 template <int NY, int CW, int NT, int R>
 __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, int b, int nblocks, int pfirst) {
-  float2* __restrict__ spec = In.spec;
   const float2* twy = In.twy;
-  const float* __restrict__ kapx = In.kapx;
   const float* __restrict__ kapy = In.kapy;
   const int nx = In.nx;
-  const unsigned tw = In.tw;
   const int tid = threadIdx.x;
   const unsigned ut = static_cast<unsigned>(tid);
   __builtin_assume(ut < static_cast<unsigned>(NT));
@@ -693,16 +686,11 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
   b = xcd_remap(b, nblocks);
   const int p = conv_column_plane(pfirst + b / nsub), sub = b % nsub;
   const unsigned c0 = sub * CW;
-  // source and destination: the spectral plane in place (tiles of tw columns), or for a
-  // population along +-y its f plane and, row-major, its spectral plane
-  const bool direct = conv_direct(p);
-  const unsigned stride = direct ? static_cast<unsigned>(nx / 2) : tw;
-  float2* g = spec + (long)p * (nx / 2) * NY + (direct ? (long)c0 : (long)(c0 / tw) * NY * tw + (c0 % tw));
-  const float2* src = direct ? In.freal + (long)(p + 1) * (nx / 2) * NY + c0 : g;
-  const float scale = direct ? In.yscale : In.scale;
-  // element e of the block is (y, c) = (e / CW, e % CW); NT is a multiple of CW, so c and
-  // the k_x multiplier are fixed per thread.  The k_y of the thread's elements are read
-  // with the data, so that their latency is not added after the forward transform.
+  const unsigned stride = static_cast<unsigned>(nx / 2);
+  float2* g = In.spec + (long)p * (nx / 2) * NY + c0;
+  const float2* src = In.freal + (long)(p + 1) * (nx / 2) * NY + c0;
+  // element e of the block is (y, c) = (e / CW, e % CW).  The k_y of the thread's elements
+  // are read with the data, so that their latency is not added after the forward transform.
   constexpr int IT = (NY * CW + NT - 1) / NT;
   constexpr bool FULL = (NY * CW) % NT == 0;
   float kyv[IT];
@@ -711,20 +699,18 @@ __device__ __forceinline__ void col_conv_body(const ColInst& In, float2* lds, in
     const unsigned e = ut + i * NT;
     kyv[i] = (FULL || e < static_cast<unsigned>(NY * CW)) ? elem(kapy, e / CW) : 0.0f;
   }
-  const float kxv = elem(kapx, c0 + ut % CW);
-  const float vx = c_vel.vx[p + 1], vy = c_vel.vy[p + 1];
+  const float vys = c_vel.vy[p + 1] * In.yscale;
   for_strided<NY * CW, NT>(ut, [&](unsigned e) {
     const unsigned y = e / CW, c = e % CW;
     lds[padu(e)] = elem(src, y * stride + c);
   });
   __syncthreads();
   fft_lds<NY, -1, NT, CW, true, CW, is_pow2(NY) && (NY * CW % 32 == 0), R>(lds, 0, 1, twy, tid);
-  const float mx = vx * kxv;  // v_x = 0 exactly for the direct planes
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const unsigned e = ut + i * NT;
     if (FULL || e < static_cast<unsigned>(NY * CW)) {
-      const float m = (mx + vy * kyv[i]) * scale;
+      const float m = vys * kyv[i];
       const float2 v = lds[padu(e)];
       lds[padu(e)] = make_float2(-m * v.y, m * v.x);
     }
@@ -1380,15 +1366,15 @@ enum : int { MODE_STEP = 0, MODE_INIT = 1, MODE_SET = 2 };
 // (MODE_SET); then moments of the new f and forward row transforms of f_1..f_32 and of
 // rho, ux, uy, T for the next step.  The 32 moving populations go in four rounds of one
 // speed group (8 populations) each: 4 pair transforms per round (XCOL), or with the spectral
-// derivative 2 diagonal pairs and the +-x pair (see below).
+// derivative the 3 x-derivative pairs (see below).
 //
 // COMP: the state is compensated, f = hi + lo with the low parts in P.flo: the update adds
 // every increment exactly (relax_update_comp), the moments add the sums of the low parts,
 // and the row transforms (the next convection terms) take hi; INIT and SET zero lo.
 //
 // XCOL: the convection spectra of all 32 moving populations come from a column pass (the
-// finite-difference schemes, k_col_conv_scheme); otherwise the 8 populations moving along
-// +-x take theirs here from f^n and the 8 along +-y theirs in real space.
+// finite-difference schemes, k_col_conv_scheme); otherwise the x-parts of the convection
+// terms are formed here from f^n and the y-parts are read in real space.
 template <int NX, int MODE, bool COMP = false, bool XCOL = false>
 __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, const Inputs& in, int blk) {
   extern __shared__ float2 lds[];
@@ -1404,23 +1390,19 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   const long hp = P.plane / 2;
 
   // Moving populations: each round covers one speed group (q = 1 + 8k .. 8 + 8k for group
-  // k, directions i = 1..8), transformed as pairs of planes (pair_dir).  The convection
-  // spectra of a round are the consecutive planes q0 - 1 .. q0 + 6.  With the spectral
-  // derivative (DIRECT) the four diagonal directions take their convection spectra from the
-  // column pass; directions i = 1 and 5 (v along +-x) need only a row derivative: the round
-  // forms z = f_1 + i f_5 (of f^n) in LDS slot NPR, transforms it forward, multiplies by
-  // i k_x / nx and inverse-transforms it with the diagonal spectra, so that their spectra are
-  // neither stored nor read (the next group's z is transformed with the round's forward
-  // batch, the first group's on its own); directions i = 3 and 7 (v along +-y) take no row
-  // transforms: the column pass forms v_y D_y f from f and leaves it in real space.  With
-  // XCOL all eight directions are transformed and every convection spectrum comes from a
-  // column pass.  The init and set modes pair the planes as the step does, so that the
-  // spectra they write are bitwise those a step would write.
+  // k, directions i = 1..8).  With XCOL, four pair transforms of the group (pair_dir): the
+  // inverse transforms of their convection spectra (consecutive planes q0 - 1 .. q0 + 6) at
+  // the start, the forward transforms of f^{n+1} (the next spectra) at the end.  With the
+  // spectral derivative (DIRECT) no population spectra exist: the convection term is
+  // v_x D_x f + v_y D_y f, the y-parts come in real space from the column pass, and the x-parts
+  // of the six directions with v_x != 0 are formed here from f^n: three pairs z = f_a + i f_b
+  // (pair_dir) transformed forward and multiplied by i k_x / nx at the end of the previous
+  // round (the first group's after the force transforms) and inverse-transformed at the
+  // start of the round.
   static_assert(GPR == 1, "one speed group per round");
   constexpr bool DIRECT = !XCOL;
-  constexpr int NPR = DIRECT ? 2 : G::NPB;  // pairs with stored spectra per round
-  constexpr bool DX = DIRECT && MODE == MODE_STEP;  // the +-x pair in slot NPR
-  constexpr int NIN = DX ? NPR + 1 : NPR;            // slots of the inverse batch
+  constexpr int NPR = G::NPB;  // pair transforms per round with XCOL
+  constexpr int NX3 = 3;       // x-derivative pairs per round with DIRECT
   auto conv_batch = [&](int rd) {
     const int q0 = 1 + 8 * rd;
     const float2* S = P.sf + (long)(q0 - 1) * hp;
@@ -1459,7 +1441,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       mt[j] = elem(mac + 3 * P.plane, s);
       mc[j] = elem(P.cpl + rb, s);
     }
-    if constexpr (PREF) cf = rows_fetch_batch<NX, NPR>(conv_batch(0), P.sg, P.kapx, row0, tid);
+    if constexpr (PREF && !DIRECT) cf = rows_fetch_batch<NX, NPR>(conv_batch(0), P.sg, P.kapx, row0, tid);
     rows_put_batch<NX, 2>(lds, b2, f2, tid);
     __syncthreads();
     rows_inverse_fft<NX, 2>(lds, twx, tid);
@@ -1482,24 +1464,29 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     }
   }
 
-  // the first group's +-x pair z = f_1 + i f_5: forward transform and i k_x / nx in slot NPR.
-  // xf holds the f^n of the +-x pair of the round's group (read once, for z and the update;
-  // not with the compensated state, whose collide has no registers to spare for it).
+  // DIRECT: xz holds the f^n of the round's six directions with v_x != 0 in pair order
+  // (read once, for the transforms and the update; with the compensated state, whose collide
+  // has no registers to spare, only for the transforms)
+  constexpr bool DX = DIRECT && MODE == MODE_STEP;
   constexpr bool XC = DX && !COMP;
-  float xf[2][J];
-  if constexpr (DX) {
+  float xz[DX ? 2 * NX3 : 1][J];
+  // the x-derivative pairs of group k of f^n into slots 0..2, forward-transformed and
+  // multiplied by i k_x / nx
+  auto x_pairs = [&](int k) {
+    const RowThread<NX> rt(opaque(tid));
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const unsigned s = rt.site(j);
-      xf[0][j] = ld_stream(P.f + P.plane + rb, s);
-      xf[1][j] = ld_stream(P.f + 5 * P.plane + rb, s);
-      lds[rt.at(NPR, j)] = make_float2(xf[0][j], xf[1][j]);
-    }
-    __syncthreads();
-    fft_lds<NX, -1, G::NT, G::RB, false, 1, is_pow2(NX) && (NX % 32 == 0), G::RADIX, true>(
-        lds, NPR * G::RB * NX, NX, twx, tid);
-    rows_dx_multiply<NX>(lds, NPR, P.kapx, tid);
-  }
+    for (int sl = 0; sl < NX3; ++sl)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const unsigned x = rt.site(j);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          xz[2 * sl + h][j] = ld_stream(P.f + (long)(1 + 8 * k + pair_dir(true, sl, h)) * P.plane + rb, x);
+        lds[rt.at(sl, j)] = make_float2(xz[2 * sl][j], xz[2 * sl + 1][j]);
+      }
+    rows_dx_forward<NX, NX3>(lds, twx, P.kapx, tid);
+  };
+  if constexpr (DX) x_pairs(0);
 
   float m0[J], mx[J], my[J], me[J];
   // sums of the low parts of a compensated state (moments of hi + lo = moments of hi + these)
@@ -1532,52 +1519,33 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
     m0[j] = fn;
     mx[j] = my[j] = me[j] = 0.0f;
   }
+  if constexpr (DIRECT) {
 #pragma unroll 1
-  for (int rd = 0; rd < 4; ++rd) {
-    const RowThread<NX> rt(opaque(tid));
-    const int q0 = 1 + 8 * rd;
-    float2* S = P.sf + (long)(q0 - 1) * hp;  // spectra of q0 .. q0 + 7 are consecutive planes
-    PairBatchOut<NPR> io;
-#pragma unroll
-    for (int p = 0; p < NPR; ++p) {
-      io.a[p] = S + pair_dir(DIRECT, p, 0) * hp;
-      io.b[p] = S + pair_dir(DIRECT, p, 1) * hp;
-      io.hb[p] = true;
-    }
-    float fpre[PREF ? 8 : 1][J];
-    float cpre[PREF && DIRECT ? 2 : 1][J];  // convection terms of directions 3 and 7 (real)
-    if constexpr (PREF) {
-      // the prefetches of a round are issued at a raised wave priority (measured faster:
-      // their loads are not held up behind the transform work of the CU's other waves)
-      __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        if (XC && (i == 0 || i == 4)) continue;  // in xf
-#pragma unroll
-        for (int j = 0; j < J; ++j) fpre[i][j] = ld_stream(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
-      }
-      if constexpr (DIRECT) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-          for (int j = 0; j < J; ++j)
-            cpre[k][j] = elem(reinterpret_cast<const float*>(S + (2 + 4 * k) * hp) + rb, rt.site(j));
-      }
-      __builtin_amdgcn_s_setprio(0);
-    }
-    if constexpr (MODE == MODE_STEP) {
-      const PairBatch<NPR> in = conv_batch(rd);
+    for (int rd = 0; rd < 4; ++rd) {
+      const RowThread<NX> rt(opaque(tid));
+      const int q0 = 1 + 8 * rd;
+      // the y-parts v_y D_y f of the group: plane of direction offset d at cy + d * plane
+      const float* cy = reinterpret_cast<const float*>(P.sf + (long)(q0 - 1) * hp) + rb;
+      float fy[PREF ? 2 : 1][J];   // f^n of the two along +-y
+      float cyv[PREF ? 8 : 1][J];  // y-parts by direction offset (0 and 4 unused)
       if constexpr (PREF) {
-        rows_put_batch<NX, NPR>(lds, in, cf, tid);
-        __syncthreads();
-        rows_inverse_fft<NX, NIN>(lds, twx, tid);
-      } else {
-        rows_load_batch<NX, NPR>(lds, in, P.sg, P.kapx, row0, tid);
-        __syncthreads();
-        rows_inverse_fft<NX, NIN>(lds, twx, tid);
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int kd = 0; kd < 2; ++kd)
+#pragma unroll
+          for (int j = 0; j < J; ++j) fy[kd][j] = ld_stream(P.f + (long)(q0 + 2 + 4 * kd) * P.plane + rb, rt.site(j));
+#pragma unroll
+        for (int d = 1; d < 8; ++d) {
+          if (d == 4) continue;
+#pragma unroll
+          for (int j = 0; j < J; ++j) cyv[d][j] = elem(cy + d * P.plane, rt.site(j));
+        }
+        __builtin_amdgcn_s_setprio(0);
       }
-    }
-    {
+      if constexpr (MODE == MODE_STEP) {
+        __syncthreads();
+        rows_inverse_fft<NX, NX3>(lds, twx, tid);
+      }
       const int k = rd;
       const float v2 = c_vel.v2[1 + 8 * k];
       GroupEq ge[J];
@@ -1589,140 +1557,197 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
           k0[j] = force_k0(st[j], M, v2);
         }
       }
+      // the group's sums of f^{n+1} (and of the low parts), added to the moments once per group:
+      // populations of one speed group have similar magnitudes, so this keeps the FP32
+      // rounding of the moments small
+      float s0[J], sx[J], sy[J], sl[COMP ? J : 1], slx[COMP ? J : 1], sly[COMP ? J : 1];
 #pragma unroll
-      for (int p = 0; p < (DIRECT ? NPR + 1 : NPR); ++p) {
-        // p = NPR (direct): the +-x pair, convection D_x f from slot NPR, no forward transform
-        const bool xp = DIRECT && p == NPR;
-        const int slot = p;
-        const int da = pair_dir(DIRECT, p, 0), db = pair_dir(DIRECT, p, 1);
-        const int qa = q0 + da, qb = q0 + db;
-        const float vxa = c_vel.vx[qa], vya = c_vel.vy[qa];
-        const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
-        float* fA = P.f + (long)qa * P.plane + rb;
-        float* fB = P.f + (long)qb * P.plane + rb;
-        float* lA = COMP ? P.flo + (long)qa * P.plane + rb : nullptr;
-        float* lB = COMP ? P.flo + (long)qb * P.plane + rb : nullptr;
+      for (int j = 0; j < J; ++j) {
+        s0[j] = sx[j] = sy[j] = 0.0f;
+        if constexpr (COMP) sl[j] = slx[j] = sly[j] = 0.0f;
+      }
+      // u = 0..5: the six with v_x != 0 (pair u / 2, side u % 2); u = 6, 7: the two along +-y
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool xd = u < 6;
+        const int d = xd ? pair_dir(true, u / 2, u % 2) : 2 + 4 * (u - 6);
+        const int q = q0 + d;
+        const bool hy = d != 0 && d != 4;  // has a y-part
+        const float vx = c_vel.vx[q], vy = c_vel.vy[q];
+        float* fQ = P.f + (long)q * P.plane + rb;
+        float* lQ = COMP ? P.flo + (long)q * P.plane + rb : nullptr;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
           const unsigned x = rt.site(j);
-          const unsigned li = rt.at(slot, j);
-          float fa, fb, la = 0.0f, lb = 0.0f;
+          float fn, ln = 0.0f;
           if constexpr (MODE == MODE_SET) {
-            fa = elem(in.a[0] + (long)qa * P.plane + rb, x);
-            fb = elem(in.a[0] + (long)qb * P.plane + rb, x);
+            fn = elem(in.a[0] + (long)q * P.plane + rb, x);
           } else {
-            const float ea = feq_moving(st[j], ge[j], vxa, vya);
-            const float eb = feq_moving(st[j], ge[j], vxb, vyb);
+            const float e = feq_moving(st[j], ge[j], vx, vy);
             if constexpr (MODE == MODE_STEP) {
-              float2 c = lds[li];
-              if (xp) c = make_float2(vxa * c.x, vxb * c.y);
-              const float f0a = XC && xp ? xf[0][j] : PREF ? fpre[da][j] : ld_stream(fA, x);
-              const float f0b = XC && xp ? xf[1][j] : PREF ? fpre[db][j] : ld_stream(fB, x);
+              float c = hy ? (PREF ? cyv[d][j] : elem(cy + d * P.plane, x)) : 0.0f;
+              if (xd) {
+                const float2 z = lds[rt.at(u / 2, j)];
+                c = fmaf(vx, u % 2 ? z.y : z.x, c);
+              }
+              const float f0 = xd ? (XC ? xz[xd ? u : 0][j] : ld_stream(fQ, x)) : (PREF ? fy[xd ? 0 : u - 6][j] : ld_stream(fQ, x));
               if constexpr (COMP) {
-                const float2 ha = relax_update_comp(st[j], M, f0a, ld_stream(lA, x), ea, c.x, vxa, vya, k0[j]);
-                const float2 hb = relax_update_comp(st[j], M, f0b, ld_stream(lB, x), eb, c.y, vxb, vyb, k0[j]);
-                fa = ha.x;
-                la = ha.y;
-                fb = hb.x;
-                lb = hb.y;
+                const float2 h = relax_update_comp(st[j], M, f0, ld_stream(lQ, x), e, c, vx, vy, k0[j]);
+                fn = h.x;
+                ln = h.y;
               } else {
-                fa = relax_update(st[j], M, f0a, ea, c.x, vxa, vya, k0[j]);
-                fb = relax_update(st[j], M, f0b, eb, c.y, vxb, vyb, k0[j]);
+                fn = relax_update(st[j], M, f0, e, c, vx, vy, k0[j]);
               }
             } else {
-              fa = rounded(ea);
-              fb = rounded(eb);
+              fn = rounded(e);
             }
           }
-          st_stream(fA, x, fa);
-          st_stream(fB, x, fb);
+          st_stream(fQ, x, fn);
           if constexpr (COMP) {
-            st_stream(lA, x, la);
-            st_stream(lB, x, lb);
-            l0[j] += la + lb;
-            lx[j] += vxa * la + vxb * lb;
-            ly[j] += vya * la + vyb * lb;
-            le[j] += v2 * (la + lb);
+            st_stream(lQ, x, ln);
+            sl[j] += ln;
+            slx[j] += vx * ln;
+            sly[j] += vy * ln;
           }
-          m0[j] += fa + fb;
-          mx[j] += vxa * fa + vxb * fb;
-          my[j] += vya * fa + vyb * fb;
-          me[j] += v2 * (fa + fb);
-          if (!xp) lds[li] = make_float2(fa, fb);
+          s0[j] += fn;
+          sx[j] += vx * fn;
+          sy[j] += vy * fn;
         }
-        // without prefetch: keep one pair's loads in flight at a time (bounds the live
+        // without prefetch: keep one population's loads in flight at a time (bounds the live
         // registers)
         if constexpr (!PREF) __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (DIRECT) {
-        // directions 3 and 7: the convection term is read in real space; no row transform
 #pragma unroll
-        for (int kd = 0; kd < 2; ++kd) {
-          const int d = 2 + 4 * kd, q = q0 + d;
-          const float vx = c_vel.vx[q], vy = c_vel.vy[q];
-          float* fQ = P.f + (long)q * P.plane + rb;
-          float* lQ = COMP ? P.flo + (long)q * P.plane + rb : nullptr;
-          const float* cQ = reinterpret_cast<const float*>(S + d * hp) + rb;
+      for (int j = 0; j < J; ++j) {
+        m0[j] += s0[j];
+        mx[j] += sx[j];
+        my[j] += sy[j];
+        me[j] += v2 * s0[j];
+        if constexpr (COMP) {
+          l0[j] += sl[j];
+          lx[j] += slx[j];
+          ly[j] += sly[j];
+          le[j] += v2 * sl[j];
+        }
+      }
+      if constexpr (DX) {
+        if (rd + 1 < 4) x_pairs(rd + 1);
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int rd = 0; rd < 4; ++rd) {
+      const RowThread<NX> rt(opaque(tid));
+      const int q0 = 1 + 8 * rd;
+      float2* S = P.sf + (long)(q0 - 1) * hp;  // spectra of q0 .. q0 + 7 are consecutive planes
+      PairBatchOut<NPR> io;
+#pragma unroll
+      for (int p = 0; p < NPR; ++p) {
+        io.a[p] = S + pair_dir(DIRECT, p, 0) * hp;
+        io.b[p] = S + pair_dir(DIRECT, p, 1) * hp;
+        io.hb[p] = true;
+      }
+      float fpre[PREF ? 8 : 1][J];
+      if constexpr (PREF) {
+        // the prefetches of a round are issued at a raised wave priority (measured faster:
+        // their loads are not held up behind the transform work of the CU's other waves)
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int j = 0; j < J; ++j) fpre[i][j] = ld_stream(P.f + (long)(q0 + i) * P.plane + rb, rt.site(j));
+        __builtin_amdgcn_s_setprio(0);
+      }
+      if constexpr (MODE == MODE_STEP) {
+        const PairBatch<NPR> in = conv_batch(rd);
+        if constexpr (PREF) {
+          rows_put_batch<NX, NPR>(lds, in, cf, tid);
+          __syncthreads();
+          rows_inverse_fft<NX, NPR>(lds, twx, tid);
+        } else {
+          rows_inverse_batch<NX, NPR>(lds, in, P.sg, twx, P.kapx, row0, tid);
+        }
+      }
+      {
+        const int k = rd;
+        const float v2 = c_vel.v2[1 + 8 * k];
+        GroupEq ge[J];
+        float k0[J];
+        if constexpr (MODE != MODE_SET) {
+#pragma unroll
+          for (int j = 0; j < J; ++j) {
+            ge[j] = group_eq(st[j], (float)group_weight((double)st[j].T, k));
+            k0[j] = force_k0(st[j], M, v2);
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < NPR; ++p) {
+          const int slot = p;
+          const int da = pair_dir(DIRECT, p, 0), db = pair_dir(DIRECT, p, 1);
+          const int qa = q0 + da, qb = q0 + db;
+          const float vxa = c_vel.vx[qa], vya = c_vel.vy[qa];
+          const float vxb = c_vel.vx[qb], vyb = c_vel.vy[qb];
+          float* fA = P.f + (long)qa * P.plane + rb;
+          float* fB = P.f + (long)qb * P.plane + rb;
+          float* lA = COMP ? P.flo + (long)qa * P.plane + rb : nullptr;
+          float* lB = COMP ? P.flo + (long)qb * P.plane + rb : nullptr;
 #pragma unroll
           for (int j = 0; j < J; ++j) {
             const unsigned x = rt.site(j);
-            float fn, ln = 0.0f;
+            const unsigned li = rt.at(slot, j);
+            float fa, fb, la = 0.0f, lb = 0.0f;
             if constexpr (MODE == MODE_SET) {
-              fn = elem(in.a[0] + (long)q * P.plane + rb, x);
+              fa = elem(in.a[0] + (long)qa * P.plane + rb, x);
+              fb = elem(in.a[0] + (long)qb * P.plane + rb, x);
             } else {
-              const float e = feq_moving(st[j], ge[j], vx, vy);
+              const float ea = feq_moving(st[j], ge[j], vxa, vya);
+              const float eb = feq_moving(st[j], ge[j], vxb, vyb);
               if constexpr (MODE == MODE_STEP) {
-                const float f0 = PREF ? fpre[d][j] : ld_stream(fQ, x);
-                const float c = PREF ? cpre[kd][j] : elem(cQ, x);
+                const float2 c = lds[li];
+                const float f0a = PREF ? fpre[da][j] : ld_stream(fA, x);
+                const float f0b = PREF ? fpre[db][j] : ld_stream(fB, x);
                 if constexpr (COMP) {
-                  const float2 h = relax_update_comp(st[j], M, f0, ld_stream(lQ, x), e, c, vx, vy, k0[j]);
-                  fn = h.x;
-                  ln = h.y;
+                  const float2 ha = relax_update_comp(st[j], M, f0a, ld_stream(lA, x), ea, c.x, vxa, vya, k0[j]);
+                  const float2 hb = relax_update_comp(st[j], M, f0b, ld_stream(lB, x), eb, c.y, vxb, vyb, k0[j]);
+                  fa = ha.x;
+                  la = ha.y;
+                  fb = hb.x;
+                  lb = hb.y;
                 } else {
-                  fn = relax_update(st[j], M, f0, e, c, vx, vy, k0[j]);
+                  fa = relax_update(st[j], M, f0a, ea, c.x, vxa, vya, k0[j]);
+                  fb = relax_update(st[j], M, f0b, eb, c.y, vxb, vyb, k0[j]);
                 }
               } else {
-                fn = rounded(e);
+                fa = rounded(ea);
+                fb = rounded(eb);
               }
             }
-            st_stream(fQ, x, fn);
+            st_stream(fA, x, fa);
+            st_stream(fB, x, fb);
             if constexpr (COMP) {
-              st_stream(lQ, x, ln);
-              l0[j] += ln;
-              lx[j] += vx * ln;
-              ly[j] += vy * ln;
-              le[j] += v2 * ln;
+              st_stream(lA, x, la);
+              st_stream(lB, x, lb);
+              l0[j] += la + lb;
+              lx[j] += vxa * la + vxb * lb;
+              ly[j] += vya * la + vyb * lb;
+              le[j] += v2 * (la + lb);
             }
-            m0[j] += fn;
-            mx[j] += vx * fn;
-            my[j] += vy * fn;
-            me[j] += v2 * fn;
+            m0[j] += fa + fb;
+            mx[j] += vxa * fa + vxb * fb;
+            my[j] += vya * fa + vyb * fb;
+            me[j] += v2 * (fa + fb);
+            lds[li] = make_float2(fa, fb);
           }
+          // without prefetch: keep one pair's loads in flight at a time (bounds the live
+          // registers)
           if constexpr (!PREF) __builtin_amdgcn_sched_barrier(0);
         }
       }
-    }
-    if constexpr (PREF) {
-      __builtin_amdgcn_s_setprio(1);
-      if (rd + 1 < 4) cf = rows_fetch_batch<NX, NPR>(conv_batch(rd + 1), P.sg, P.kapx, row0, tid);
-      __builtin_amdgcn_s_setprio(0);
-    }
-    if constexpr (DX) {
-      if (rd + 1 < 4) {
-        // z of the next group's +-x pair into slot NPR, transformed with this round's batch
-        const int qn = q0 + 8;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-          const unsigned x = rt.site(j);
-          xf[0][j] = ld_stream(P.f + (long)qn * P.plane + rb, x);
-          xf[1][j] = ld_stream(P.f + (long)(qn + 4) * P.plane + rb, x);
-          lds[rt.at(NPR, j)] = make_float2(xf[0][j], xf[1][j]);
-        }
-        rows_forward_batch_dx<NX, NPR>(lds, io, P.sg, twx, P.kapx, row0, tid);
-      } else {
-        rows_forward_batch<NX, NPR>(lds, io, P.sg, twx, row0, tid);
+      if constexpr (PREF) {
+        __builtin_amdgcn_s_setprio(1);
+        if (rd + 1 < 4) cf = rows_fetch_batch<NX, NPR>(conv_batch(rd + 1), P.sg, P.kapx, row0, tid);
+        __builtin_amdgcn_s_setprio(0);
       }
-    } else {
       rows_forward_batch<NX, NPR>(lds, io, P.sg, twx, row0, tid);
     }
   }

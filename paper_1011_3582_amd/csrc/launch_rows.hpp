@@ -42,7 +42,8 @@ int launch_rows(const StepLaunch& L, int kernel, const Inputs& in, hipStream_t s
         else
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_STEP, false>), grid, block, lds, s, a, in);
         break;
-      // init and set pair the row transforms as the step of the instance's scheme does
+      // init and set take the variant of the instance's scheme (the finite-difference schemes
+      // need the row spectra of every population; the spectral derivative needs none)
       case RK_INIT:
         if (L.scheme && L.comp)
           hipLaunchKernelGGL((k_rows_collide<NX, MODE_INIT, true, true>), grid, block, lds, s, a, in);

@@ -178,10 +178,11 @@ int fftlb_derivative(fftlb_handle* h, const float* g, float* out, int32_t op, vo
 int fftlb_derivative_static(const fftlb_config* cfg, const float* g, float* out, int32_t op, void* stream);
 
 /* Enqueue `reps` launches of one kernel of the time step, without graph capture:
- * stage 0 = stage-1 derivative column pass together with the convection column pass of
- * 16 of the 24 populations with v_y != 0 (one launch), 1 = stage-2 row kernel (closure of
- * Eqs. (18)-(23)), 2 = stage-2 divergence column pass together with the convection column
- * pass of the other 8, 3 = collide row kernel (Eqs. (3), (11) and the update).  Running stages
+ * stage 0 = stage-1 derivative column pass together with the column pass that forms the
+ * y-parts v_y D_y f of the convection terms of 16 of the 24 populations with v_y != 0 from f
+ * (one launch), 1 = stage-2 row kernel (closure of Eqs. (18)-(23)), 2 = stage-2 divergence
+ * column pass together with the y-parts of the other 8, 3 = collide row kernel (the x-parts
+ * v_x D_x f from f^n, Eqs. (3), (11) and the update).  Running stages
  * 0..3 once, in order, is exactly one fftlb_step; repeating a stage is for timing and
  * leaves the state meaningless until the next fftlb_set_state or fftlb_init (each
  * stage-3 launch counts as a step).  With a finite-difference convection scheme or the NPS
@@ -191,8 +192,9 @@ int fftlb_derivative_static(const fftlb_config* cfg, const float* g, float* out,
  * alone.  Other stage numbers: FFTLB_EINVAL. */
 int fftlb_run_stage(fftlb_handle* h, int32_t stage, int32_t reps, void* stream);
 
-/* Column-pass plan of a handle: spectral columns per block of the convection pass and of
- * the derivative passes (powers of two up to 16, at most the tile width min(16, the
+/* Column-pass plan of a handle: complex columns per block of the convection pass (pairs of
+ * real columns of f, or spectral columns with a finite-difference scheme) and of the
+ * derivative passes (powers of two up to 16, at most the tile width min(16, the
  * largest power of two dividing nx/2), and within 64 KB of LDS: ny * conv_cols <= 8192,
  * 3 * ny * multi_cols <= 8192), and the largest radix of the column transforms of each
  * (8 or 16).  In the step both derivative passes run inside convection launches, with
@@ -212,7 +214,7 @@ int fftlb_set_plan(fftlb_handle* h, const fftlb_plan* plan);
 
 /* Autotuner: time every column plan of the handle's grid size (`reps` launches each, on
  * `stream`, synchronising) on the handle's current state and set the fastest.  The state
- * is restored afterwards (the spectra are recomputed from f), so the trajectory is
+ * is restored afterwards (everything derived from f is recomputed from it), so the trajectory is
  * unchanged.  With `cache_path` (a text file, NULL for none) a plan already stored there
  * for this device architecture and grid size is used without timing, and a newly timed
  * plan is appended.  *best (may be NULL) receives the plan. */

@@ -206,3 +206,45 @@ def test_central_difference_convection_equals_its_symbol():
     for q in range(1, 33):
         ref = np.fft.ifft2(1j * (v[q, 0] * kx + v[q, 1] * ky) * np.fft.fft2(f[q])).real
         assert np.abs(got[q] - ref).max() < 1e-12 * np.abs(ref).max() + 1e-12
+
+
+@pytest.mark.parametrize("m", [0, 1, 4, O.CENTRAL_DIFFERENCE])
+def test_convection_splits_by_axis_into_one_dimensional_derivatives(m):
+    """The convection term of Sec. 3.6 (one 2D transform pair with the multiplier
+    i (v_x k_m(kx) + v_y k_m(ky))) equals v_x times the 1D windowed derivative along each row plus
+    v_y times the 1D windowed derivative along each column, each formed with 1D transforms: the
+    multiplier is a sum of one-axis multipliers.  The 1D derivatives also pass two real rows (or
+    columns) at once as one complex sequence a + i b: the multiplier is odd and zero at the
+    Nyquist bin, so the result is D a + i D b.  (The HIP path forms the parts this way.)"""
+    ny, nx = 24, 40
+    p = O.Params(dx=1.0 / 40, dy=1.0 / 36, m=m)
+    rng = np.random.default_rng(17 + m)
+    f = rng.uniform(0.0, 1.0, (3, ny, nx))
+    v = np.array([[0.0, 0.0], [1.9 * 0.7071, 1.9 * 0.7071], [-2.9, 0.0]])
+    D = O.Deriv(ny, nx, p)
+    conv = O.convection(f, v, D)
+    kx = O.kappa(nx, p.dx, m) if m != O.CENTRAL_DIFFERENCE else np.sin(O.wavenumbers(nx, p.dx) * p.dx) / p.dx
+    ky = O.kappa(ny, p.dy, m) if m != O.CENTRAL_DIFFERENCE else np.sin(O.wavenumbers(ny, p.dy) * p.dy) / p.dy
+    kx[nx // 2] = 0.0
+    ky[ny // 2] = 0.0
+
+    def d1(z, k, axis):
+        Z = np.fft.fft(z, axis=axis)
+        shape = [1, 1]
+        shape[axis] = -1
+        return np.fft.ifft(1j * k.reshape(shape) * Z, axis=axis)
+
+    for q in (1, 2):
+        dx_rows = d1(f[q], kx, 1).real
+        dy_cols = d1(f[q], ky, 0).real
+        np.testing.assert_allclose(conv[q], v[q, 0] * dx_rows + v[q, 1] * dy_cols, rtol=0, atol=1e-11 * np.abs(conv[q]).max())
+        # two real rows as one complex row, two real columns as one complex column
+        pr = d1(f[q] + 1j * f[q + 1 if q < 2 else 1], kx, 1)
+        np.testing.assert_allclose(pr.real, dx_rows, rtol=0, atol=1e-11 * np.abs(dx_rows).max())
+        np.testing.assert_allclose(pr.imag, d1(f[q + 1 if q < 2 else 1], kx, 1).real, rtol=0,
+                                   atol=1e-11 * np.abs(dx_rows).max())
+        pc = d1(f[q][:, 0::2] + 1j * f[q][:, 1::2], ky, 0)
+        np.testing.assert_allclose(pc.real, dy_cols[:, 0::2], rtol=0, atol=1e-11 * np.abs(dy_cols).max())
+        np.testing.assert_allclose(pc.imag, dy_cols[:, 1::2], rtol=0, atol=1e-11 * np.abs(dy_cols).max())
+    # the rest population has no convection term
+    assert np.all(conv[0] == 0.0)

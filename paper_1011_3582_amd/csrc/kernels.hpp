@@ -1469,7 +1469,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
   // has no registers to spare, only for the transforms)
   constexpr bool DX = DIRECT && MODE == MODE_STEP;
   constexpr bool XC = DX && !COMP;
-  float xz[DX ? 2 * NX3 : 1][J];
+  float xz[2 * NX3][J];  // unused (and dropped by the compiler) unless DX
   // the x-derivative pairs of group k of f^n into slots 0..2, forward-transformed and
   // multiplied by i k_x / nx
   auto x_pairs = [&](int k) {
@@ -1526,8 +1526,8 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
       const int q0 = 1 + 8 * rd;
       // the y-parts v_y D_y f of the group: plane of direction offset d at cy + d * plane
       const float* cy = reinterpret_cast<const float*>(P.sf + (long)(q0 - 1) * hp) + rb;
-      float fy[PREF ? 2 : 1][J];   // f^n of the two along +-y
-      float cyv[PREF ? 8 : 1][J];  // y-parts by direction offset (0 and 4 unused)
+      float fy[2][J];   // f^n of the two along +-y (prefetched with PREF)
+      float cyv[8][J];  // y-parts by direction offset (prefetched with PREF; 0 and 4 unused)
       if constexpr (PREF) {
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
@@ -1647,7 +1647,7 @@ __device__ __forceinline__ void rows_collide(const Planes& P, const Model& M, co
         io.b[p] = S + pair_dir(DIRECT, p, 1) * hp;
         io.hb[p] = true;
       }
-      float fpre[PREF ? 8 : 1][J];
+      float fpre[8][J];  // f^n of the round's populations (prefetched with PREF)
       if constexpr (PREF) {
         // the prefetches of a round are issued at a raised wave priority (measured faster:
         // their loads are not held up behind the transform work of the CU's other waves)
